@@ -1,0 +1,254 @@
+/*
+ * bbfmm.h -- C ABI of the MI355X (gfx950) black-box FMM kernel matvec.
+ *
+ * The library computes phi = K sigma (eq. (1)-(2) of the paper) for a set of
+ * N points that are both sources and targets, with the Chebyshev black-box
+ * FMM: octree (Section 2.1), Lagrange interpolation (Section 2.2), the
+ * four stages P2M/M2M, M2L, L2L/L2P and P2P (Section 2.3), and the
+ * homogeneous-kernel reuse, SVD-compressed M2L and multi-RHS grouping of
+ * Section 2.5.  The three calls mirror the paper's API (Section 3):
+ * building the hierarchy, precomputing the M2L operators, computing.
+ *
+ * Conventions for every entry point
+ *   - Every function returns a bbfmm_status; nothing throws across the ABI.
+ *     On failure bbfmm_last_error() returns a message (thread-local, valid
+ *     until the next call on the same thread).
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are stream-ordered; build_tree and precompute_operators return
+ *     only after their work is complete (they read sizes back), matvec and
+ *     plan_execute are asynchronous.  A fault inside a kernel surfaces at
+ *     the next synchronising call.
+ *   - Handles (trees, operator sets, plans) own their device memory and are
+ *     immutable after creation, except that a plan owns a workspace, so a
+ *     plan must not be executed concurrently with itself.  Distinct plans on
+ *     distinct streams may run concurrently.
+ *   - Free functions accept NULL.
+ */
+#ifndef BBFMM_H
+#define BBFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BBFMM_OK = 0,
+    BBFMM_ERR_INVALID_ARG = 1,   /* bad size, pointer, option or input value */
+    BBFMM_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed        */
+    BBFMM_ERR_HIP = 3,           /* a HIP runtime call or launch failed       */
+    BBFMM_ERR_BUDGET = 4,        /* reserved: request exceeds a memory budget */
+    BBFMM_ERR_NOT_FOUND = 5,     /* unknown array / level in an export        */
+    BBFMM_ERR_INTERNAL = 6       /* an internal consistency check failed      */
+} bbfmm_status;
+
+/* Kernel functions (Sections 1 and 4; all translation invariant). */
+enum {
+    BBFMM_K_INV_R = 0,      /* 1/|x-y|; K = 0 where |x-y|^2 == 0; homogeneous, degree -1 */
+    BBFMM_K_EXP = 1,        /* exp(-|x-y|/a), a = kernel_param                         */
+    BBFMM_K_GAUSS = 2,      /* exp(-|x-y|^2/a^2), a = kernel_param                      */
+    BBFMM_K_POLY_TEST = 100 /* prod_d g((x_d-y_d)/a), g(u) = 1 + u/2 - u^2/3 + u^3/5:
+                               degree 3 per coordinate, for exactness tests only     */
+};
+
+/* Arithmetic of the M2L contraction (the rest of the matvec is FP32). */
+enum {
+    BBFMM_M2L_FP32 = 0
+};
+
+typedef struct {
+    int32_t kernel_id;     /* one of BBFMM_K_*                                       */
+    double kernel_param;   /* length scale a (ignored by 1/r)                        */
+    int32_t cheb_order;    /* Chebyshev nodes per axis n, 2..8 (Section 2.2)         */
+    int32_t leaf_size;     /* depth rule: smallest depth whose largest leaf holds at
+                              most leaf_size points (>= 1)                          */
+    int32_t max_depth;     /* cap on the number of levels incl. the root, 1..22     */
+    int32_t fixed_depth;   /* > 0: use exactly this many levels (1..22)             */
+} bbfmm_tree_params;
+
+typedef struct bbfmm_tree bbfmm_tree;
+typedef struct bbfmm_ops bbfmm_ops;
+typedef struct bbfmm_plan bbfmm_plan;
+
+typedef struct {
+    int64_t n_points;
+    int32_t depth;             /* levels including the root; leaf level = depth-1 */
+    int32_t cheb_order;
+    int32_t kernel_id;
+    double kernel_param;
+    float lo[3];               /* bounding-cube anchor (per-axis minimum)          */
+    float side;                /* cube side (largest extent, 1 if all coincide)    */
+    float scale;               /* 2^21 / side, the binning factor                  */
+    int32_t max_leaf_points;
+    int32_t cells[22];         /* occupied cells per level                         */
+    int64_t pairs[22];         /* M2L pairs per level (0 on levels 0 and 1)        */
+    int64_t near_pairs;        /* point pairs evaluated by P2P                     */
+} bbfmm_tree_info;
+
+/*
+ * Build the octree over the bounding cube of the points (Section 2.1,
+ * Definition 2.1).
+ *   points  device, N x 3 float32 row-major, original order; read only.
+ *   n       number of points, >= 1 and < 2^31.
+ * The tree is uniform: every leaf sits on level depth-1; empty cells are not
+ * stored.  Binning: q_d = clamp(floor((x_d - lo_d) * scale), 0, 2^21-1) in
+ * float32 (one rounding per operation), the level-l coordinate is
+ * q_d >> (21-l); points are ordered by a stable sort of the Morton leaf key
+ * (bit b of x, y, z at bits 3b, 3b+1, 3b+2).  Also built: the leaf
+ * neighbour lists N(.) and, on every level >= 2, the interaction lists I(.)
+ * grouped by transfer vector.
+ * Errors: INVALID_ARG for n < 1, NULL pointers, non-finite coordinates,
+ * cheb_order outside 2..8, leaf_size < 1, depths outside 1..22 or an unknown
+ * kernel; OUT_OF_MEMORY; HIP.
+ */
+bbfmm_status bbfmm_build_tree(const float *points, int64_t n,
+                              const bbfmm_tree_params *params, void *stream,
+                              bbfmm_tree **out);
+
+bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *tree, bbfmm_tree_info *out);
+
+/* Arrays a tree exposes for inspection (copied device -> host). */
+enum {
+    BBFMM_TA_PERM = 0,      /* int32[N]: sorted position -> original index         */
+    BBFMM_TA_KEYS = 1,      /* uint64[C_l]: Morton keys of level l, ascending      */
+    BBFMM_TA_PB = 2,        /* int32[C_l]: first point (sorted order)              */
+    BBFMM_TA_PE = 3,        /* int32[C_l]: one past the last point                 */
+    BBFMM_TA_PARENT = 4,    /* int32[C_l]: parent index on level l-1 (-1 at root)  */
+    BBFMM_TA_CB = 5,        /* int32[C_l]: first child on level l+1 (-1 on leaves) */
+    BBFMM_TA_CE = 6,        /* int32[C_l]: one past the last child                 */
+    BBFMM_TA_NBR_OFF = 7,   /* int32[C_L+1]: leaf neighbour CSR offsets            */
+    BBFMM_TA_NBR_IDX = 8,   /* int32[nnz]: neighbours, ascending cell index        */
+    BBFMM_TA_PAIR_T = 9,    /* int32[P_l]: transfer-vector index 0..315 per pair   */
+    BBFMM_TA_PAIR_TGT = 10, /* int32[P_l]: target cell of each pair                */
+    BBFMM_TA_PAIR_SRC = 11, /* int32[P_l]: source cell of each pair                */
+    BBFMM_TA_PAIR_GOFF = 12 /* int32[317]: group offsets by transfer vector        */
+};
+
+/*
+ * Copy one tree array to host memory.
+ *   what   one of BBFMM_TA_*; level selects the level for per-level arrays.
+ *   dst    host buffer of capacity bytes, or NULL to query the size only.
+ *   size   receives the array size in bytes.
+ * Pair arrays list (target, source) with source - target = transfer vector
+ * t (t in {-3..3}^3 minus {-1..1}^3, index ascending in
+ * (tx+3) + 7(ty+3) + 49(tz+3)), grouped by t, ascending target within a group.
+ * Errors: NOT_FOUND for an unknown array or level; INVALID_ARG when
+ * capacity is too small.  Synchronous.
+ */
+bbfmm_status bbfmm_tree_export(const bbfmm_tree *tree, int32_t what,
+                               int32_t level, void *dst, int64_t capacity,
+                               int64_t *size);
+
+/*
+ * Precompute the M2L operators of every level >= 2 on the GPU in FP64
+ * (Sections 2.3 and 2.5): sample the 316 operators
+ * K_t[i][j] = K(h s_i, h (2t + s_j)) (h the level's half-width), compress
+ * them with the truncated SVD of the fat and thin concatenations
+ * (k = largest count of singular values above svd_eps times the largest,
+ * U / V the leading left / right singular vectors, C_t = U^T K_t V), and
+ * cast U, V, C_t to the matvec precision.  For the homogeneous kernel 1/r
+ * one set is built and scaled by 1/h per level.  svd_eps = 0 disables the
+ * compression (U = V = identity).
+ * Errors: INVALID_ARG (svd_eps < 0 or not finite, unknown precision),
+ * OUT_OF_MEMORY, HIP.  Synchronous.
+ */
+bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *tree,
+                                        double svd_eps, int32_t precision,
+                                        void *stream, bbfmm_ops **out);
+
+/* Rank k of level l (levels >= 2), or NOT_FOUND. */
+bbfmm_status bbfmm_ops_rank(const bbfmm_ops *ops, int32_t level, int32_t *k);
+
+/* Arrays an operator set exposes (FP64, copied device -> host). */
+enum {
+    BBFMM_OA_U = 0,        /* double[m][k]: left basis, row-major (m = n^3)      */
+    BBFMM_OA_V = 1,        /* double[m][k]: right basis                          */
+    BBFMM_OA_C = 2,        /* double[316][k][k]: compressed operators, level-scaled */
+    BBFMM_OA_SV_FAT = 3,   /* double[m]: singular values of the fat matrix       */
+    BBFMM_OA_SV_THIN = 4   /* double[m]: singular values of the thin matrix      */
+};
+
+/* Same calling convention as bbfmm_tree_export. */
+bbfmm_status bbfmm_ops_export(const bbfmm_ops *ops, int32_t what,
+                              int32_t level, void *dst, int64_t capacity,
+                              int64_t *size);
+
+/*
+ * Build an operator set from host FP64 arrays instead of the SVD (lets a
+ * caller test the matvec with given operators).
+ *   ranks  host int32[depth]: k of each level (entries of levels 0, 1 unused)
+ *   U, V   host double: for each level l >= 2 in order, m x k_l row-major
+ *   C      host double: for each level l >= 2 in order, 316 x k_l x k_l,
+ *          already scaled for that level
+ * Errors: INVALID_ARG (k outside 1..m, NULL arrays), OUT_OF_MEMORY, HIP.
+ */
+bbfmm_status bbfmm_ops_import(const bbfmm_tree *tree, int32_t precision,
+                              const int32_t *ranks, const double *U,
+                              const double *V, const double *C, void *stream,
+                              bbfmm_ops **out);
+
+/*
+ * phi = K sigma for r right-hand sides (Section 2.5, multiple RHS).
+ *   sigma  device, N x r float32 row-major (r fastest), original point order.
+ *   phi    device, N x r float32, overwritten; must not overlap sigma.
+ * Runs gather, P2M, M2M, compression, M2L, decompression, L2L, L2P and P2P
+ * on the stream with a temporary workspace, and returns once the product is
+ * complete (the workspace is freed).  For repeated or asynchronous products
+ * use a plan.
+ * Errors: INVALID_ARG (r < 1 or > 4096, NULL pointers, ops not built for
+ * this tree), OUT_OF_MEMORY, HIP.
+ */
+bbfmm_status bbfmm_matvec(const bbfmm_tree *tree, const bbfmm_ops *ops,
+                          const float *sigma, int64_t r, float *phi,
+                          void *stream);
+
+/*
+ * A reusable matvec for a fixed (tree, operators, r) that owns its
+ * workspace, so repeated products allocate nothing.  plan_execute has the
+ * semantics of bbfmm_matvec.  The tree and operators must outlive the plan.
+ */
+bbfmm_status bbfmm_plan_create(const bbfmm_tree *tree, const bbfmm_ops *ops,
+                               int64_t r, bbfmm_plan **out);
+bbfmm_status bbfmm_plan_execute(bbfmm_plan *plan, const float *sigma,
+                                float *phi, void *stream);
+/* Bytes of device workspace the plan holds. */
+bbfmm_status bbfmm_plan_workspace_bytes(const bbfmm_plan *plan, int64_t *bytes);
+
+/* Stages of one matvec, in execution order (Section 2.3).  Each stage is
+ * one kernel launch except M2M and DOWN, which launch once per level. */
+enum {
+    BBFMM_STAGE_GATHER = 0, /* sigma into tree order                          */
+    BBFMM_STAGE_P2M = 1,    /* leaf multipoles and their compression          */
+    BBFMM_STAGE_M2M = 2,    /* upward translation and compression, per level  */
+    BBFMM_STAGE_M2L = 3,    /* all levels' interaction lists, one launch      */
+    BBFMM_STAGE_DOWN = 4,   /* decompression + L2L, per level                 */
+    BBFMM_STAGE_P2P = 5,    /* L2P + near field + scatter to phi              */
+    BBFMM_NUM_STAGES = 6
+};
+
+/*
+ * Device-time measurement of the stages with HIP events recorded on the
+ * execution stream (enable = 1 to start, 0 to stop).  While enabled, every
+ * plan_execute records BBFMM_NUM_STAGES + 1 events.
+ * plan_stage_times waits for the recorded executions and returns the summed
+ * milliseconds per stage (ms: array of BBFMM_NUM_STAGES) and the number of
+ * executions they cover; reset != 0 clears the totals afterwards.
+ */
+bbfmm_status bbfmm_plan_set_timing(bbfmm_plan *plan, int32_t enable);
+bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *executions,
+                                    int32_t reset);
+
+void bbfmm_tree_free(bbfmm_tree *tree);
+void bbfmm_ops_free(bbfmm_ops *ops);
+void bbfmm_plan_free(bbfmm_plan *plan);
+
+const char *bbfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBFMM_H */

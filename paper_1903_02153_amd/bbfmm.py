@@ -1,0 +1,287 @@
+"""Python binding of libbbfmm (ctypes, argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+device tensors to pointers and handles to Python objects, and raises
+``BBFMMError`` on a non-zero status.  It refuses to run when the shared
+library has not been built -- there is no fallback path.
+
+Names follow the C ABI in include/bbfmm.h: ``build_tree``,
+``precompute_operators``, ``matvec``, plus export/import helpers and plans.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
+
+K_INV_R, K_EXP, K_GAUSS, K_POLY_TEST = 0, 1, 2, 100
+M2L_FP32 = 0
+
+TA = dict(perm=0, keys=1, pb=2, pe=3, parent=4, cb=5, ce=6, nbr_off=7, nbr_idx=8,
+          pair_t=9, pair_tgt=10, pair_src=11, pair_goff=12)
+_TA_DTYPE = dict(keys=np.uint64)
+OA = dict(U=0, V=1, C=2, sv_fat=3, sv_thin=4)
+STAGES = ("gather", "p2m", "m2m", "m2l", "down", "p2p")
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "BUDGET",
+          5: "NOT_FOUND", 6: "INTERNAL"}
+
+
+class BBFMMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TreeParams(ctypes.Structure):
+    _fields_ = [("kernel_id", ctypes.c_int32), ("kernel_param", ctypes.c_double),
+                ("cheb_order", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("fixed_depth", ctypes.c_int32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("cheb_order", ctypes.c_int32), ("kernel_id", ctypes.c_int32),
+                ("kernel_param", ctypes.c_double), ("lo", ctypes.c_float * 3),
+                ("side", ctypes.c_float), ("scale", ctypes.c_float),
+                ("max_leaf_points", ctypes.c_int32), ("cells", ctypes.c_int32 * 22),
+                ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64)]
+
+
+_lib_handle = None
+
+# name -> (restype, argtypes); every symbol of include/bbfmm.h
+_VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_PVP = ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = {
+    "bbfmm_build_tree": (_I32, [_VP, _I64, ctypes.POINTER(TreeParams), _VP, _PVP]),
+    "bbfmm_tree_info_get": (_I32, [_VP, ctypes.POINTER(TreeInfo)]),
+    "bbfmm_tree_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
+    "bbfmm_precompute_operators": (_I32, [_VP, _D, _I32, _VP, _PVP]),
+    "bbfmm_ops_rank": (_I32, [_VP, _I32, ctypes.POINTER(_I32)]),
+    "bbfmm_ops_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
+    "bbfmm_ops_import": (_I32, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _PVP]),
+    "bbfmm_matvec": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP]),
+    "bbfmm_plan_create": (_I32, [_VP, _VP, _I64, _PVP]),
+    "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
+    "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
+    "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
+    "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+    "bbfmm_tree_free": (None, [_VP]),
+    "bbfmm_ops_free": (None, [_VP]),
+    "bbfmm_plan_free": (None, [_VP]),
+    "bbfmm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libbbfmm.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib_handle = h
+    return _lib_handle
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise BBFMMError(status, lib().bbfmm_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _device_f32(t, name: str, shape: Optional[Sequence[int]] = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Tree:
+    def __init__(self, handle: int, params: TreeParams):
+        self._h = handle
+        self.params = params
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> TreeInfo:
+        out = TreeInfo()
+        _check(lib().bbfmm_tree_info_get(self._h, ctypes.byref(out)))
+        return out
+
+    def export(self, what: str, level: int = 0) -> np.ndarray:
+        code = TA[what]
+        size = _I64(0)
+        _check(lib().bbfmm_tree_export(self._h, code, level, None, 0, ctypes.byref(size)))
+        dt = _TA_DTYPE.get(what, np.int32)
+        out = np.empty(size.value // np.dtype(dt).itemsize, dtype=dt)
+        _check(lib().bbfmm_tree_export(self._h, code, level, out.ctypes.data_as(_VP),
+                                       out.nbytes, ctypes.byref(size)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().bbfmm_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ops:
+    def __init__(self, handle: int, tree: Tree):
+        self._h = handle
+        self.tree = tree
+
+    @property
+    def handle(self):
+        return self._h
+
+    def rank(self, level: int) -> int:
+        k = _I32(0)
+        _check(lib().bbfmm_ops_rank(self._h, level, ctypes.byref(k)))
+        return k.value
+
+    def export(self, what: str, level: int) -> np.ndarray:
+        size = _I64(0)
+        _check(lib().bbfmm_ops_export(self._h, OA[what], level, None, 0, ctypes.byref(size)))
+        out = np.empty(size.value // 8, dtype=np.float64)
+        _check(lib().bbfmm_ops_export(self._h, OA[what], level, out.ctypes.data_as(_VP),
+                                      out.nbytes, ctypes.byref(size)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().bbfmm_ops_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Reusable matvec for a fixed (tree, ops, r); owns its workspace."""
+
+    def __init__(self, tree: Tree, ops: Ops, r: int):
+        h = _VP()
+        _check(lib().bbfmm_plan_create(tree.handle, ops.handle, int(r), ctypes.byref(h)))
+        self._h = h.value
+        self.tree, self.ops, self.r = tree, ops, int(r)
+        self.n = tree.info().n_points
+
+    def workspace_bytes(self) -> int:
+        b = _I64(0)
+        _check(lib().bbfmm_plan_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().bbfmm_plan_set_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self, reset: bool = True):
+        """(dict stage -> summed device ms, number of timed executions)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = _I64(0)
+        _check(lib().bbfmm_plan_stage_times(self._h, ms, ctypes.byref(n), 1 if reset else 0))
+        return dict(zip(STAGES, list(ms))), n.value
+
+    def execute(self, sigma, phi, stream=None):
+        _device_f32(sigma, "sigma", (self.n, self.r))
+        _device_f32(phi, "phi", (self.n, self.r))
+        _check(lib().bbfmm_plan_execute(self._h, sigma.data_ptr(), phi.data_ptr(),
+                                        _stream_handle(stream)))
+        return phi
+
+    def close(self):
+        if self._h:
+            lib().bbfmm_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
+               cheb_order: int = 4, leaf_size: int = 64, max_depth: int = 22,
+               fixed_depth: int = 0, stream=None) -> Tree:
+    """Octree over the bounding cube of ``points`` ((N,3) float32 on the GPU)."""
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    _device_f32(points, "points")
+    p = TreeParams(kernel_id, kernel_param, cheb_order, leaf_size, max_depth, fixed_depth)
+    h = _VP()
+    _check(lib().bbfmm_build_tree(points.data_ptr(), points.shape[0], ctypes.byref(p),
+                                  _stream_handle(stream), ctypes.byref(h)))
+    return Tree(h.value, p)
+
+
+def precompute_operators(tree: Tree, svd_eps: float = 1e-5, precision: int = M2L_FP32,
+                         stream=None) -> Ops:
+    h = _VP()
+    _check(lib().bbfmm_precompute_operators(tree.handle, float(svd_eps), int(precision),
+                                            _stream_handle(stream), ctypes.byref(h)))
+    return Ops(h.value, tree)
+
+
+def ops_import(tree: Tree, ranks: Sequence[int], U: Sequence[np.ndarray],
+               V: Sequence[np.ndarray], C: Sequence[np.ndarray],
+               precision: int = M2L_FP32, stream=None) -> Ops:
+    """Operators from host FP64 arrays: lists over levels 2..depth-1."""
+    depth = tree.info().depth
+    rk = np.zeros(max(depth, 1), dtype=np.int32)
+    for i, k in enumerate(ranks):
+        rk[2 + i] = k
+    cat = lambda xs: np.ascontiguousarray(np.concatenate([np.ravel(x) for x in xs])
+                                          if len(xs) else np.zeros(1), dtype=np.float64)
+    u, v, c = cat(U), cat(V), cat(C)
+    h = _VP()
+    _check(lib().bbfmm_ops_import(tree.handle, int(precision), rk.ctypes.data_as(_VP),
+                                  u.ctypes.data_as(_VP), v.ctypes.data_as(_VP),
+                                  c.ctypes.data_as(_VP), _stream_handle(stream),
+                                  ctypes.byref(h)))
+    return Ops(h.value, tree)
+
+
+def matvec(tree: Tree, ops: Ops, sigma, phi=None, stream=None):
+    """phi = K sigma for sigma of shape (N, r) (or (N,)) float32 on the GPU."""
+    import torch
+    squeeze = sigma.dim() == 1
+    s2 = sigma.reshape(-1, 1) if squeeze else sigma
+    _device_f32(s2, "sigma")
+    if phi is None:
+        phi = torch.empty_like(s2)
+    _device_f32(phi, "phi", tuple(s2.shape))
+    _check(lib().bbfmm_matvec(tree.handle, ops.handle, s2.data_ptr(), s2.shape[1],
+                              phi.data_ptr(), _stream_handle(stream)))
+    return phi.reshape(-1) if squeeze else phi

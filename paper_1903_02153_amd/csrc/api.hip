@@ -1,0 +1,275 @@
+// C-ABI entry points of libbbfmm (declared in include/bbfmm.h).
+// Each entry point converts internal exceptions into a bbfmm_status and a
+// thread-local message; nothing propagates across the ABI.
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace bbfmm {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void fail(bbfmm_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    throw Exception{st};
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+template <class F>
+bbfmm_status guarded(F &&f) {
+    clear_error();
+    try {
+        f();
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        snprintf(g_err, sizeof(g_err), "host allocation failed");
+        return BBFMM_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        snprintf(g_err, sizeof(g_err), "unexpected internal error");
+        return BBFMM_ERR_INTERNAL;
+    }
+}
+
+const char *last_error() { return g_err; }
+
+template <class T>
+void copy_out(const T *dev, int64_t count, void *dst, int64_t capacity, int64_t *size) {
+    const int64_t bytes = count * int64_t(sizeof(T));
+    if (size) *size = bytes;
+    if (dst == nullptr) return;
+    BB_REQUIRE(capacity >= bytes, "destination holds %lld bytes, %lld needed",
+               (long long)capacity, (long long)bytes);
+    if (bytes > 0) BB_HIP(hipMemcpy(dst, dev, size_t(bytes), hipMemcpyDeviceToHost));
+}
+
+}  // namespace bbfmm
+
+using namespace bbfmm;
+
+struct bbfmm_plan {
+    Plan *impl = nullptr;
+    ~bbfmm_plan() { plan_destroy(impl); }
+};
+
+extern "C" {
+
+const char *bbfmm_last_error(void) { return last_error(); }
+
+bbfmm_status bbfmm_build_tree(const float *points, int64_t n, const bbfmm_tree_params *params,
+                              void *stream, bbfmm_tree **out) {
+    return guarded([&] {
+        BB_REQUIRE(params != nullptr && out != nullptr, "params / out is NULL");
+        *out = nullptr;
+        *out = build_tree_impl(points, n, *params, static_cast<hipStream_t>(stream));
+    });
+}
+
+bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *t, bbfmm_tree_info *out) {
+    return guarded([&] {
+        BB_REQUIRE(t != nullptr && out != nullptr, "tree / out is NULL");
+        std::memset(out, 0, sizeof(*out));
+        out->n_points = t->n;
+        out->depth = t->depth;
+        out->cheb_order = t->params.cheb_order;
+        out->kernel_id = t->params.kernel_id;
+        out->kernel_param = t->params.kernel_param;
+        for (int d = 0; d < 3; ++d) out->lo[d] = t->lo[d];
+        out->side = t->side;
+        out->scale = t->scale;
+        out->max_leaf_points = t->max_leaf;
+        for (int l = 0; l < t->depth; ++l) {
+            out->cells[l] = t->lv[l].C;
+            out->pairs[l] = t->lv[l].npairs;
+        }
+        out->near_pairs = t->near_pairs;
+    });
+}
+
+bbfmm_status bbfmm_tree_export(const bbfmm_tree *t, int32_t what, int32_t level, void *dst,
+                               int64_t capacity, int64_t *size) {
+    return guarded([&] {
+        BB_REQUIRE(t != nullptr, "tree is NULL");
+        const bool per_level = what >= BBFMM_TA_KEYS && what <= BBFMM_TA_CE;
+        const bool pair = what >= BBFMM_TA_PAIR_T && what <= BBFMM_TA_PAIR_GOFF;
+        if (per_level || pair) {
+            if (level < 0 || level >= t->depth || (pair && level < 2))
+                fail(BBFMM_ERR_NOT_FOUND, "level %d has no such array", level);
+        }
+        const LevelData *lv = (per_level || pair) ? &t->lv[level] : nullptr;
+        const int L = t->leaf_level();
+        switch (what) {
+        case BBFMM_TA_PERM: copy_out(t->perm.p, t->n, dst, capacity, size); break;
+        case BBFMM_TA_KEYS: copy_out(lv->keys.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_PB: copy_out(lv->pb.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_PE: copy_out(lv->pe.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_PARENT: copy_out(lv->parent.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_CB: copy_out(lv->cb.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_CE: copy_out(lv->ce.p, lv->C, dst, capacity, size); break;
+        case BBFMM_TA_NBR_OFF: copy_out(t->nbr_off.p, int64_t(t->lv[L].C) + 1, dst, capacity, size); break;
+        case BBFMM_TA_NBR_IDX: copy_out(t->nbr_idx.p, t->nbr_nnz, dst, capacity, size); break;
+        case BBFMM_TA_PAIR_T: copy_out(lv->pair_t.p, lv->npairs, dst, capacity, size); break;
+        case BBFMM_TA_PAIR_TGT: copy_out(lv->pair_tgt.p, lv->npairs, dst, capacity, size); break;
+        case BBFMM_TA_PAIR_SRC: copy_out(lv->pair_src.p, lv->npairs, dst, capacity, size); break;
+        case BBFMM_TA_PAIR_GOFF: copy_out(lv->pair_goff.p, int64_t(kNumT) + 1, dst, capacity, size); break;
+        default: fail(BBFMM_ERR_NOT_FOUND, "unknown tree array %d", what);
+        }
+    });
+}
+
+bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *t, double svd_eps, int32_t precision,
+                                        void *stream, bbfmm_ops **out) {
+    return guarded([&] {
+        BB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = precompute_impl(t, svd_eps, precision, static_cast<hipStream_t>(stream));
+    });
+}
+
+bbfmm_status bbfmm_ops_rank(const bbfmm_ops *o, int32_t level, int32_t *k) {
+    return guarded([&] {
+        BB_REQUIRE(o != nullptr && k != nullptr, "ops / k is NULL");
+        if (level < 2 || level >= o->tree->depth || o->lv[level].set == nullptr)
+            fail(BBFMM_ERR_NOT_FOUND, "level %d has no M2L operators", level);
+        *k = o->lv[level].set->k;
+    });
+}
+
+bbfmm_status bbfmm_ops_export(const bbfmm_ops *o, int32_t what, int32_t level, void *dst,
+                              int64_t capacity, int64_t *size) {
+    return guarded([&] {
+        BB_REQUIRE(o != nullptr, "ops is NULL");
+        if (level < 2 || level >= o->tree->depth || o->lv[level].set == nullptr)
+            fail(BBFMM_ERR_NOT_FOUND, "level %d has no M2L operators", level);
+        const OpSet &set = *o->lv[level].set;
+        const int64_t m = o->m, k = set.k;
+        switch (what) {
+        case BBFMM_OA_U: copy_out(set.U64.p, m * k, dst, capacity, size); break;
+        case BBFMM_OA_V: copy_out(set.V64.p, m * k, dst, capacity, size); break;
+        case BBFMM_OA_C: {
+            copy_out(set.C64.p, int64_t(kNumT) * k * k, dst, capacity, size);
+            if (dst != nullptr && o->lv[level].scale != 1.0) {
+                double *d = static_cast<double *>(dst);
+                for (int64_t i = 0; i < int64_t(kNumT) * k * k; ++i) d[i] *= o->lv[level].scale;
+            }
+            break;
+        }
+        case BBFMM_OA_SV_FAT:
+            if (set.sv_fat.n == 0) fail(BBFMM_ERR_NOT_FOUND, "no singular values (imported or eps = 0)");
+            copy_out(set.sv_fat.p, m, dst, capacity, size);
+            break;
+        case BBFMM_OA_SV_THIN:
+            if (set.sv_thin.n == 0) fail(BBFMM_ERR_NOT_FOUND, "no singular values (imported or eps = 0)");
+            copy_out(set.sv_thin.p, m, dst, capacity, size);
+            break;
+        default: fail(BBFMM_ERR_NOT_FOUND, "unknown operator array %d", what);
+        }
+    });
+}
+
+bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int32_t *ranks,
+                              const double *U, const double *V, const double *C, void *stream,
+                              bbfmm_ops **out) {
+    return guarded([&] {
+        BB_REQUIRE(t != nullptr && out != nullptr, "tree / out is NULL");
+        *out = nullptr;
+        BB_REQUIRE(precision == BBFMM_M2L_FP32, "unsupported M2L precision %d", precision);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
+        ops->tree = t;
+        ops->n = t->params.cheb_order;
+        ops->m = ops->n * ops->n * ops->n;
+        ops->precision = precision;
+        cheb_setup(ops.get(), s);
+        const int L = t->leaf_level();
+        if (L >= 2) BB_REQUIRE(ranks && U && V && C, "ranks / U / V / C is NULL");
+        const int64_t m = ops->m;
+        int64_t offUV = 0, offC = 0;
+        for (int lvl = 2; lvl <= L; ++lvl) {
+            const int k = ranks[lvl];
+            BB_REQUIRE(k >= 1 && k <= m, "rank %d of level %d outside [1, %lld]", k, lvl, (long long)m);
+            std::unique_ptr<OpSet> set(new OpSet());
+            set->k = k;
+            set->U64.alloc(m * k);
+            set->V64.alloc(m * k);
+            set->C64.alloc(int64_t(kNumT) * k * k);
+            BB_HIP(hipMemcpy(set->U64.p, U + offUV, m * k * sizeof(double), hipMemcpyHostToDevice));
+            BB_HIP(hipMemcpy(set->V64.p, V + offUV, m * k * sizeof(double), hipMemcpyHostToDevice));
+            BB_HIP(hipMemcpy(set->C64.p, C + offC, int64_t(kNumT) * k * k * sizeof(double),
+                             hipMemcpyHostToDevice));
+            offUV += m * k;
+            offC += int64_t(kNumT) * k * k;
+            finalize_opset(*set, int(m), s);
+            ops->lv[lvl].set = set.get();
+            ops->lv[lvl].scale = 1.0;
+            ops->sets.push_back(std::move(set));
+        }
+        *out = ops.release();
+    });
+}
+
+bbfmm_status bbfmm_plan_create(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                               bbfmm_plan **out) {
+    return guarded([&] {
+        BB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
+        p->impl = plan_create_impl(t, o, r);
+        *out = p.release();
+    });
+}
+
+bbfmm_status bbfmm_plan_execute(bbfmm_plan *p, const float *sigma, float *phi, void *stream) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr, "plan is NULL");
+        plan_execute_impl(p->impl, sigma, phi, static_cast<hipStream_t>(stream));
+    });
+}
+
+bbfmm_status bbfmm_plan_workspace_bytes(const bbfmm_plan *p, int64_t *bytes) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr && bytes != nullptr, "plan / bytes is NULL");
+        *bytes = plan_workspace_bytes(p->impl);
+    });
+}
+
+bbfmm_status bbfmm_plan_set_timing(bbfmm_plan *p, int32_t enable) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr, "plan is NULL");
+        plan_set_timing(p->impl, enable != 0);
+    });
+}
+
+bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *p, double *ms, int64_t *executions,
+                                    int32_t reset) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr, "plan is NULL");
+        plan_stage_times(p->impl, ms, executions, reset != 0);
+    });
+}
+
+bbfmm_status bbfmm_matvec(const bbfmm_tree *t, const bbfmm_ops *o, const float *sigma, int64_t r,
+                          float *phi, void *stream) {
+    return guarded([&] {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
+        p->impl = plan_create_impl(t, o, r);
+        plan_execute_impl(p->impl, sigma, phi, s);
+        // the workspace is released only after the stream has consumed it
+        BB_HIP(hipStreamSynchronize(s));
+    });
+}
+
+void bbfmm_tree_free(bbfmm_tree *t) { delete t; }
+void bbfmm_ops_free(bbfmm_ops *o) { delete o; }
+void bbfmm_plan_free(bbfmm_plan *p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal definitions shared by the translation units of libbbfmm.
+// Every host-side failure is raised as bbfmm::Exception and turned into a
+// bbfmm_status at the C-ABI boundary (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "bbfmm.h"
+
+namespace bbfmm {
+
+constexpr int kQBits = 21;          // binning resolution per axis (2^21 cells)
+constexpr int kMaxLevels = 22;      // levels 0..21
+constexpr int kNumT = 316;          // M2L transfer vectors per level
+constexpr int kSlots = 189;         // transfer vectors valid for one octant
+constexpr int kMaxOrder = 8;
+
+struct Exception {
+    bbfmm_status status;
+};
+
+[[noreturn]] void fail(bbfmm_status st, const char *fmt, ...);
+void clear_error();
+
+#define BB_HIP(call)                                                            \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess)                                                   \
+            ::bbfmm::fail(e_ == hipErrorOutOfMemory ? BBFMM_ERR_OUT_OF_MEMORY   \
+                                                    : BBFMM_ERR_HIP,            \
+                          "%s: %s (%s:%d)", #call, hipGetErrorString(e_),       \
+                          __FILE__, __LINE__);                                  \
+    } while (0)
+
+#define BB_LAUNCH_CHECK() BB_HIP(hipGetLastError())
+
+#define BB_REQUIRE(cond, ...)                                                   \
+    do {                                                                        \
+        if (!(cond)) ::bbfmm::fail(BBFMM_ERR_INVALID_ARG, __VA_ARGS__);         \
+    } while (0)
+
+#define BB_INTERNAL(cond, ...)                                                  \
+    do {                                                                        \
+        if (!(cond)) ::bbfmm::fail(BBFMM_ERR_INTERNAL, __VA_ARGS__);            \
+    } while (0)
+
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        BB_HIP(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Host-side table of the 316 transfer vectors (compact index order) and,
+// per octant, the 189 of them whose parents are adjacent.
+struct TransferTables {
+    int tvec[kNumT][3];
+    int slot_t[8][kSlots];      // octant, slot -> compact t index
+    int t_slot[8][kNumT];       // octant, t -> slot or -1
+    TransferTables();
+};
+const TransferTables &transfer_tables();
+
+// ---------------------------------------------------------------- tree ----
+struct LevelData {
+    int32_t C = 0;
+    DBuf<uint64_t> keys;
+    DBuf<int32_t> pb, pe, parent, cb, ce;
+    // M2L structures, levels >= 2
+    DBuf<int32_t> itab;             // [C][189]: source cell per slot, -1 if none
+    DBuf<int32_t> oct_cells;        // cells grouped by octant (stable)
+    int32_t oct_off[9] = {0};       // group boundaries in oct_cells
+    int64_t npairs = 0;
+    DBuf<int32_t> pair_t, pair_tgt, pair_src, pair_goff;
+};
+
+}  // namespace bbfmm
+
+struct bbfmm_tree {
+    int64_t n = 0;
+    int depth = 0;
+    bbfmm_tree_params params{};
+    float lo[3] = {0, 0, 0};
+    float side = 1.f, scale = 1.f;
+    int32_t max_leaf = 0;
+    int64_t near_pairs = 0;
+    bbfmm::DBuf<int32_t> perm;
+    bbfmm::DBuf<float> xs, ys, zs;
+    bbfmm::LevelData lv[bbfmm::kMaxLevels];
+    bbfmm::DBuf<int32_t> nbr_off, nbr_idx;
+    int64_t nbr_nnz = 0;
+    bbfmm::DBuf<int32_t> tables;    // tvec[316][3], slot_t[8][189], t_slot[8][316]
+    int leaf_level() const { return depth - 1; }
+    double half_width(int level) const { return double(side) / double(1ull << (level + 1)); }
+};
+
+namespace bbfmm {
+
+// Chebyshev constants in float, passed to kernels by value.
+struct ChebConst {
+    int n;
+    float s[kMaxOrder];              // nodes cos((2m+1) pi / 2n)
+    float w[kMaxOrder];              // 1 / prod_{k != m} (s_m - s_k)
+    float T[2][kMaxOrder][kMaxOrder];// T[o][i][j] = l_i((2o-1)/2 + s_j/2)
+};
+
+// One compressed operator set (a level, or every level of a homogeneous kernel).
+struct OpSet {
+    int k = 0, kp = 0;               // rank and rank padded for MFMA tiles
+    DBuf<double> U64, V64, C64;      // m x k, m x k, 316 x k x k
+    DBuf<double> sv_fat, sv_thin;    // m each (empty when imported / eps = 0)
+    DBuf<float> UT32;                // kp x m: U^T, zero rows past k (decompression)
+    DBuf<float> V32;                 // m x kp: V, zero columns past k (compression)
+    DBuf<float> C32;                 // 316 x kp x kp (zero-padded)
+};
+
+struct OpsLevel {
+    OpSet *set = nullptr;
+    double scale = 1.0;              // factor applied after M2L (h^m for homogeneous kernels)
+};
+
+}  // namespace bbfmm
+
+struct bbfmm_ops {
+    const bbfmm_tree *tree = nullptr;
+    int n = 0, m = 0;
+    int precision = 0;
+    double eps = 0.0;
+    bbfmm::ChebConst cheb{};
+    std::vector<std::unique_ptr<bbfmm::OpSet>> sets;
+    bbfmm::OpsLevel lv[bbfmm::kMaxLevels];
+};
+
+namespace bbfmm {
+
+// --------------------------------------------------------------- entry ----
+bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params &p,
+                            hipStream_t s);
+bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s);
+void cheb_setup(bbfmm_ops *ops, hipStream_t s);
+void finalize_opset(OpSet &set, int m, hipStream_t s);
+
+struct Plan;
+Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r);
+void plan_execute_impl(Plan *p, const float *sigma, float *phi, hipStream_t s);
+int64_t plan_workspace_bytes(const Plan *p);
+void plan_destroy(Plan *p);
+void plan_set_timing(Plan *p, bool on);
+void plan_stage_times(Plan *p, double *ms, int64_t *execs, bool reset);
+
+// --------------------------------------------------------- primitives ----
+// exclusive prefix sum of n int32 values (in may equal out); returns total
+int64_t scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+// stable LSD radix sort of (key, value) by the low `bits` bits of key
+void radix_sort_pairs(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+
+}  // namespace bbfmm

@@ -1,0 +1,681 @@
+// The bbFMM matvec on the GPU (Section 2.3), FP32 throughout.
+//
+// Data in HBM (per level l >= 2; C_l cells, r right-hand sides, m = n^3,
+// kp = compressed rank padded to 16):
+//   M_l  [C_l][r][m]   multipole coefficients     (P2M / M2M)
+//   Mh_l [C_l][r][kp]  compressed multipoles      V^T M
+//   Fh_l [C_l][r][kp]  compressed locals          sum_t C_t Mh      (M2L)
+//   F_l  [C_l][r][m]   local coefficients         scale U Fh + L2L
+// Points stay sorted (structure of arrays) and sigma is gathered into that
+// order once; phi is written straight back in the caller's order.
+//
+// Stages (one launch each, level-synchronous):
+//   gather   sigma -> sorted order
+//   p2m      per leaf: M = S^T sigma, then Mh = V^T M
+//   m2m      per parent, levels L-1..2: M = sum_children T (x) T (x) T M_child,
+//            three n x n mode products in LDS; then Mh = V^T M
+//   m2l      per tile of same-octant targets: Fh += C_t Mh[source] for the
+//            189 transfer vectors of that octant, fp32 MFMA 16x16x4
+//   down     per cell, levels 2..L: F = scale U Fh + (T^T (x) T^T (x) T^T) F_parent
+//   p2p      per 64 targets of a leaf: L2P of F plus the direct sum over
+//            the neighbour leaves, staged through LDS
+// No atomics on the data path: every output has one owner, so results are
+// bitwise reproducible.
+#include "common.h"
+
+namespace bbfmm {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kLdsFloats = 4096;      // per LDS buffer of the up / down kernels
+
+// --------------------------------------------------------- geometry ----
+__device__ inline uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return uint32_t(x);
+}
+
+// Cell centre lo + (2k+1) h as an unevaluated float pair hi + lo (exact
+// product by FMA, exact sum by Knuth's two-sum), so that the local
+// coordinate (x - c) / h keeps float precision at every depth.
+__device__ inline void center_pair(float lo, uint32_t k, float h, float &chi, float &clo) {
+#pragma clang fp contract(off)
+    const float f = float(2u * k + 1u);
+    const float p = __fmul_rn(f, h);
+    const float e = __fmaf_rn(f, h, -p);
+    const float s = __fadd_rn(lo, p);
+    const float bb = __fsub_rn(s, lo);
+    const float err = __fadd_rn(__fsub_rn(lo, __fsub_rn(s, bb)), __fsub_rn(p, bb));
+    chi = s;
+    clo = __fadd_rn(err, e);
+}
+
+__device__ inline float local_coord(float x, float chi, float clo, float inv_h) {
+#pragma clang fp contract(off)
+    return __fmul_rn(__fsub_rn(__fsub_rn(x, chi), clo), inv_h);
+}
+
+// l_m(xi) = w_m prod_{k != m} (xi - s_k)  for m < n
+__device__ inline void lagrange(const ChebConst &cc, float xi, float *out) {
+    const int n = cc.n;
+    for (int m = 0; m < n; ++m) {
+        float p = cc.w[m];
+        for (int k = 0; k < n; ++k)
+            if (k != m) p *= xi - cc.s[k];
+        out[m] = p;
+    }
+}
+
+struct Geo {
+    float lo[3];
+    float h;        // half-width of a leaf
+    float inv_h;
+};
+
+// ----------------------------------------------------------- kernels ----
+template <int KID>
+__device__ inline float kernel_eval(float dx, float dy, float dz, float ia, float ia2) {
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if constexpr (KID == BBFMM_K_INV_R) {
+        return r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
+    } else if constexpr (KID == BBFMM_K_EXP) {
+        return __expf(-__fsqrt_rn(r2) * ia);
+    } else if constexpr (KID == BBFMM_K_GAUSS) {
+        return __expf(-r2 * ia2);
+    } else {
+        const float u[3] = {dx * ia, dy * ia, dz * ia};
+        float p = 1.f;
+        for (int d = 0; d < 3; ++d)
+            p *= 1.f + u[d] * 0.5f - u[d] * u[d] * (1.f / 3.f) + u[d] * u[d] * u[d] * 0.2f;
+        return p;
+    }
+}
+
+// ------------------------------------------------------------ gather ----
+__global__ void __launch_bounds__(kThreads)
+k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, float *sig_s) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= n * r) return;
+    const int64_t i = g / r;
+    const int c = int(g % r);
+    sig_s[g] = sigma[int64_t(perm[i]) * r + c];
+}
+
+// --------------------------------------------------------------- P2M ----
+// grid (leaves, rhs chunks of rc); M = S^T sigma, Mh = V^T M.
+__global__ void __launch_bounds__(kThreads)
+k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
+      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int r, int rc,
+      const float *V32, int kp, float *M, float *Mh) {
+    __shared__ float acc[kLdsFloats];
+    __shared__ float lv[64][3][kMaxOrder];
+    __shared__ float sg[64][16];
+    const int a = blockIdx.x, rhs0 = blockIdx.y * rc;
+    const int nr = min(rc, r - rhs0);
+    const int n = cc.n, m = n * n * n, tot = nr * m;
+    const int tid = threadIdx.x;
+    const uint64_t key = keys[a];
+    float chi[3], clo[3];
+    for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
+    for (int idx = tid; idx < tot; idx += kThreads) acc[idx] = 0.f;
+    const int b = pb[a], e = pe[a];
+    for (int p0 = b; p0 < e; p0 += 64) {
+        const int np = min(64, e - p0);
+        __syncthreads();
+        if (tid < 3 * np) {
+            const int p = tid / 3, d = tid % 3;
+            const float x = (d == 0 ? xs : d == 1 ? ys : zs)[p0 + p];
+            float l[kMaxOrder];
+            lagrange(cc, local_coord(x, chi[d], clo[d], geo.inv_h), l);
+            for (int q = 0; q < n; ++q) lv[p][d][q] = l[q];
+        }
+        for (int idx = tid; idx < np * nr; idx += kThreads)
+            sg[idx / nr][idx % nr] = sig_s[int64_t(p0 + idx / nr) * r + rhs0 + idx % nr];
+        __syncthreads();
+        for (int idx = tid; idx < tot; idx += kThreads) {
+            const int c = idx / m, i = idx % m;
+            const int i1 = i % n, i2 = (i / n) % n, i3 = i / (n * n);
+            float s = acc[idx];
+            for (int p = 0; p < np; ++p) s += lv[p][0][i1] * lv[p][1][i2] * lv[p][2][i3] * sg[p][c];
+            acc[idx] = s;
+        }
+    }
+    __syncthreads();
+    float *Mo = M + (int64_t(a) * r + rhs0) * m;
+    for (int idx = tid; idx < tot; idx += kThreads) Mo[idx] = acc[idx];
+    float *Mho = Mh + (int64_t(a) * r + rhs0) * kp;
+    for (int idx = tid; idx < nr * kp; idx += kThreads) {
+        const int c = idx / kp, kk = idx % kp;
+        float s = 0.f;
+        for (int i = 0; i < m; ++i) s += V32[int64_t(i) * kp + kk] * acc[c * m + i];
+        Mho[idx] = s;
+    }
+}
+
+// Three mode products of an n x n x n block per rhs, in LDS:
+// B[c][i3][i2][i1] = sum_j T(ox,i1,j1) T(oy,i2,j2) T(oz,i3,j3) A[c][j3][j2][j1],
+// with T(o,i,j) = Ts[o][i][j] (trans = false) or Ts[o][j][i].  A is clobbered.
+__device__ inline void mode3(float *A, float *B, int nr, int n, const float (*Ts)[kMaxOrder][kMaxOrder],
+                             int ox, int oy, int oz, bool trans) {
+    const int m = n * n * n, tot = nr * m;
+    auto T = [&](int o, int i, int j) { return trans ? Ts[o][j][i] : Ts[o][i][j]; };
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx / m, i = idx % m;
+        const int i1 = i % n, rest = i - i1;
+        float s = 0.f;
+        for (int j = 0; j < n; ++j) s += T(ox, i1, j) * A[c * m + rest + j];
+        B[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx / m, i = idx % m;
+        const int i1 = i % n, i2 = (i / n) % n, i3 = i / (n * n);
+        float s = 0.f;
+        for (int j = 0; j < n; ++j) s += T(oy, i2, j) * B[c * m + i3 * n * n + j * n + i1];
+        A[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx / m, i = idx % m;
+        const int i12 = i % (n * n), i3 = i / (n * n);
+        float s = 0.f;
+        for (int j = 0; j < n; ++j) s += T(oz, i3, j) * A[c * m + j * n * n + i12];
+        B[idx] = s;
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- M2M ----
+// grid (parents on level l, rhs chunks)
+__global__ void __launch_bounds__(kThreads)
+k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Mc, ChebConst cc,
+      int r, int rc, const float *V32, int kp, float *M, float *Mh) {
+    __shared__ float acc[kLdsFloats], bufA[kLdsFloats], bufB[kLdsFloats];
+    __shared__ float Ts[2][kMaxOrder][kMaxOrder];
+    const int P = blockIdx.x, rhs0 = blockIdx.y * rc;
+    const int nr = min(rc, r - rhs0);
+    const int n = cc.n, m = n * n * n, tot = nr * m;
+    const int tid = threadIdx.x;
+    if (tid < 2 * kMaxOrder * kMaxOrder) (&Ts[0][0][0])[tid] = (&cc.T[0][0][0])[tid];
+    for (int idx = tid; idx < tot; idx += kThreads) acc[idx] = 0.f;
+    for (int ch = cb[P]; ch < ce[P]; ++ch) {
+        const int o = int(ckeys[ch] & 7);
+        __syncthreads();
+        const float *src = Mc + (int64_t(ch) * r + rhs0) * m;
+        for (int idx = tid; idx < tot; idx += kThreads) bufA[idx] = src[idx];
+        __syncthreads();
+        mode3(bufA, bufB, nr, n, Ts, o & 1, (o >> 1) & 1, (o >> 2) & 1, false);
+        for (int idx = tid; idx < tot; idx += kThreads) acc[idx] += bufB[idx];
+    }
+    __syncthreads();
+    float *Mo = M + (int64_t(P) * r + rhs0) * m;
+    for (int idx = tid; idx < tot; idx += kThreads) Mo[idx] = acc[idx];
+    float *Mho = Mh + (int64_t(P) * r + rhs0) * kp;
+    for (int idx = tid; idx < nr * kp; idx += kThreads) {
+        const int c = idx / kp, kk = idx % kp;
+        float s = 0.f;
+        for (int i = 0; i < m; ++i) s += V32[int64_t(i) * kp + kk] * acc[c * m + i];
+        Mho[idx] = s;
+    }
+}
+
+// --------------------------------------------------------------- M2L ----
+// One workgroup = one tile of up to 64 columns (target, rhs) of targets that
+// share an octant, times 64 rows of the compressed rank.  For every slot
+// j < 189 the octant fixes the transfer vector t; the sources Mh[k(a) + t]
+// of the tile are staged in LDS and multiplied by C_t with
+// v_mfma_f32_16x16x4f32 (each wave owns 16 rows x 64 columns).
+// Lane layout of the 16x16x4 MFMA: A[i][k] from lane i + 16k, B[k][j] from
+// lane j + 16k, D[i][j] in lane j + 16 (i / 4), register i % 4.  The K index
+// of four consecutive MFMAs is permuted identically for A and B so each lane
+// reads 4 consecutive K values with one 16-byte load.
+constexpr int kM2LCols = 64;
+
+struct M2LLevel {
+    const float *Mh;
+    float *Fh;
+    const float *C32;
+    const int32_t *itab;
+    const int32_t *oct_cells;
+    int kp;
+};
+
+struct M2LArgs {
+    M2LLevel lv[kMaxLevels];
+    const int32_t *tiles;       // [ntiles][4]: level, octant, first in oct_cells, count
+    const int32_t *tables;      // slot_t[8][189] at offset 3 * 316
+    int r, rc, tpt;
+};
+
+__global__ void __launch_bounds__(kThreads) k_m2l(M2LArgs g) {
+    constexpr int ldb = 64 + 4;                   // K chunk of 64 plus padding
+    __shared__ float Bs[kM2LCols * ldb];
+    __shared__ int32_t tgt[kM2LCols], srcs[kM2LCols];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[blockIdx.x];
+    const M2LLevel &L = g.lv[tile.x];
+    const int o = tile.y, start = tile.z, cnt = tile.w;
+    const int kp = L.kp;
+    if (int(blockIdx.y) * 64 >= kp) return;       // row group beyond this level's rank
+    const float *Mh = L.Mh;
+    const int32_t *itab = L.itab;
+    const int r = g.r, rc = g.rc, tpt = g.tpt;
+    const int rhs0 = blockIdx.z * rc;
+    const int row0 = blockIdx.y * 64 + wave * 16;
+    const bool active = row0 < kp;
+    const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
+    if (tid < kM2LCols) tgt[tid] = tid < cnt ? L.oct_cells[start + tid] : -1;
+    v4f acc[4];
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < kSlots; ++j) {
+        __syncthreads();
+        if (tid < kM2LCols) srcs[tid] = (tid < cnt) ? itab[int64_t(tgt[tid]) * kSlots + j] : -1;
+        __syncthreads();
+        const float *A = L.C32 + int64_t(slot_t[j]) * kp * kp;
+        for (int kc = 0; kc < kp; kc += 64) {
+            const int nf4 = min(64, kp - kc) / 4;
+            for (int e = tid; e < kM2LCols * nf4; e += kThreads) {
+                const int col = e / nf4, q = e % nf4;
+                const int tl = col / rc, c = col % rc;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (tl < tpt && rhs0 + c < r) {
+                    const int sc = srcs[tl];
+                    if (sc >= 0)
+                        v = *reinterpret_cast<const float4 *>(
+                            Mh + (int64_t(sc) * r + rhs0 + c) * kp + kc + 4 * q);
+                }
+                *reinterpret_cast<float4 *>(Bs + col * ldb + 4 * q) = v;
+            }
+            __syncthreads();
+            if (active) {
+                for (int kb = 0; kb < nf4 / 4; ++kb) {
+                    const float4 a4 = *reinterpret_cast<const float4 *>(
+                        A + int64_t(row0 + (lane & 15)) * kp + kc + 16 * kb + 4 * (lane >> 4));
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const float4 b4 = *reinterpret_cast<const float4 *>(
+                            Bs + (cb * 16 + (lane & 15)) * ldb + 16 * kb + 4 * (lane >> 4));
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!active) return;
+    for (int cb = 0; cb < 4; ++cb) {
+        const int col = cb * 16 + (lane & 15);
+        const int tl = col / rc, c = col % rc;
+        if (tl < cnt && rhs0 + c < r) {
+            float *dst = L.Fh + (int64_t(tgt[tl]) * r + rhs0 + c) * kp + row0 + 4 * (lane >> 4);
+            *reinterpret_cast<float4 *>(dst) = make_float4(acc[cb][0], acc[cb][1], acc[cb][2], acc[cb][3]);
+        }
+    }
+}
+
+// -------------------------------------------------------------- down ----
+// grid (cells on level l, rhs chunks): F = scale U Fh (+ L2L of the parent F)
+__global__ void __launch_bounds__(kThreads)
+k_down(const float *Fh, const float *UT32, int kp, float scale, const int32_t *parent,
+       const uint64_t *keys, const float *Fp, ChebConst cc, int r, int rc, float *F) {
+    __shared__ float acc[kLdsFloats], bufA[kLdsFloats], bufB[kLdsFloats];
+    __shared__ float Ts[2][kMaxOrder][kMaxOrder];
+    const int a = blockIdx.x, rhs0 = blockIdx.y * rc;
+    const int nr = min(rc, r - rhs0);
+    const int n = cc.n, m = n * n * n, tot = nr * m;
+    const int tid = threadIdx.x;
+    if (tid < 2 * kMaxOrder * kMaxOrder) (&Ts[0][0][0])[tid] = (&cc.T[0][0][0])[tid];
+    const float *fh = Fh + (int64_t(a) * r + rhs0) * kp;
+    for (int idx = tid; idx < nr * kp; idx += kThreads) bufA[idx] = fh[idx];
+    __syncthreads();
+    for (int idx = tid; idx < tot; idx += kThreads) {
+        const int c = idx / m, i = idx % m;
+        float s = 0.f;
+        for (int kk = 0; kk < kp; ++kk) s += UT32[int64_t(kk) * m + i] * bufA[c * kp + kk];
+        acc[idx] = scale * s;
+    }
+    if (Fp != nullptr) {
+        const int P = parent[a];
+        const int o = int(keys[a] & 7);
+        __syncthreads();
+        const float *src = Fp + (int64_t(P) * r + rhs0) * m;
+        for (int idx = tid; idx < tot; idx += kThreads) bufA[idx] = src[idx];
+        __syncthreads();
+        mode3(bufA, bufB, nr, n, Ts, o & 1, (o >> 1) & 1, (o >> 2) & 1, true);
+        for (int idx = tid; idx < tot; idx += kThreads) acc[idx] += bufB[idx];
+    }
+    float *Fo = F + (int64_t(a) * r + rhs0) * m;
+    for (int idx = tid; idx < tot; idx += kThreads) Fo[idx] = acc[idx];
+}
+
+// --------------------------------------------------------- L2P + P2P ----
+// One wave per work item (leaf, first target): lanes own targets; sources of
+// the neighbour leaves are staged 64 at a time in LDS.
+template <int KID, int RC>
+__global__ void __launch_bounds__(64)
+k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
+      const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
+      const int32_t *work, const float *sig_s, int r, float ia, float ia2, const float *FL,
+      Geo geo, ChebConst cc, float *phi) {
+    __shared__ float sx[64], sy[64], sz[64], ss[64][RC];
+    const int lane = threadIdx.x;
+    const int a = work[2 * blockIdx.x], t0 = work[2 * blockIdx.x + 1];
+    const int rhs0 = blockIdx.y * RC;
+    const int nr = min(RC, r - rhs0);
+    const int i = t0 + lane;
+    const bool valid = i < pe[a];
+    const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
+    float acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0.f;
+    for (int q = nbr_off[a]; q < nbr_off[a + 1]; ++q) {
+        const int b = nbr_idx[q];
+        const int sb = pb[b], se = pe[b];
+        for (int s0 = sb; s0 < se; s0 += 64) {
+            const int ns = min(64, se - s0);
+            __syncthreads();
+            if (lane < ns) {
+                sx[lane] = xs[s0 + lane];
+                sy[lane] = ys[s0 + lane];
+                sz[lane] = zs[s0 + lane];
+#pragma unroll
+                for (int c = 0; c < RC; ++c)
+                    ss[lane][c] = c < nr ? sig_s[int64_t(s0 + lane) * r + rhs0 + c] : 0.f;
+            }
+            __syncthreads();
+            for (int j = 0; j < ns; ++j) {
+                const float k = kernel_eval<KID>(x - sx[j], y - sy[j], z - sz[j], ia, ia2);
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[c] += k * ss[j][c];
+            }
+        }
+    }
+    if (!valid) return;
+    if (FL != nullptr) {
+        const int n = cc.n, m = n * n * n;
+        const uint64_t key = keys[a];
+        float l[3][kMaxOrder];
+        const float p[3] = {x, y, z};
+        for (int d = 0; d < 3; ++d) {
+            float chi, clo;
+            center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
+            lagrange(cc, local_coord(p[d], chi, clo, geo.inv_h), l[d]);
+        }
+        for (int c = 0; c < nr; ++c) {
+            const float *f = FL + (int64_t(a) * r + rhs0 + c) * m;
+            float s = 0.f;
+            for (int i3 = 0; i3 < n; ++i3) {
+                float s2 = 0.f;
+                for (int i2 = 0; i2 < n; ++i2) {
+                    float s1 = 0.f;
+                    for (int i1 = 0; i1 < n; ++i1) s1 += l[0][i1] * f[(i3 * n + i2) * n + i1];
+                    s2 += l[1][i2] * s1;
+                }
+                s += l[2][i3] * s2;
+            }
+#pragma unroll
+            for (int cc2 = 0; cc2 < RC; ++cc2)
+                if (cc2 == c) acc[cc2] += s;
+        }
+    }
+    float *out = phi + int64_t(perm[i]) * r + rhs0;
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+        if (c < nr) out[c] = acc[c];
+}
+
+inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
+
+}  // namespace
+
+// -------------------------------------------------------------- plan ----
+constexpr int kTimingRing = 64;
+
+struct Plan {
+    const bbfmm_tree *tree = nullptr;
+    const bbfmm_ops *ops = nullptr;
+    int64_t r = 0;
+    int rc_up = 1;                      // rhs chunk of the up / down kernels
+    int rc_m2l = 1, tpt = 64;           // M2L column tile: tpt targets x rc_m2l rhs
+    int rc_p2p = 1;
+    DBuf<float> sig_s;
+    DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
+    DBuf<int32_t> tiles;                // all M2L tiles of all levels
+    int ntiles = 0, max_kp = 0;
+    DBuf<int32_t> work;
+    int nwork = 0;
+    int64_t ws_bytes = 0;
+    // stage timing: a ring of event sets, harvested on query
+    bool timing = false;
+    std::vector<hipEvent_t> events;     // kTimingRing x (BBFMM_NUM_STAGES + 1)
+    int ring_head = 0, ring_pending = 0;
+    double stage_ms[BBFMM_NUM_STAGES] = {0};
+    int64_t timed_execs = 0;
+    ~Plan() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+};
+
+Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
+    BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
+    BB_REQUIRE(o->tree == t, "operators were built for another tree");
+    BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
+    std::unique_ptr<Plan> p(new Plan());
+    p->tree = t;
+    p->ops = o;
+    p->r = r;
+    const int L = t->leaf_level();
+    const int m = o->m;
+    p->rc_up = int(std::max<int64_t>(1, std::min<int64_t>(r, kLdsFloats / std::max(m, 512))));
+    p->rc_m2l = int(std::min<int64_t>(r, kM2LCols));
+    p->tpt = kM2LCols / p->rc_m2l;
+    p->rc_p2p = 1;
+    while (p->rc_p2p < r && p->rc_p2p < 64) p->rc_p2p *= 2;
+    p->sig_s.alloc(t->n * r);
+    int64_t ws = p->sig_s.bytes();
+    std::vector<int32_t> tl;
+    for (int lvl = 2; lvl <= L; ++lvl) {
+        const int64_t C = t->lv[lvl].C;
+        const int kp = o->lv[lvl].set->kp;
+        p->max_kp = std::max(p->max_kp, kp);
+        p->M[lvl].alloc(C * r * m);
+        p->F[lvl].alloc(C * r * m);
+        p->Mh[lvl].alloc(C * r * kp);
+        p->Fh[lvl].alloc(C * r * kp);
+        ws += p->M[lvl].bytes() + p->F[lvl].bytes() + p->Mh[lvl].bytes() + p->Fh[lvl].bytes();
+        // M2L tiles: runs of up to tpt cells of one octant
+        for (int oc = 0; oc < 8; ++oc)
+            for (int s = t->lv[lvl].oct_off[oc]; s < t->lv[lvl].oct_off[oc + 1]; s += p->tpt) {
+                tl.push_back(lvl);
+                tl.push_back(oc);
+                tl.push_back(s);
+                tl.push_back(std::min(p->tpt, t->lv[lvl].oct_off[oc + 1] - s));
+            }
+    }
+    p->ntiles = int(tl.size() / 4);
+    if (p->ntiles) {
+        p->tiles.alloc(tl.size());
+        BB_HIP(hipMemcpy(p->tiles.p, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    // P2P work items: (leaf, first target) per 64 targets
+    {
+        const LevelData &leaf = t->lv[L];
+        std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
+        BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        BB_HIP(hipMemcpy(he.data(), leaf.pe.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int a = 0; a < leaf.C; ++a)
+            for (int s = hb[a]; s < he[a]; s += 64) { w.push_back(a); w.push_back(s); }
+        p->nwork = int(w.size() / 2);
+        p->work.alloc(w.size());
+        BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    p->ws_bytes = ws;
+    return p.release();
+}
+
+int64_t plan_workspace_bytes(const Plan *p) { return p->ws_bytes; }
+void plan_destroy(Plan *p) { delete p; }
+
+namespace {
+
+constexpr int kEv = BBFMM_NUM_STAGES + 1;
+
+// fold the oldest pending execution's stage times into the totals
+void harvest_one(Plan &p) {
+    const int slot = (p.ring_head - p.ring_pending + kTimingRing) % kTimingRing;
+    hipEvent_t *ev = &p.events[size_t(slot) * kEv];
+    BB_HIP(hipEventSynchronize(ev[kEv - 1]));
+    for (int st = 0; st < BBFMM_NUM_STAGES; ++st) {
+        float ms = 0.f;
+        BB_HIP(hipEventElapsedTime(&ms, ev[st], ev[st + 1]));
+        p.stage_ms[st] += ms;
+    }
+    --p.ring_pending;
+    ++p.timed_execs;
+}
+
+template <int KID>
+void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipStream_t s) {
+    const bbfmm_tree &t = *p.tree;
+    const LevelData &leaf = t.lv[t.leaf_level()];
+    const double a = t.params.kernel_param;
+    const float ia = float(1.0 / a), ia2 = float(1.0 / (a * a));
+    dim3 g(p.nwork, unsigned(ceil_div(p.r, p.rc_p2p)));
+#define BB_P2P(RCV)                                                                          \
+    k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
+                                     t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p,         \
+                                     p.work.p, p.sig_s.p, int(p.r), ia, ia2, FL, geo,         \
+                                     p.ops->cheb, phi)
+    switch (p.rc_p2p) {
+    case 1: BB_P2P(1); break;
+    case 2: BB_P2P(2); break;
+    case 4: BB_P2P(4); break;
+    case 8: BB_P2P(8); break;
+    case 16: BB_P2P(16); break;
+    case 32: BB_P2P(32); break;
+    default: BB_P2P(64); break;
+    }
+#undef BB_P2P
+    BB_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void plan_set_timing(Plan *p, bool on) {
+    BB_REQUIRE(p != nullptr, "plan is NULL");
+    if (on && p->events.empty()) {
+        p->events.resize(size_t(kTimingRing) * kEv);
+        for (hipEvent_t &e : p->events) BB_HIP(hipEventCreate(&e));
+    }
+    if (!on)
+        while (p->ring_pending > 0) harvest_one(*p);
+    p->timing = on;
+}
+
+void plan_stage_times(Plan *p, double *ms, int64_t *execs, bool reset) {
+    BB_REQUIRE(p != nullptr, "plan is NULL");
+    while (p->ring_pending > 0) harvest_one(*p);
+    if (ms)
+        for (int st = 0; st < BBFMM_NUM_STAGES; ++st) ms[st] = p->stage_ms[st];
+    if (execs) *execs = p->timed_execs;
+    if (reset) {
+        for (double &v : p->stage_ms) v = 0.0;
+        p->timed_execs = 0;
+    }
+}
+
+void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) {
+    BB_REQUIRE(pp != nullptr, "plan is NULL");
+    BB_REQUIRE(sigma != nullptr && phi != nullptr, "sigma / phi is NULL");
+    Plan &p = *pp;
+    const bbfmm_tree &t = *p.tree;
+    const bbfmm_ops &o = *p.ops;
+    const int L = t.leaf_level();
+    const int r = int(p.r);
+    Geo geo;
+    for (int d = 0; d < 3; ++d) geo.lo[d] = t.lo[d];
+    geo.h = float(t.half_width(L));
+    geo.inv_h = 1.0f / geo.h;
+
+    hipEvent_t *ev = nullptr;
+    if (p.timing) {
+        if (p.ring_pending == kTimingRing) harvest_one(p);
+        ev = &p.events[size_t(p.ring_head) * kEv];
+        p.ring_head = (p.ring_head + 1) % kTimingRing;
+        ++p.ring_pending;
+    }
+    auto mark = [&](int st) {
+        if (ev) BB_HIP(hipEventRecord(ev[st], s));
+    };
+
+    mark(BBFMM_STAGE_GATHER);
+    k_gather_sigma<<<grid(t.n * r), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.sig_s.p);
+    BB_LAUNCH_CHECK();
+    const float *FL = nullptr;
+    const unsigned rchunks = unsigned(ceil_div(r, p.rc_up));
+    mark(BBFMM_STAGE_P2M);
+    if (L >= 2) {
+        const LevelData &leaf = t.lv[L];
+        const OpSet &set = *o.lv[L].set;
+        k_p2m<<<dim3(leaf.C, rchunks), kThreads, 0, s>>>(
+            t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, leaf.keys.p, geo, o.cheb, p.sig_s.p, r,
+            p.rc_up, set.V32.p, set.kp, p.M[L].p, p.Mh[L].p);
+        BB_LAUNCH_CHECK();
+    }
+    mark(BBFMM_STAGE_M2M);
+    for (int lvl = L - 1; lvl >= 2; --lvl) {
+        const LevelData &lv = t.lv[lvl], &ch = t.lv[lvl + 1];
+        const OpSet &set = *o.lv[lvl].set;
+        k_m2m<<<dim3(lv.C, rchunks), kThreads, 0, s>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p,
+                                                       o.cheb, r, p.rc_up, set.V32.p, set.kp,
+                                                       p.M[lvl].p, p.Mh[lvl].p);
+        BB_LAUNCH_CHECK();
+    }
+    mark(BBFMM_STAGE_M2L);
+    if (L >= 2) {
+        M2LArgs g{};
+        for (int lvl = 2; lvl <= L; ++lvl) {
+            const OpSet &set = *o.lv[lvl].set;
+            g.lv[lvl] = M2LLevel{p.Mh[lvl].p, p.Fh[lvl].p, set.C32.p, t.lv[lvl].itab.p,
+                                 t.lv[lvl].oct_cells.p, set.kp};
+        }
+        g.tiles = p.tiles.p;
+        g.tables = t.tables.p;
+        g.r = r;
+        g.rc = p.rc_m2l;
+        g.tpt = p.tpt;
+        dim3 gr(p.ntiles, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
+        k_m2l<<<gr, kThreads, 0, s>>>(g);
+        BB_LAUNCH_CHECK();
+    }
+    mark(BBFMM_STAGE_DOWN);
+    for (int lvl = 2; lvl <= L; ++lvl) {
+        const LevelData &lv = t.lv[lvl];
+        const OpSet &set = *o.lv[lvl].set;
+        k_down<<<dim3(lv.C, rchunks), kThreads, 0, s>>>(
+            p.Fh[lvl].p, set.UT32.p, set.kp, float(o.lv[lvl].scale), lv.parent.p, lv.keys.p,
+            lvl > 2 ? p.F[lvl - 1].p : nullptr, o.cheb, r, p.rc_up, p.F[lvl].p);
+        BB_LAUNCH_CHECK();
+    }
+    if (L >= 2) FL = p.F[L].p;
+    mark(BBFMM_STAGE_P2P);
+    switch (t.params.kernel_id) {
+    case BBFMM_K_INV_R: launch_p2p<BBFMM_K_INV_R>(p, FL, geo, phi, s); break;
+    case BBFMM_K_EXP: launch_p2p<BBFMM_K_EXP>(p, FL, geo, phi, s); break;
+    case BBFMM_K_GAUSS: launch_p2p<BBFMM_K_GAUSS>(p, FL, geo, phi, s); break;
+    default: launch_p2p<BBFMM_K_POLY_TEST>(p, FL, geo, phi, s); break;
+    }
+    mark(BBFMM_NUM_STAGES);
+}
+
+}  // namespace bbfmm

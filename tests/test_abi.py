@@ -1,0 +1,75 @@
+"""The C-ABI library loads, exports every symbol include/bbfmm.h declares,
+and rejects invalid arguments before touching the GPU (CPU-only tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1903_02153_amd import bbfmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bbfmm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(bbfmm_[a-z_]+)\s*\(", text))
+
+
+def test_header_declares_the_paper_api():
+    names = declared_functions()
+    for fn in ("bbfmm_build_tree", "bbfmm_precompute_operators", "bbfmm_matvec"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bbfmm.lib()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    assert names == set(bbfmm.SIGNATURES)
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    lib = bbfmm.lib()
+    p = bbfmm.TreeParams(0, 1.0, 4, 64, 22, 0)
+    out = ctypes.c_void_p()
+    assert lib.bbfmm_build_tree(None, 10, ctypes.byref(p), None, ctypes.byref(out)) == 1
+    assert b"NULL" in lib.bbfmm_last_error()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bbfmm_build_tree(fake, 0, ctypes.byref(p), None, ctypes.byref(out)) == 1
+    bad = bbfmm.TreeParams(0, 1.0, 9, 64, 22, 0)
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert b"cheb_order" in lib.bbfmm_last_error()
+    bad = bbfmm.TreeParams(7, 1.0, 4, 64, 22, 0)
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    bad = bbfmm.TreeParams(0, 1.0, 4, 64, 23, 0)
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    bad = bbfmm.TreeParams(1, -1.0, 4, 64, 22, 0)
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert lib.bbfmm_precompute_operators(None, 1e-5, 0, None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_plan_create(None, None, 1, ctypes.byref(out)) == 1
+    assert lib.bbfmm_plan_execute(None, None, None, None) == 1
+    info = bbfmm.TreeInfo()
+    assert lib.bbfmm_tree_info_get(None, ctypes.byref(info)) == 1
+    # free functions accept NULL
+    lib.bbfmm_tree_free(None)
+    lib.bbfmm_ops_free(None)
+    lib.bbfmm_plan_free(None)
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        bbfmm.build_tree(torch.zeros((10, 3)))
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(bbfmm, "_lib_handle", None)
+    monkeypatch.setattr(bbfmm, "LIB_PATH", "/nonexistent/libbbfmm.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        bbfmm.lib()
