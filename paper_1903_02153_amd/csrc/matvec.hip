@@ -254,63 +254,150 @@ struct M2LArgs {
     int r, rc, tpt;
 };
 
-__global__ void __launch_bounds__(kThreads) k_m2l(M2LArgs g) {
-    constexpr int ldb = 64 + 4;                   // K chunk of 64 plus padding
-    __shared__ float Bs[kM2LCols * ldb];
-    __shared__ int32_t tgt[kM2LCols], srcs[kM2LCols];
+// Block index -> tile so that each XCD (blocks are dealt round-robin over
+// the 8 XCDs) receives a contiguous run of tiles: neighbouring tiles share
+// most of their sources, which then meet in the same L2.
+__device__ inline int xcd_tile(int bid, int nblocks) {
+    const int xcd = bid & 7, idx = bid >> 3;
+    const int full = nblocks >> 3, rem = nblocks & 7;
+    return xcd * full + min(xcd, rem) + idx;
+}
+
+// Software-pipelined M2L.  A step is (slot j, K chunk kc of 64).  While the
+// MFMAs of step s read LDS buffer s%2 and the C_t fragment held in
+// registers, the loads of step s+1 (gathered sources and the next C_t rows)
+// are already in flight into registers; they are written to the other LDS
+// buffer after the MFMAs, followed by the step's only barrier.  The source
+// index of slot j+3 is fetched during the last step of slot j into the
+// three-deep ring entry that slot j no longer needs.
+__global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
+    constexpr int ldb = 64 + 4;
+    __shared__ float Bs[2][kM2LCols * ldb];
+    __shared__ int32_t tgt[kM2LCols], srcs[3][kM2LCols];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[blockIdx.x];
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[xcd_tile(blockIdx.x, gridDim.x)];
     const M2LLevel &L = g.lv[tile.x];
     const int o = tile.y, start = tile.z, cnt = tile.w;
     const int kp = L.kp;
     if (int(blockIdx.y) * 64 >= kp) return;       // row group beyond this level's rank
     const float *Mh = L.Mh;
     const int32_t *itab = L.itab;
-    const int r = g.r, rc = g.rc, tpt = g.tpt;
+    const int r = g.r, rc = g.rc;
     const int rhs0 = blockIdx.z * rc;
     const int row0 = blockIdx.y * 64 + wave * 16;
     const bool active = row0 < kp;
     const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
-    if (tid < kM2LCols) tgt[tid] = tid < cnt ? L.oct_cells[start + tid] : -1;
+    const int nkc = (kp + 63) / 64;
+    const int nsteps = kSlots * nkc;
+    (void)lane;
+
+    if (tid < kM2LCols) {
+        const int a = tid < cnt ? L.oct_cells[start + tid] : -1;
+        tgt[tid] = a;
+        for (int q = 0; q < 3; ++q) srcs[q][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
+    }
+    __syncthreads();
+
+    // Per-thread share of one B chunk (64 columns x 16 float4): element
+    // e = tid + 256 i is column e / 16, float4 e % 16.  Column -> (target
+    // slot, rhs) is fixed for the whole tile, so all index math is hoisted.
+    int bq[4], btl[4];
+    int64_t boff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + i * kThreads;
+        const int col = e >> 4;
+        bq[i] = e & 15;
+        btl[i] = col / rc;
+        const int c = col - btl[i] * rc;
+        boff[i] = (rhs0 + c < r) ? int64_t(rhs0 + c) * kp + 4 * bq[i] : -1;
+    }
+    auto load_b = [&](int j, int kc, float4 *breg) {
+        const int lim = min(64, kp - kc * 64) / 4;   // float4 per column in this chunk
+        const int32_t *sj = srcs[j % 3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int sc = btl[i] < kM2LCols ? sj[btl[i]] : -1;
+            if (sc >= 0 && boff[i] >= 0 && bq[i] < lim)
+                v = *reinterpret_cast<const float4 *>(Mh + int64_t(sc) * r * kp + boff[i] + kc * 64);
+            breg[i] = v;
+        }
+    };
+    auto store_b = [&](int buf, const float4 *breg) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kThreads;
+            *reinterpret_cast<float4 *>(&Bs[buf][(e >> 4) * ldb + 4 * bq[i]]) = breg[i];
+        }
+    };
+    const float *Arow = L.C32 + int64_t(row0 + (lane & 15)) * kp + 4 * (lane >> 4);
+    auto load_a = [&](int j, int kc, float4 *areg) {
+        const int nkb = min(64, kp - kc * 64) / 16;
+        const float *A = Arow + int64_t(slot_t[j]) * kp * kp + kc * 64;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+            areg[kb] = (active && kb < nkb) ? *reinterpret_cast<const float4 *>(A + 16 * kb)
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+
     v4f acc[4];
     for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < kSlots; ++j) {
-        __syncthreads();
-        if (tid < kM2LCols) srcs[tid] = (tid < cnt) ? itab[int64_t(tgt[tid]) * kSlots + j] : -1;
-        __syncthreads();
-        const float *A = L.C32 + int64_t(slot_t[j]) * kp * kp;
-        for (int kc = 0; kc < kp; kc += 64) {
-            const int nf4 = min(64, kp - kc) / 4;
-            for (int e = tid; e < kM2LCols * nf4; e += kThreads) {
-                const int col = e / nf4, q = e % nf4;
-                const int tl = col / rc, c = col % rc;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (tl < tpt && rhs0 + c < r) {
-                    const int sc = srcs[tl];
-                    if (sc >= 0)
-                        v = *reinterpret_cast<const float4 *>(
-                            Mh + (int64_t(sc) * r + rhs0 + c) * kp + kc + 4 * q);
-                }
-                *reinterpret_cast<float4 *>(Bs + col * ldb + 4 * q) = v;
+    float4 breg[4], acur[4], anxt[4];
+    load_b(0, 0, breg);
+    store_b(0, breg);
+    load_a(0, 0, acur);
+    __syncthreads();
+    int32_t itab_next = -1;
+    int j = 0, kc = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        int j1 = j, kc1 = kc + 1;
+        if (kc1 == nkc) { kc1 = 0; ++j1; }
+        const bool more = s + 1 < nsteps;
+        const bool new_slot = more && kc1 == 0;
+        if (more) {
+            load_b(j1, kc1, breg);
+            load_a(j1, kc1, anxt);
+            if (new_slot && tid < kM2LCols && j + 3 < kSlots) {
+                const int a = tgt[tid];
+                itab_next = a >= 0 ? itab[int64_t(a) * kSlots + j + 3] : -1;
             }
-            __syncthreads();
-            if (active) {
-                for (int kb = 0; kb < nf4 / 4; ++kb) {
-                    const float4 a4 = *reinterpret_cast<const float4 *>(
-                        A + int64_t(row0 + (lane & 15)) * kp + kc + 16 * kb + 4 * (lane >> 4));
-#pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
-                        const float4 b4 = *reinterpret_cast<const float4 *>(
-                            Bs + (cb * 16 + (lane & 15)) * ldb + 16 * kb + 4 * (lane >> 4));
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[cb], 0, 0, 0);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[cb], 0, 0, 0);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[cb], 0, 0, 0);
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[cb], 0, 0, 0);
-                    }
-                }
-            }
-            __syncthreads();
         }
+        if (active) {
+            const int nkb = min(64, kp - kc * 64) / 16;
+            const float *B = Bs[s & 1] + (lane & 15) * ldb + 4 * (lane >> 4);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                if (kb < nkb) {
+                    float4 b4[4];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        b4[cb] = *reinterpret_cast<const float4 *>(B + cb * 16 * ldb + 16 * kb);
+                    // independent accumulators back to back
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].x, b4[cb].x, acc[cb], 0, 0, 0);
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].y, b4[cb].y, acc[cb], 0, 0, 0);
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].z, b4[cb].z, acc[cb], 0, 0, 0);
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].w, b4[cb].w, acc[cb], 0, 0, 0);
+                }
+            }
+        }
+        if (more) {
+            store_b((s + 1) & 1, breg);
+            if (new_slot && tid < kM2LCols && j + 3 < kSlots) srcs[j % 3][tid] = itab_next;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acur[kb] = anxt[kb];
+        j = j1;
+        kc = kc1;
     }
     if (!active) return;
     for (int cb = 0; cb < 4; ++cb) {
@@ -359,8 +446,11 @@ k_down(const float *Fh, const float *UT32, int kp, float scale, const int32_t *p
 }
 
 // --------------------------------------------------------- L2P + P2P ----
-// One wave per work item (leaf, first target): lanes own targets; sources of
-// the neighbour leaves are staged 64 at a time in LDS.
+// One wave per work item (leaf a, first target t0, log2 S): the wave holds
+// T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes")
+// that stride through the sources staged 64 at a time in LDS, and through
+// the i3 planes of the L2P sum.  The S partial sums of a target are added
+// by a fixed butterfly of cross-lane shuffles, so results are reproducible.
 template <int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
@@ -369,10 +459,12 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
       Geo geo, ChebConst cc, float *phi) {
     __shared__ float sx[64], sy[64], sz[64], ss[64][RC];
     const int lane = threadIdx.x;
-    const int a = work[2 * blockIdx.x], t0 = work[2 * blockIdx.x + 1];
+    const int a = work[3 * blockIdx.x], t0 = work[3 * blockIdx.x + 1];
+    const int lgS = work[3 * blockIdx.x + 2];
+    const int S = 1 << lgS, sub = lane & (S - 1);
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, r - rhs0);
-    const int i = t0 + lane;
+    const int i = t0 + (lane >> lgS);
     const bool valid = i < pe[a];
     const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
     float acc[RC];
@@ -393,15 +485,14 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                     ss[lane][c] = c < nr ? sig_s[int64_t(s0 + lane) * r + rhs0 + c] : 0.f;
             }
             __syncthreads();
-            for (int j = 0; j < ns; ++j) {
+            for (int j = sub; j < ns; j += S) {
                 const float k = kernel_eval<KID>(x - sx[j], y - sy[j], z - sz[j], ia, ia2);
 #pragma unroll
                 for (int c = 0; c < RC; ++c) acc[c] += k * ss[j][c];
             }
         }
     }
-    if (!valid) return;
-    if (FL != nullptr) {
+    if (FL != nullptr && valid) {
         const int n = cc.n, m = n * n * n;
         const uint64_t key = keys[a];
         float l[3][kMaxOrder];
@@ -411,10 +502,12 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
             center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
             lagrange(cc, local_coord(p[d], chi, clo, geo.inv_h), l[d]);
         }
-        for (int c = 0; c < nr; ++c) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            if (c >= nr) break;
             const float *f = FL + (int64_t(a) * r + rhs0 + c) * m;
             float s = 0.f;
-            for (int i3 = 0; i3 < n; ++i3) {
+            for (int i3 = sub; i3 < n; i3 += S) {
                 float s2 = 0.f;
                 for (int i2 = 0; i2 < n; ++i2) {
                     float s1 = 0.f;
@@ -423,11 +516,14 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                 }
                 s += l[2][i3] * s2;
             }
-#pragma unroll
-            for (int cc2 = 0; cc2 < RC; ++cc2)
-                if (cc2 == c) acc[cc2] += s;
+            acc[c] += s;
         }
     }
+    for (int msk = 1; msk < S; msk <<= 1) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] += __shfl_xor(acc[c], msk, 64);
+    }
+    if (!valid || sub != 0) return;
     float *out = phi + int64_t(perm[i]) * r + rhs0;
 #pragma unroll
     for (int c = 0; c < RC; ++c)
@@ -507,15 +603,24 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
         p->tiles.alloc(tl.size());
         BB_HIP(hipMemcpy(p->tiles.p, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    // P2P work items: (leaf, first target) per 64 targets
+    // P2P work items (leaf, first target, log2 S): leaves of at most 64
+    // points take one wave with 64 / next_pow2(count) sub-lanes per target
     {
         const LevelData &leaf = t->lv[L];
         std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
         BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
         BB_HIP(hipMemcpy(he.data(), leaf.pe.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
-        for (int a = 0; a < leaf.C; ++a)
-            for (int s = hb[a]; s < he[a]; s += 64) { w.push_back(a); w.push_back(s); }
-        p->nwork = int(w.size() / 2);
+        for (int a = 0; a < leaf.C; ++a) {
+            const int cnt = he[a] - hb[a];
+            int lgT = 0;
+            while ((1 << lgT) < std::min(cnt, 64)) ++lgT;
+            for (int s = hb[a]; s < he[a]; s += (1 << lgT)) {
+                w.push_back(a);
+                w.push_back(s);
+                w.push_back(6 - lgT);
+            }
+        }
+        p->nwork = int(w.size() / 3);
         p->work.alloc(w.size());
         BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
