@@ -187,6 +187,7 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
         ops->tree = t;
         ops->n = t->params.cheb_order;
         ops->m = ops->n * ops->n * ops->n;
+        ops->mp = int(ceil_div(ops->m, 16) * 16);
         ops->precision = precision;
         cheb_setup(ops.get(), s);
         const int L = t->leaf_level();
@@ -207,7 +208,7 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
                              hipMemcpyHostToDevice));
             offUV += m * k;
             offC += int64_t(kNumT) * k * k;
-            finalize_opset(*set, int(m), s);
+            finalize_opset(*set, int(m), ops->mp, s);
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0;
             ops->sets.push_back(std::move(set));

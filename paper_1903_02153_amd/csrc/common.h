@@ -142,8 +142,8 @@ struct OpSet {
     int k = 0, kp = 0;               // rank and rank padded for MFMA tiles
     DBuf<double> U64, V64, C64;      // m x k, m x k, 316 x k x k
     DBuf<double> sv_fat, sv_thin;    // m each (empty when imported / eps = 0)
-    DBuf<float> UT32;                // kp x m: U^T, zero rows past k (decompression)
-    DBuf<float> V32;                 // m x kp: V, zero columns past k (compression)
+    DBuf<float> U32;                 // mp x kp: U, zero past (m, k)   (decompression)
+    DBuf<float> VT32;                // kp x mp: V^T, zero past (k, m) (compression)
     DBuf<float> C32;                 // 316 x kp x kp (zero-padded)
 };
 
@@ -156,7 +156,7 @@ struct OpsLevel {
 
 struct bbfmm_ops {
     const bbfmm_tree *tree = nullptr;
-    int n = 0, m = 0;
+    int n = 0, m = 0, mp = 0;        // order, n^3, n^3 padded to a multiple of 16
     int precision = 0;
     double eps = 0.0;
     bbfmm::ChebConst cheb{};
@@ -171,7 +171,7 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
                             hipStream_t s);
 bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s);
 void cheb_setup(bbfmm_ops *ops, hipStream_t s);
-void finalize_opset(OpSet &set, int m, hipStream_t s);
+void finalize_opset(OpSet &set, int m, int mp, hipStream_t s);
 
 struct Plan;
 Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r);

@@ -108,121 +108,248 @@ k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, float 
     sig_s[g] = sigma[int64_t(perm[i]) * r + c];
 }
 
-// --------------------------------------------------------------- P2M ----
-// grid (leaves, rhs chunks of rc); M = S^T sigma, Mh = V^T M.
-__global__ void __launch_bounds__(kThreads)
+// ----------------------------------------------------- up / down ----
+// Node rows are padded from m = n^3 to mp (a multiple of 16) with zeros so
+// that the compression GEMMs can read them with 16-byte loads.  All up /
+// down interpolation kernels are one wave per (cell, right-hand side) and
+// are compiled per order N, so node index arithmetic is by constants.
+
+template <int N>
+struct NodeIdx {
+    static constexpr int m = N * N * N;
+    static constexpr int Q = (m + 63) / 64;     // node slots per lane
+};
+
+// P2M: M[leaf][c][i] = sum_p L_i(xi_p) sigma_p[c]   (grid: leaves x r)
+template <int N>
+__global__ void __launch_bounds__(64)
 k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int r, int rc,
-      const float *V32, int kp, float *M, float *Mh) {
-    __shared__ float acc[kLdsFloats];
-    __shared__ float lv[64][3][kMaxOrder];
-    __shared__ float sg[64][16];
-    const int a = blockIdx.x, rhs0 = blockIdx.y * rc;
-    const int nr = min(rc, r - rhs0);
-    const int n = cc.n, m = n * n * n, tot = nr * m;
-    const int tid = threadIdx.x;
+      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int r, int mp, float *M) {
+    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
+    __shared__ float lv[64][3][N];
+    __shared__ float sg[64];
+    const int lane = threadIdx.x;
+    const int a = blockIdx.x, c = blockIdx.y;
     const uint64_t key = keys[a];
     float chi[3], clo[3];
     for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
-    for (int idx = tid; idx < tot; idx += kThreads) acc[idx] = 0.f;
+    float acc[Q];
+    int i1[Q], i2[Q], i3[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+        acc[q] = 0.f;
+        i1[q] = i % N;
+        i2[q] = (i / N) % N;
+        i3[q] = (i / (N * N)) % N;
+    }
     const int b = pb[a], e = pe[a];
     for (int p0 = b; p0 < e; p0 += 64) {
         const int np = min(64, e - p0);
         __syncthreads();
-        if (tid < 3 * np) {
-            const int p = tid / 3, d = tid % 3;
-            const float x = (d == 0 ? xs : d == 1 ? ys : zs)[p0 + p];
-            float l[kMaxOrder];
-            lagrange(cc, local_coord(x, chi[d], clo[d], geo.inv_h), l);
-            for (int q = 0; q < n; ++q) lv[p][d][q] = l[q];
+        if (lane < np) {
+            const float p[3] = {xs[p0 + lane], ys[p0 + lane], zs[p0 + lane]};
+            for (int d = 0; d < 3; ++d) {
+                float l[kMaxOrder];
+                lagrange(cc, local_coord(p[d], chi[d], clo[d], geo.inv_h), l);
+#pragma unroll
+                for (int k = 0; k < N; ++k) lv[lane][d][k] = l[k];
+            }
+            sg[lane] = sig_s[int64_t(p0 + lane) * r + c];
         }
-        for (int idx = tid; idx < np * nr; idx += kThreads)
-            sg[idx / nr][idx % nr] = sig_s[int64_t(p0 + idx / nr) * r + rhs0 + idx % nr];
         __syncthreads();
-        for (int idx = tid; idx < tot; idx += kThreads) {
-            const int c = idx / m, i = idx % m;
-            const int i1 = i % n, i2 = (i / n) % n, i3 = i / (n * n);
-            float s = acc[idx];
-            for (int p = 0; p < np; ++p) s += lv[p][0][i1] * lv[p][1][i2] * lv[p][2][i3] * sg[p][c];
-            acc[idx] = s;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (lane + 64 * q < m) {
+                float s = acc[q];
+                for (int pp = 0; pp < np; ++pp)
+                    s += lv[pp][0][i1[q]] * lv[pp][1][i2[q]] * lv[pp][2][i3[q]] * sg[pp];
+                acc[q] = s;
+            }
+        }
+    }
+    float *out = M + (int64_t(a) * r + c) * mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + 64 * q < m) out[lane + 64 * q] = acc[q];
+    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
+}
+
+// One child -> parent translation (trans = false) or parent -> child
+// (trans = true) of an n^3 block held in LDS `A`, as three n x n mode
+// products; the result is returned in registers (node slots of the lane).
+template <int N>
+__device__ inline void mode3(float *A, float *B, const float (*Ts)[N][N], int o, bool trans,
+                             const int *i1, const int *i2, const int *i3, float *out) {
+    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
+    const int lane = threadIdx.x;
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (lane + 64 * q < m) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                s += (trans ? Ts[ox][j][i1[q]] : Ts[ox][i1[q]][j]) * A[(i3[q] * N + i2[q]) * N + j];
+            B[lane + 64 * q] = s;
         }
     }
     __syncthreads();
-    float *Mo = M + (int64_t(a) * r + rhs0) * m;
-    for (int idx = tid; idx < tot; idx += kThreads) Mo[idx] = acc[idx];
-    float *Mho = Mh + (int64_t(a) * r + rhs0) * kp;
-    for (int idx = tid; idx < nr * kp; idx += kThreads) {
-        const int c = idx / kp, kk = idx % kp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (lane + 64 * q < m) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                s += (trans ? Ts[oy][j][i2[q]] : Ts[oy][i2[q]][j]) * B[(i3[q] * N + j) * N + i1[q]];
+            A[lane + 64 * q] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
         float s = 0.f;
-        for (int i = 0; i < m; ++i) s += V32[int64_t(i) * kp + kk] * acc[c * m + i];
-        Mho[idx] = s;
+        if (lane + 64 * q < m) {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                s += (trans ? Ts[oz][j][i3[q]] : Ts[oz][i3[q]][j]) * A[(j * N + i2[q]) * N + i1[q]];
+        }
+        out[q] = s;
     }
 }
 
-// Three mode products of an n x n x n block per rhs, in LDS:
-// B[c][i3][i2][i1] = sum_j T(ox,i1,j1) T(oy,i2,j2) T(oz,i3,j3) A[c][j3][j2][j1],
-// with T(o,i,j) = Ts[o][i][j] (trans = false) or Ts[o][j][i].  A is clobbered.
-__device__ inline void mode3(float *A, float *B, int nr, int n, const float (*Ts)[kMaxOrder][kMaxOrder],
-                             int ox, int oy, int oz, bool trans) {
-    const int m = n * n * n, tot = nr * m;
-    auto T = [&](int o, int i, int j) { return trans ? Ts[o][j][i] : Ts[o][i][j]; };
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx / m, i = idx % m;
-        const int i1 = i % n, rest = i - i1;
-        float s = 0.f;
-        for (int j = 0; j < n; ++j) s += T(ox, i1, j) * A[c * m + rest + j];
-        B[idx] = s;
+template <int N>
+__device__ inline void load_T(const ChebConst &cc, float (*Ts)[N][N]) {
+    for (int e = threadIdx.x; e < 2 * N * N; e += 64) {
+        const int o = e / (N * N), i = (e / N) % N, j = e % N;
+        Ts[o][i][j] = cc.T[o][i][j];
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx / m, i = idx % m;
-        const int i1 = i % n, i2 = (i / n) % n, i3 = i / (n * n);
-        float s = 0.f;
-        for (int j = 0; j < n; ++j) s += T(oy, i2, j) * B[c * m + i3 * n * n + j * n + i1];
-        A[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx / m, i = idx % m;
-        const int i12 = i % (n * n), i3 = i / (n * n);
-        float s = 0.f;
-        for (int j = 0; j < n; ++j) s += T(oz, i3, j) * A[c * m + j * n * n + i12];
-        B[idx] = s;
-    }
-    __syncthreads();
 }
 
-// --------------------------------------------------------------- M2M ----
-// grid (parents on level l, rhs chunks)
-__global__ void __launch_bounds__(kThreads)
+// M2M: M[P][c] = sum over children of (T (x) T (x) T) M[child][c]   (grid: parents x r)
+template <int N>
+__global__ void __launch_bounds__(64)
 k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Mc, ChebConst cc,
-      int r, int rc, const float *V32, int kp, float *M, float *Mh) {
-    __shared__ float acc[kLdsFloats], bufA[kLdsFloats], bufB[kLdsFloats];
-    __shared__ float Ts[2][kMaxOrder][kMaxOrder];
-    const int P = blockIdx.x, rhs0 = blockIdx.y * rc;
-    const int nr = min(rc, r - rhs0);
-    const int n = cc.n, m = n * n * n, tot = nr * m;
-    const int tid = threadIdx.x;
-    if (tid < 2 * kMaxOrder * kMaxOrder) (&Ts[0][0][0])[tid] = (&cc.T[0][0][0])[tid];
-    for (int idx = tid; idx < tot; idx += kThreads) acc[idx] = 0.f;
+      int r, int mp, float *M) {
+    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
+    __shared__ float Ts[2][N][N];
+    __shared__ float A[64 * Q], B[64 * Q];
+    const int lane = threadIdx.x;
+    const int P = blockIdx.x, c = blockIdx.y;
+    load_T<N>(cc, Ts);
+    float acc[Q], t[Q];
+    int i1[Q], i2[Q], i3[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+        acc[q] = 0.f;
+        i1[q] = i % N;
+        i2[q] = (i / N) % N;
+        i3[q] = (i / (N * N)) % N;
+    }
     for (int ch = cb[P]; ch < ce[P]; ++ch) {
         const int o = int(ckeys[ch] & 7);
+        const float *src = Mc + (int64_t(ch) * r + c) * mp;
         __syncthreads();
-        const float *src = Mc + (int64_t(ch) * r + rhs0) * m;
-        for (int idx = tid; idx < tot; idx += kThreads) bufA[idx] = src[idx];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (lane + 64 * q < m) A[lane + 64 * q] = src[lane + 64 * q];
         __syncthreads();
-        mode3(bufA, bufB, nr, n, Ts, o & 1, (o >> 1) & 1, (o >> 2) & 1, false);
-        for (int idx = tid; idx < tot; idx += kThreads) acc[idx] += bufB[idx];
+        mode3<N>(A, B, Ts, o, false, i1, i2, i3, t);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] += t[q];
     }
+    float *out = M + (int64_t(P) * r + c) * mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + 64 * q < m) out[lane + 64 * q] = acc[q];
+    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
+}
+
+// L2L: F[cell][c] = (T^T (x) T^T (x) T^T) F[parent][c]   (grid: cells x r)
+template <int N>
+__global__ void __launch_bounds__(64)
+k_l2l(const int32_t *parent, const uint64_t *keys, const float *Fp, ChebConst cc, int r, int mp,
+      float *F) {
+    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
+    __shared__ float Ts[2][N][N];
+    __shared__ float A[64 * Q], B[64 * Q];
+    const int lane = threadIdx.x;
+    const int a = blockIdx.x, c = blockIdx.y;
+    load_T<N>(cc, Ts);
+    int i1[Q], i2[Q], i3[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+        i1[q] = i % N;
+        i2[q] = (i / N) % N;
+        i3[q] = (i / (N * N)) % N;
+    }
+    const float *src = Fp + (int64_t(parent[a]) * r + c) * mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + 64 * q < m) A[lane + 64 * q] = src[lane + 64 * q];
     __syncthreads();
-    float *Mo = M + (int64_t(P) * r + rhs0) * m;
-    for (int idx = tid; idx < tot; idx += kThreads) Mo[idx] = acc[idx];
-    float *Mho = Mh + (int64_t(P) * r + rhs0) * kp;
-    for (int idx = tid; idx < nr * kp; idx += kThreads) {
-        const int c = idx / kp, kk = idx % kp;
-        float s = 0.f;
-        for (int i = 0; i < m; ++i) s += V32[int64_t(i) * kp + kk] * acc[c * m + i];
-        Mho[idx] = s;
+    float t[Q];
+    mode3<N>(A, B, Ts, int(keys[a] & 7), true, i1, i2, i3, t);
+    float *out = F + (int64_t(a) * r + c) * mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + 64 * q < m) out[lane + 64 * q] = t[q];
+    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
+}
+
+// Y[R][N] = alpha X[R][K] Bt[N][K]^T + beta Y with FP32 MFMA 16x16x4; K a
+// multiple of 16 and both operands zero beyond the true K.  A wave owns 16
+// rows x 64 columns; operands are read straight from global memory with
+// 16-byte loads along K (same permuted-K trick as the M2L kernel).
+// Compression: Mh = M VT^T;  decompression: F = scale Fh U^T (+ F).
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nt(const float *X, int64_t ldx, const float *Bt, int64_t ldb, float *Y, int64_t ldy,
+          int64_t R, int Ncol, int K, float alpha, float beta) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+    const int col0 = blockIdx.y * 64;
+    const int64_t arow = row0 + (lane & 15);
+    const float *xa = X + arow * ldx + 4 * (lane >> 4);
+    const float *bb[4];
+    bool bok[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int bc = col0 + cb * 16 + (lane & 15);
+        bok[cb] = bc < Ncol;
+        bb[cb] = Bt + int64_t(bok[cb] ? bc : 0) * ldb + 4 * (lane >> 4);
+    }
+    const bool aok = arow < R;
+    v4f acc[4];
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const float4 a4 = aok ? *reinterpret_cast<const float4 *>(xa + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 b4[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+            b4[cb] = bok[cb] ? *reinterpret_cast<const float4 *>(bb[cb] + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4[cb].x, acc[cb], 0, 0, 0);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4[cb].y, acc[cb], 0, 0, 0);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4[cb].z, acc[cb], 0, 0, 0);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4[cb].w, acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        if (!bok[cb]) continue;
+        const int col = col0 + cb * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = row0 + 4 * (lane >> 4) + v;
+            if (row < R) {
+                float *y = Y + row * ldy + col;
+                *y = alpha * acc[cb][v] + (beta != 0.f ? beta * *y : 0.f);
+            }
+        }
     }
 }
 
@@ -410,41 +537,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     }
 }
 
-// -------------------------------------------------------------- down ----
-// grid (cells on level l, rhs chunks): F = scale U Fh (+ L2L of the parent F)
-__global__ void __launch_bounds__(kThreads)
-k_down(const float *Fh, const float *UT32, int kp, float scale, const int32_t *parent,
-       const uint64_t *keys, const float *Fp, ChebConst cc, int r, int rc, float *F) {
-    __shared__ float acc[kLdsFloats], bufA[kLdsFloats], bufB[kLdsFloats];
-    __shared__ float Ts[2][kMaxOrder][kMaxOrder];
-    const int a = blockIdx.x, rhs0 = blockIdx.y * rc;
-    const int nr = min(rc, r - rhs0);
-    const int n = cc.n, m = n * n * n, tot = nr * m;
-    const int tid = threadIdx.x;
-    if (tid < 2 * kMaxOrder * kMaxOrder) (&Ts[0][0][0])[tid] = (&cc.T[0][0][0])[tid];
-    const float *fh = Fh + (int64_t(a) * r + rhs0) * kp;
-    for (int idx = tid; idx < nr * kp; idx += kThreads) bufA[idx] = fh[idx];
-    __syncthreads();
-    for (int idx = tid; idx < tot; idx += kThreads) {
-        const int c = idx / m, i = idx % m;
-        float s = 0.f;
-        for (int kk = 0; kk < kp; ++kk) s += UT32[int64_t(kk) * m + i] * bufA[c * kp + kk];
-        acc[idx] = scale * s;
-    }
-    if (Fp != nullptr) {
-        const int P = parent[a];
-        const int o = int(keys[a] & 7);
-        __syncthreads();
-        const float *src = Fp + (int64_t(P) * r + rhs0) * m;
-        for (int idx = tid; idx < tot; idx += kThreads) bufA[idx] = src[idx];
-        __syncthreads();
-        mode3(bufA, bufB, nr, n, Ts, o & 1, (o >> 1) & 1, (o >> 2) & 1, true);
-        for (int idx = tid; idx < tot; idx += kThreads) acc[idx] += bufB[idx];
-    }
-    float *Fo = F + (int64_t(a) * r + rhs0) * m;
-    for (int idx = tid; idx < tot; idx += kThreads) Fo[idx] = acc[idx];
-}
-
 // --------------------------------------------------------- L2P + P2P ----
 // One wave per work item (leaf a, first target t0, log2 S): the wave holds
 // T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes")
@@ -456,7 +548,7 @@ __global__ void __launch_bounds__(64)
 k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
       const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
       const int32_t *work, const float *sig_s, int r, float ia, float ia2, const float *FL,
-      Geo geo, ChebConst cc, float *phi) {
+      int mp, Geo geo, ChebConst cc, float *phi) {
     __shared__ float sx[64], sy[64], sz[64], ss[64][RC];
     const int lane = threadIdx.x;
     const int a = work[3 * blockIdx.x], t0 = work[3 * blockIdx.x + 1];
@@ -493,7 +585,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         }
     }
     if (FL != nullptr && valid) {
-        const int n = cc.n, m = n * n * n;
+        const int n = cc.n;
         const uint64_t key = keys[a];
         float l[3][kMaxOrder];
         const float p[3] = {x, y, z};
@@ -505,7 +597,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
             if (c >= nr) break;
-            const float *f = FL + (int64_t(a) * r + rhs0 + c) * m;
+            const float *f = FL + (int64_t(a) * r + rhs0 + c) * mp;
             float s = 0.f;
             for (int i3 = sub; i3 < n; i3 += S) {
                 float s2 = 0.f;
@@ -541,7 +633,6 @@ struct Plan {
     const bbfmm_tree *tree = nullptr;
     const bbfmm_ops *ops = nullptr;
     int64_t r = 0;
-    int rc_up = 1;                      // rhs chunk of the up / down kernels
     int rc_m2l = 1, tpt = 64;           // M2L column tile: tpt targets x rc_m2l rhs
     int rc_p2p = 1;
     DBuf<float> sig_s;
@@ -571,8 +662,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
     p->ops = o;
     p->r = r;
     const int L = t->leaf_level();
-    const int m = o->m;
-    p->rc_up = int(std::max<int64_t>(1, std::min<int64_t>(r, kLdsFloats / std::max(m, 512))));
+    const int mp = o->mp;
     p->rc_m2l = int(std::min<int64_t>(r, kM2LCols));
     p->tpt = kM2LCols / p->rc_m2l;
     p->rc_p2p = 1;
@@ -584,8 +674,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
         const int64_t C = t->lv[lvl].C;
         const int kp = o->lv[lvl].set->kp;
         p->max_kp = std::max(p->max_kp, kp);
-        p->M[lvl].alloc(C * r * m);
-        p->F[lvl].alloc(C * r * m);
+        p->M[lvl].alloc(C * r * mp);
+        p->F[lvl].alloc(C * r * mp);
         p->Mh[lvl].alloc(C * r * kp);
         p->Fh[lvl].alloc(C * r * kp);
         ws += p->M[lvl].bytes() + p->F[lvl].bytes() + p->Mh[lvl].bytes() + p->Fh[lvl].bytes();
@@ -659,8 +749,8 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
 #define BB_P2P(RCV)                                                                          \
     k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
                                      t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p,         \
-                                     p.work.p, p.sig_s.p, int(p.r), ia, ia2, FL, geo,         \
-                                     p.ops->cheb, phi)
+                                     p.work.p, p.sig_s.p, int(p.r), ia, ia2, FL, p.ops->mp,   \
+                                     geo, p.ops->cheb, phi)
     switch (p.rc_p2p) {
     case 1: BB_P2P(1); break;
     case 2: BB_P2P(2); break;
@@ -727,24 +817,40 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     k_gather_sigma<<<grid(t.n * r), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.sig_s.p);
     BB_LAUNCH_CHECK();
     const float *FL = nullptr;
-    const unsigned rchunks = unsigned(ceil_div(r, p.rc_up));
+    const int n = o.n, mp = o.mp;
     mark(BBFMM_STAGE_P2M);
     if (L >= 2) {
         const LevelData &leaf = t.lv[L];
-        const OpSet &set = *o.lv[L].set;
-        k_p2m<<<dim3(leaf.C, rchunks), kThreads, 0, s>>>(
-            t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, leaf.keys.p, geo, o.cheb, p.sig_s.p, r,
-            p.rc_up, set.V32.p, set.kp, p.M[L].p, p.Mh[L].p);
+        dim3 g(leaf.C, r);
+        switch (n) {
+#define BB_P2M(NN) case NN: k_p2m<NN><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, \
+            leaf.keys.p, geo, o.cheb, p.sig_s.p, r, mp, p.M[L].p); break;
+        BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
+#undef BB_P2M
+        }
         BB_LAUNCH_CHECK();
     }
+    auto compress = [&](int lvl) {
+        const OpSet &set = *o.lv[lvl].set;
+        const int64_t R = int64_t(t.lv[lvl].C) * r;
+        dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(set.kp, 64)));
+        k_gemm_nt<<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, set.VT32.p, mp, p.Mh[lvl].p, set.kp, R,
+                                         set.kp, mp, 1.f, 0.f);
+        BB_LAUNCH_CHECK();
+    };
+    if (L >= 2) compress(L);
     mark(BBFMM_STAGE_M2M);
     for (int lvl = L - 1; lvl >= 2; --lvl) {
         const LevelData &lv = t.lv[lvl], &ch = t.lv[lvl + 1];
-        const OpSet &set = *o.lv[lvl].set;
-        k_m2m<<<dim3(lv.C, rchunks), kThreads, 0, s>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p,
-                                                       o.cheb, r, p.rc_up, set.V32.p, set.kp,
-                                                       p.M[lvl].p, p.Mh[lvl].p);
+        dim3 g(lv.C, r);
+        switch (n) {
+#define BB_M2M(NN) case NN: k_m2m<NN><<<g, 64, 0, s>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p, \
+            o.cheb, r, mp, p.M[lvl].p); break;
+        BB_M2M(2) BB_M2M(3) BB_M2M(4) BB_M2M(5) BB_M2M(6) BB_M2M(7) BB_M2M(8)
+#undef BB_M2M
+        }
         BB_LAUNCH_CHECK();
+        compress(lvl);
     }
     mark(BBFMM_STAGE_M2L);
     if (L >= 2) {
@@ -767,9 +873,21 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     for (int lvl = 2; lvl <= L; ++lvl) {
         const LevelData &lv = t.lv[lvl];
         const OpSet &set = *o.lv[lvl].set;
-        k_down<<<dim3(lv.C, rchunks), kThreads, 0, s>>>(
-            p.Fh[lvl].p, set.UT32.p, set.kp, float(o.lv[lvl].scale), lv.parent.p, lv.keys.p,
-            lvl > 2 ? p.F[lvl - 1].p : nullptr, o.cheb, r, p.rc_up, p.F[lvl].p);
+        if (lvl > 2) {
+            dim3 g(lv.C, r);
+            switch (n) {
+#define BB_L2L(NN) case NN: k_l2l<NN><<<g, 64, 0, s>>>(lv.parent.p, lv.keys.p, p.F[lvl - 1].p, \
+                o.cheb, r, mp, p.F[lvl].p); break;
+            BB_L2L(2) BB_L2L(3) BB_L2L(4) BB_L2L(5) BB_L2L(6) BB_L2L(7) BB_L2L(8)
+#undef BB_L2L
+            }
+            BB_LAUNCH_CHECK();
+        }
+        const int64_t R = int64_t(lv.C) * r;
+        dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
+        k_gemm_nt<<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, set.U32.p, set.kp, p.F[lvl].p, mp,
+                                         R, mp, set.kp, float(o.lv[lvl].scale),
+                                         lvl > 2 ? 1.f : 0.f);
         BB_LAUNCH_CHECK();
     }
     if (L >= 2) FL = p.F[L].p;

@@ -266,13 +266,13 @@ k_cast_pad(const double *src, int rows, int cols, int pad_rows, int pad_cols, in
     dst[g] = (i < rows && j < cols) ? float(src[b * rows * cols + int64_t(i) * cols + j]) : 0.f;
 }
 
-// dst[kk][i] = src[i][kk] (src m x k), zero rows kk >= k
+// dst[kk][i] = src[i][kk] (src m x k) as a kp x mp array, zero outside
 __global__ void __launch_bounds__(kThreads)
-k_cast_pad_t(const double *src, int m, int k, int kp, float *dst) {
+k_cast_pad_t(const double *src, int m, int k, int mp, int kp, float *dst) {
     const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (g >= int64_t(kp) * m) return;
-    const int kk = int(g / m), i = int(g % m);
-    dst[g] = kk < k ? float(src[int64_t(i) * k + kk]) : 0.f;
+    if (g >= int64_t(kp) * mp) return;
+    const int kk = int(g / mp), i = int(g % mp);
+    dst[g] = (kk < k && i < m) ? float(src[int64_t(i) * k + kk]) : 0.f;
 }
 
 inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
@@ -360,16 +360,16 @@ void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, hipStream_t s)
 
 }  // namespace
 
-void finalize_opset(OpSet &set, int m, hipStream_t s) {
+void finalize_opset(OpSet &set, int m, int mp, hipStream_t s) {
     const int k = set.k;
     set.kp = pad16(k);
-    set.UT32.alloc(int64_t(m) * set.kp);
-    set.V32.alloc(int64_t(m) * set.kp);
+    set.U32.alloc(int64_t(mp) * set.kp);
+    set.VT32.alloc(int64_t(set.kp) * mp);
     set.C32.alloc(int64_t(kNumT) * set.kp * set.kp);
-    k_cast_pad_t<<<grid(int64_t(m) * set.kp), kThreads, 0, s>>>(set.U64.p, m, k, set.kp,
-                                                               set.UT32.p);
-    k_cast_pad<<<grid(int64_t(m) * set.kp), kThreads, 0, s>>>(set.V64.p, m, k, m, set.kp, 1,
-                                                             set.V32.p);
+    k_cast_pad<<<grid(int64_t(mp) * set.kp), kThreads, 0, s>>>(set.U64.p, m, k, mp, set.kp, 1,
+                                                              set.U32.p);
+    k_cast_pad_t<<<grid(int64_t(mp) * set.kp), kThreads, 0, s>>>(set.V64.p, m, k, mp, set.kp,
+                                                                set.VT32.p);
     k_cast_pad<<<grid(int64_t(kNumT) * set.kp * set.kp), kThreads, 0, s>>>(
         set.C64.p, k, k, set.kp, set.kp, kNumT, set.C32.p);
     BB_LAUNCH_CHECK();
@@ -407,6 +407,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
     ops->tree = t;
     ops->n = t->params.cheb_order;
     ops->m = ops->n * ops->n * ops->n;
+    ops->mp = int(ceil_div(ops->m, 16) * 16);
     ops->precision = precision;
     ops->eps = eps;
     cheb_setup(ops.get(), s);
@@ -438,7 +439,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
         std::unique_ptr<OpSet> set(new OpSet());
         DBuf<double> K = sample(1.0);
         compress_set(*set, K, m, eps, s);
-        finalize_opset(*set, m, s);
+        finalize_opset(*set, m, ops->mp, s);
         for (int lvl = 2; lvl <= L; ++lvl) {
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0 / t->half_width(lvl);
@@ -449,7 +450,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
             std::unique_ptr<OpSet> set(new OpSet());
             DBuf<double> K = sample(t->half_width(lvl));
             compress_set(*set, K, m, eps, s);
-            finalize_opset(*set, m, s);
+            finalize_opset(*set, m, ops->mp, s);
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0;
             ops->sets.push_back(std::move(set));

@@ -46,6 +46,16 @@ def test_matvec_matches_oracle(nn, seed, kind, kid, prm, n, depth, r, eps):
     assert errs.max() < TOL, errs
 
 
+@pytest.mark.parametrize("n", range(2, 9))
+def test_every_order(n):
+    """Each Chebyshev order has its own compiled up/down kernels."""
+    pts, sig = synth.random_cloud(5000, 30 + n, r=2, kind="clustered")
+    gt, go, ot, oo = _both(pts, sig, 1, 0.3, n, 1e-5, fixed_depth=4)
+    got = gpu_matvec(gt, go, sig)
+    ref = ofmm.matvec(ot, oo, pts, sig, 1, 0.3)
+    assert ofmm.rel_l2_cols(got, ref).max() < TOL
+
+
 @pytest.mark.parametrize("depth", [1, 2])
 def test_p2p_only_is_the_direct_sum(depth):
     pts, sig = synth.random_cloud(2500, 9, r=2)
