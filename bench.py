@@ -74,6 +74,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -150,6 +152,13 @@ def main() -> int:
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+        for _ in range(3):
+            dst = src.clone()
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         plan.execute(sig, phi)

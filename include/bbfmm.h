@@ -213,6 +213,21 @@ bbfmm_status bbfmm_matvec(const bbfmm_tree *tree, const bbfmm_ops *ops,
  */
 bbfmm_status bbfmm_plan_create(const bbfmm_tree *tree, const bbfmm_ops *ops,
                                int64_t r, bbfmm_plan **out);
+
+/* Launch-shape choices of a plan; 0 selects the built-in heuristic. */
+typedef struct {
+    int32_t m2l_split;      /* workgroups sharing one M2L tile's 189 slots, 1..8   */
+    int32_t m2l_min_waves;  /* heuristic target of M2L workgroups per CU, 1..16   */
+    int32_t p2p_max_split;  /* cap on sub-lanes per P2P target, 1..64 (power of 2) */
+    int32_t reserved[5];    /* must be 0                                          */
+} bbfmm_plan_options;
+
+/* plan_create with explicit launch shapes (NULL options = defaults).  The
+ * results do not depend on the options beyond floating-point summation
+ * order.  Errors: INVALID_ARG for out-of-range options. */
+bbfmm_status bbfmm_plan_create_ex(const bbfmm_tree *tree, const bbfmm_ops *ops,
+                                  int64_t r, const bbfmm_plan_options *options,
+                                  bbfmm_plan **out);
 bbfmm_status bbfmm_plan_execute(bbfmm_plan *plan, const float *sigma,
                                 float *phi, void *stream);
 /* Bytes of device workspace the plan holds. */

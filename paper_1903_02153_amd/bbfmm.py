@@ -53,6 +53,11 @@ class TreeInfo(ctypes.Structure):
                 ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64)]
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
+                ("p2p_max_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
 _lib_handle = None
 
 # name -> (restype, argtypes); every symbol of include/bbfmm.h
@@ -68,6 +73,7 @@ SIGNATURES = {
     "bbfmm_ops_import": (_I32, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _PVP]),
     "bbfmm_matvec": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "bbfmm_plan_create": (_I32, [_VP, _VP, _I64, _PVP]),
+    "bbfmm_plan_create_ex": (_I32, [_VP, _VP, _I64, _VP, _PVP]),
     "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
     "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
@@ -191,9 +197,15 @@ class Ops:
 class Plan:
     """Reusable matvec for a fixed (tree, ops, r); owns its workspace."""
 
-    def __init__(self, tree: Tree, ops: Ops, r: int):
+    def __init__(self, tree: Tree, ops: Ops, r: int, **options):
+        """options: m2l_split, m2l_min_waves, p2p_max_split (0 = heuristic)."""
         h = _VP()
-        _check(lib().bbfmm_plan_create(tree.handle, ops.handle, int(r), ctypes.byref(h)))
+        opt = PlanOptions()
+        for k, v in options.items():
+            setattr(opt, k, int(v))
+        _check(lib().bbfmm_plan_create_ex(tree.handle, ops.handle, int(r), ctypes.byref(opt),
+                                          ctypes.byref(h)))
+        self.options = dict(options)
         self._h = h.value
         self.tree, self.ops, self.r = tree, ops, int(r)
         self.n = tree.info().n_points

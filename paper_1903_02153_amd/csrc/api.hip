@@ -217,15 +217,20 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
     });
 }
 
-bbfmm_status bbfmm_plan_create(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
-                               bbfmm_plan **out) {
+bbfmm_status bbfmm_plan_create_ex(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                                  const bbfmm_plan_options *opt, bbfmm_plan **out) {
     return guarded([&] {
         BB_REQUIRE(out != nullptr, "out is NULL");
         *out = nullptr;
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-        p->impl = plan_create_impl(t, o, r);
+        p->impl = plan_create_impl(t, o, r, opt);
         *out = p.release();
     });
+}
+
+bbfmm_status bbfmm_plan_create(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                               bbfmm_plan **out) {
+    return bbfmm_plan_create_ex(t, o, r, nullptr, out);
 }
 
 bbfmm_status bbfmm_plan_execute(bbfmm_plan *p, const float *sigma, float *phi, void *stream) {
@@ -262,7 +267,7 @@ bbfmm_status bbfmm_matvec(const bbfmm_tree *t, const bbfmm_ops *o, const float *
     return guarded([&] {
         hipStream_t s = static_cast<hipStream_t>(stream);
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-        p->impl = plan_create_impl(t, o, r);
+        p->impl = plan_create_impl(t, o, r, nullptr);
         plan_execute_impl(p->impl, sigma, phi, s);
         // the workspace is released only after the stream has consumed it
         BB_HIP(hipStreamSynchronize(s));

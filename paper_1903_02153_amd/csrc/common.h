@@ -174,7 +174,8 @@ void cheb_setup(bbfmm_ops *ops, hipStream_t s);
 void finalize_opset(OpSet &set, int m, int mp, hipStream_t s);
 
 struct Plan;
-Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r);
+Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                       const bbfmm_plan_options *opt);
 void plan_execute_impl(Plan *p, const float *sigma, float *phi, hipStream_t s);
 int64_t plan_workspace_bytes(const Plan *p);
 void plan_destroy(Plan *p);

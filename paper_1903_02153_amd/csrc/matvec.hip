@@ -21,6 +21,8 @@
 //            the neighbour leaves, staged through LDS
 // No atomics on the data path: every output has one owner, so results are
 // bitwise reproducible.
+#include <type_traits>
+
 #include "common.h"
 
 namespace bbfmm {
@@ -299,14 +301,16 @@ k_l2l(const int32_t *parent, const uint64_t *keys, const float *Fp, ChebConst cc
     for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
 }
 
-// Y[R][N] = alpha X[R][K] Bt[N][K]^T + beta Y with FP32 MFMA 16x16x4; K a
+// Y[R][N] = alpha X[R][K] Bt[N][K]^T + beta Y with FP32 MFMA 16x16x4, where
+// X is the sum of nsum arrays xstride floats apart (the partial F^ of a
+// split M2L); K a
 // multiple of 16 and both operands zero beyond the true K.  A wave owns 16
 // rows x 64 columns; operands are read straight from global memory with
 // 16-byte loads along K (same permuted-K trick as the M2L kernel).
 // Compression: Mh = M VT^T;  decompression: F = scale Fh U^T (+ F).
 __global__ void __launch_bounds__(kThreads)
-k_gemm_nt(const float *X, int64_t ldx, const float *Bt, int64_t ldb, float *Y, int64_t ldy,
-          int64_t R, int Ncol, int K, float alpha, float beta) {
+k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *Bt, int64_t ldb,
+          float *Y, int64_t ldy, int64_t R, int Ncol, int K, float alpha, float beta) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
     const int col0 = blockIdx.y * 64;
@@ -324,7 +328,12 @@ k_gemm_nt(const float *X, int64_t ldx, const float *Bt, int64_t ldb, float *Y, i
     v4f acc[4];
     for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 16) {
-        const float4 a4 = aok ? *reinterpret_cast<const float4 *>(xa + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (aok)
+            for (int q = 0; q < nsum; ++q) {   // fixed order: reproducible
+                const float4 v = *reinterpret_cast<const float4 *>(xa + q * xstride + k0);
+                a4.x += v.x; a4.y += v.y; a4.z += v.z; a4.w += v.w;
+            }
         float4 b4[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
@@ -367,11 +376,12 @@ constexpr int kM2LCols = 64;
 
 struct M2LLevel {
     const float *Mh;
-    float *Fh;
+    float *Fh;                  // nsplit partial results, each [C][r][kp]
     const float *C32;
     const int32_t *itab;
     const int32_t *oct_cells;
     int kp;
+    int64_t rows;               // C r: rows of one partial result
 };
 
 struct M2LArgs {
@@ -379,6 +389,7 @@ struct M2LArgs {
     const int32_t *tiles;       // [ntiles][4]: level, octant, first in oct_cells, count
     const int32_t *tables;      // slot_t[8][189] at offset 3 * 316
     int r, rc, tpt;
+    int nsplit;                 // the 189 slots are split over this many workgroups
 };
 
 // Block index -> tile so that each XCD (blocks are dealt round-robin over
@@ -401,9 +412,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     constexpr int ldb = 64 + 4;
     __shared__ float Bs[2][kM2LCols * ldb];
     __shared__ int32_t tgt[kM2LCols], srcs[3][kM2LCols];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[xcd_tile(blockIdx.x, gridDim.x)];
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave-uniform, so that per-wave conditions compile to scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int vb = xcd_tile(blockIdx.x, gridDim.x);
+    const int split = vb % g.nsplit;
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[vb / g.nsplit];
     const M2LLevel &L = g.lv[tile.x];
+    const int jbeg = split * kSlots / g.nsplit, jend = (split + 1) * kSlots / g.nsplit;
     const int o = tile.y, start = tile.z, cnt = tile.w;
     const int kp = L.kp;
     if (int(blockIdx.y) * 64 >= kp) return;       // row group beyond this level's rank
@@ -415,13 +431,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const bool active = row0 < kp;
     const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
     const int nkc = (kp + 63) / 64;
-    const int nsteps = kSlots * nkc;
+    const int nsteps = (jend - jbeg) * nkc;
     (void)lane;
 
     if (tid < kM2LCols) {
         const int a = tid < cnt ? L.oct_cells[start + tid] : -1;
         tgt[tid] = a;
-        for (int q = 0; q < 3; ++q) srcs[q][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
+        for (int q = jbeg; q < min(jbeg + 3, jend); ++q)
+            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
     }
     __syncthreads();
 
@@ -439,16 +456,22 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
         const int c = col - btl[i] * rc;
         boff[i] = (rhs0 + c < r) ? int64_t(rhs0 + c) * kp + 4 * bq[i] : -1;
     }
+    // Loads are issued unconditionally from clamped in-bounds addresses and
+    // masked afterwards: no branches, so the compiler never has to drain the
+    // prefetches before the MFMAs of the current step.
     auto load_b = [&](int j, int kc, float4 *breg) {
         const int lim = min(64, kp - kc * 64) / 4;   // float4 per column in this chunk
         const int32_t *sj = srcs[j % 3];
+        int sc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sc[i] = sj[btl[i]];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int sc = btl[i] < kM2LCols ? sj[btl[i]] : -1;
-            if (sc >= 0 && boff[i] >= 0 && bq[i] < lim)
-                v = *reinterpret_cast<const float4 *>(Mh + int64_t(sc) * r * kp + boff[i] + kc * 64);
-            breg[i] = v;
+            const bool ok = sc[i] >= 0 && boff[i] >= 0 && bq[i] < lim;
+            const float w = ok ? 1.f : 0.f;      // Mh is finite: 0 * v == 0
+            const float4 v = *reinterpret_cast<const float4 *>(
+                Mh + (ok ? int64_t(sc[i]) * r * kp + boff[i] + kc * 64 : 0));
+            breg[i] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
         }
     };
     auto store_b = [&](int buf, const float4 *breg) {
@@ -458,80 +481,97 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
             *reinterpret_cast<float4 *>(&Bs[buf][(e >> 4) * ldb + 4 * bq[i]]) = breg[i];
         }
     };
-    const float *Arow = L.C32 + int64_t(row0 + (lane & 15)) * kp + 4 * (lane >> 4);
+    // rows past the rank (inactive waves) read row 0 and are masked to zero
+    const float *Arow = L.C32 + int64_t(active ? row0 + (lane & 15) : 0) * kp + 4 * (lane >> 4);
     auto load_a = [&](int j, int kc, float4 *areg) {
         const int nkb = min(64, kp - kc * 64) / 16;
         const float *A = Arow + int64_t(slot_t[j]) * kp * kp + kc * 64;
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-            areg[kb] = (active && kb < nkb) ? *reinterpret_cast<const float4 *>(A + 16 * kb)
-                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int kb = 0; kb < 4; ++kb) {
+            const bool ok = active && kb < nkb;    // wave-uniform
+            const float w = ok ? 1.f : 0.f;        // C32 is finite: 0 * v == 0
+            const float4 v = *reinterpret_cast<const float4 *>(A + (ok ? 16 * kb : 0));
+            areg[kb] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
+        }
     };
 
     v4f acc[4];
     for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
-    float4 breg[4], acur[4], anxt[4];
-    load_b(0, 0, breg);
+    float4 breg[4], a0[4], a1[4];
+    load_b(jbeg, 0, breg);
     store_b(0, breg);
-    load_a(0, 0, acur);
+    load_a(jbeg, 0, a0);
     __syncthreads();
     int32_t itab_next = -1;
-    int j = 0, kc = 0;
-    for (int s = 0; s < nsteps; ++s) {
+    int j = jbeg, kc = 0;
+    // One step: prefetch step s+1 (sources into breg, C_t rows into anxt,
+    // the source index of slot j+3), multiply LDS buffer s%2 by acur, then
+    // publish the prefetch.  Every prefetching step issues the same nine
+    // unconditional loads per thread, so the compiler's wait counts stay
+    // exact and the MFMAs never wait on the loads of the step they overlap.
+    auto step = [&](auto more_c, int s, const float4 *acur, float4 *anxt) {
+        constexpr bool MORE = decltype(more_c)::value;
         int j1 = j, kc1 = kc + 1;
         if (kc1 == nkc) { kc1 = 0; ++j1; }
-        const bool more = s + 1 < nsteps;
-        const bool new_slot = more && kc1 == 0;
-        if (more) {
+        const bool new_slot = MORE && kc1 == 0 && j + 3 < jend;
+        if constexpr (MORE) {
             load_b(j1, kc1, breg);
             load_a(j1, kc1, anxt);
-            if (new_slot && tid < kM2LCols && j + 3 < kSlots) {
-                const int a = tgt[tid];
-                itab_next = a >= 0 ? itab[int64_t(a) * kSlots + j + 3] : -1;
-            }
+            const int a = tgt[tid & 63];
+            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + min(j + 3, kSlots - 1)];
+            itab_next = a >= 0 ? v : -1;
         }
-        if (active) {
-            const int nkb = min(64, kp - kc * 64) / 16;
-            const float *B = Bs[s & 1] + (lane & 15) * ldb + 4 * (lane >> 4);
+        // Straight-line MFMA block: a K chunk shorter than 64 (the tail of a
+        // rank that is not a multiple of 64) multiplies zeros in both
+        // operands, and idle waves (rows past the rank) multiply zero A.
+        const float *B = Bs[s & 1] + (lane & 15) * ldb + 4 * (lane >> 4);
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                if (kb < nkb) {
-                    float4 b4[4];
+        for (int kb = 0; kb < 4; ++kb) {
+            float4 b4[4];
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        b4[cb] = *reinterpret_cast<const float4 *>(B + cb * 16 * ldb + 16 * kb);
-                    // independent accumulators back to back
+            for (int cb = 0; cb < 4; ++cb)
+                b4[cb] = *reinterpret_cast<const float4 *>(B + cb * 16 * ldb + 16 * kb);
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].x, b4[cb].x, acc[cb], 0, 0, 0);
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].x, b4[cb].x, acc[cb], 0, 0, 0);
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].y, b4[cb].y, acc[cb], 0, 0, 0);
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].y, b4[cb].y, acc[cb], 0, 0, 0);
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].z, b4[cb].z, acc[cb], 0, 0, 0);
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].z, b4[cb].z, acc[cb], 0, 0, 0);
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].w, b4[cb].w, acc[cb], 0, 0, 0);
-                }
-            }
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].w, b4[cb].w, acc[cb], 0, 0, 0);
         }
-        if (more) {
+        if constexpr (MORE) {
             store_b((s + 1) & 1, breg);
-            if (new_slot && tid < kM2LCols && j + 3 < kSlots) srcs[j % 3][tid] = itab_next;
+            if (new_slot && tid < kM2LCols) srcs[j % 3][tid] = itab_next;
         }
         __syncthreads();
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acur[kb] = anxt[kb];
         j = j1;
         kc = kc1;
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    int s = 0;
+    for (; s + 2 < nsteps; s += 2) {
+        step(yes{}, s, a0, a1);
+        step(yes{}, s + 1, a1, a0);
+    }
+    if (s + 1 < nsteps) {
+        step(yes{}, s, a0, a1);
+        step(no{}, s + 1, a1, a0);
+    } else {
+        step(no{}, s, a0, a1);
     }
     if (!active) return;
     for (int cb = 0; cb < 4; ++cb) {
         const int col = cb * 16 + (lane & 15);
         const int tl = col / rc, c = col % rc;
         if (tl < cnt && rhs0 + c < r) {
-            float *dst = L.Fh + (int64_t(tgt[tl]) * r + rhs0 + c) * kp + row0 + 4 * (lane >> 4);
+            float *dst = L.Fh + split * L.rows * kp +
+                         (int64_t(tgt[tl]) * r + rhs0 + c) * kp + row0 + 4 * (lane >> 4);
             *reinterpret_cast<float4 *>(dst) = make_float4(acc[cb][0], acc[cb][1], acc[cb][2], acc[cb][3]);
         }
     }
@@ -539,20 +579,48 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
 
 // --------------------------------------------------------- L2P + P2P ----
 // One wave per work item (leaf a, first target t0, log2 S): the wave holds
-// T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes")
-// that stride through the sources staged 64 at a time in LDS, and through
-// the i3 planes of the L2P sum.  The S partial sums of a target are added
-// by a fixed butterfly of cross-lane shuffles, so results are reproducible.
+// T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes").
+// The sources of all neighbour leaves are copied into LDS in as few passes
+// as fit (x, y, z, sigma packed in one 16-byte record, zero-padded to a
+// multiple of 4 S records so the inner loop is uniform and unrolled; padding
+// records have sigma = 0 and a finite kernel value).  Sub-lane s takes
+// records s, s + S, ... and the i3 planes s, s + S, ... of the L2P sum; the
+// S partial sums of a target are added by a fixed butterfly of cross-lane
+// shuffles, so results are reproducible.
+template <int RC>
+struct P2PCap {   // records per LDS pass: a multiple of 64, about 8-17 KB of LDS per wave
+    static constexpr int value = RC == 1 ? 512 : (RC <= 4 ? 256 : (RC <= 16 ? 128 : 64));
+};
+
+template <int KID, int RC, int S>
+__device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? RC - 1 : 1],
+                                   int npad, int sub, float x, float y, float z, float ia,
+                                   float ia2, float *acc) {
+    for (int u = 0; u < npad; u += 4 * S) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int jj = u + v * S + sub;
+            const float4 q = sp[jj];
+            const float k = kernel_eval<KID>(x - q.x, y - q.y, z - q.z, ia, ia2);
+            acc[0] += k * q.w;
+#pragma unroll
+            for (int c = 1; c < RC; ++c) acc[c] += k * ss[jj][c - 1];
+        }
+    }
+}
+
 template <int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
       const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
       const int32_t *work, const float *sig_s, int r, float ia, float ia2, const float *FL,
       int mp, Geo geo, ChebConst cc, float *phi) {
-    __shared__ float sx[64], sy[64], sz[64], ss[64][RC];
+    constexpr int CAP = P2PCap<RC>::value;
+    __shared__ float4 sp[CAP];                        // x, y, z, sigma of the first rhs
+    __shared__ float ss[CAP][RC > 1 ? RC - 1 : 1];    // remaining rhs
     const int lane = threadIdx.x;
     const int a = work[3 * blockIdx.x], t0 = work[3 * blockIdx.x + 1];
-    const int lgS = work[3 * blockIdx.x + 2];
+    const int lgS = min(work[3 * blockIdx.x + 2], 4);   // at most 16 sub-lanes
     const int S = 1 << lgS, sub = lane & (S - 1);
     const int rhs0 = blockIdx.y * RC;
     const int nr = min(RC, r - rhs0);
@@ -562,26 +630,38 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
     float acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0.f;
-    for (int q = nbr_off[a]; q < nbr_off[a + 1]; ++q) {
-        const int b = nbr_idx[q];
-        const int sb = pb[b], se = pe[b];
-        for (int s0 = sb; s0 < se; s0 += 64) {
-            const int ns = min(64, se - s0);
-            __syncthreads();
-            if (lane < ns) {
-                sx[lane] = xs[s0 + lane];
-                sy[lane] = ys[s0 + lane];
-                sz[lane] = zs[s0 + lane];
+    // walk the neighbour list, filling LDS passes of up to CAP records
+    const int q0 = nbr_off[a], q1 = nbr_off[a + 1];
+    int q = q0, off = 0;   // next neighbour and offset within it
+    while (q < q1) {
+        int n = 0;
+        __syncthreads();
+        while (q < q1 && n < CAP) {
+            const int b = nbr_idx[q];
+            const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - n);
+            for (int e = lane; e < cnt; e += 64) {
+                const float *sg = sig_s + int64_t(sb + e) * r + rhs0;
+                sp[n + e] = make_float4(xs[sb + e], ys[sb + e], zs[sb + e], sg[0]);
 #pragma unroll
-                for (int c = 0; c < RC; ++c)
-                    ss[lane][c] = c < nr ? sig_s[int64_t(s0 + lane) * r + rhs0 + c] : 0.f;
+                for (int c = 1; c < RC; ++c) ss[n + e][c - 1] = c < nr ? sg[c] : 0.f;
             }
-            __syncthreads();
-            for (int j = sub; j < ns; j += S) {
-                const float k = kernel_eval<KID>(x - sx[j], y - sy[j], z - sz[j], ia, ia2);
+            n += cnt;
+            if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
+        }
+        // CAP is a multiple of 64 >= 4 S, so the padded count stays within LDS
+        const int npad = min(CAP, (n + 4 * S - 1) / (4 * S) * (4 * S));
+        for (int e = n + lane; e < npad; e += 64) {
+            sp[e] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int c = 0; c < RC; ++c) acc[c] += k * ss[j][c];
-            }
+            for (int c = 1; c < RC; ++c) ss[e][c - 1] = 0.f;
+        }
+        __syncthreads();
+        switch (lgS) {
+        case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+        case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+        case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+        case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+        default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
         }
     }
     if (FL != nullptr && valid) {
@@ -598,7 +678,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         for (int c = 0; c < RC; ++c) {
             if (c >= nr) break;
             const float *f = FL + (int64_t(a) * r + rhs0 + c) * mp;
-            float s = 0.f;
+            float sacc = 0.f;
             for (int i3 = sub; i3 < n; i3 += S) {
                 float s2 = 0.f;
                 for (int i2 = 0; i2 < n; ++i2) {
@@ -606,9 +686,9 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                     for (int i1 = 0; i1 < n; ++i1) s1 += l[0][i1] * f[(i3 * n + i2) * n + i1];
                     s2 += l[1][i2] * s1;
                 }
-                s += l[2][i3] * s2;
+                sacc += l[2][i3] * s2;
             }
-            acc[c] += s;
+            acc[c] += sacc;
         }
     }
     for (int msk = 1; msk < S; msk <<= 1) {
@@ -634,6 +714,7 @@ struct Plan {
     const bbfmm_ops *ops = nullptr;
     int64_t r = 0;
     int rc_m2l = 1, tpt = 64;           // M2L column tile: tpt targets x rc_m2l rhs
+    int nsplit = 1;                     // M2L slot split (partial F^ summed in decompression)
     int rc_p2p = 1;
     DBuf<float> sig_s;
     DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
@@ -653,8 +734,17 @@ struct Plan {
     }
 };
 
-Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
+Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                       const bbfmm_plan_options *opt) {
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
+    bbfmm_plan_options op{};
+    if (opt) op = *opt;
+    BB_REQUIRE(op.m2l_split >= 0 && op.m2l_split <= 8, "m2l_split must be in [0, 8]");
+    BB_REQUIRE(op.m2l_min_waves >= 0 && op.m2l_min_waves <= 16, "m2l_min_waves must be in [0, 16]");
+    BB_REQUIRE(op.p2p_max_split >= 0 && op.p2p_max_split <= 64 &&
+                   (op.p2p_max_split & (op.p2p_max_split - 1)) == 0,
+               "p2p_max_split must be 0 or a power of two <= 64");
+    for (int i = 0; i < 5; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -677,8 +767,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
         p->M[lvl].alloc(C * r * mp);
         p->F[lvl].alloc(C * r * mp);
         p->Mh[lvl].alloc(C * r * kp);
-        p->Fh[lvl].alloc(C * r * kp);
-        ws += p->M[lvl].bytes() + p->F[lvl].bytes() + p->Mh[lvl].bytes() + p->Fh[lvl].bytes();
+        ws += p->M[lvl].bytes() + p->F[lvl].bytes() + p->Mh[lvl].bytes();
         // M2L tiles: runs of up to tpt cells of one octant
         for (int oc = 0; oc < 8; ++oc)
             for (int s = t->lv[lvl].oct_off[oc]; s < t->lv[lvl].oct_off[oc + 1]; s += p->tpt) {
@@ -689,6 +778,19 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
             }
     }
     p->ntiles = int(tl.size() / 4);
+    // split the slots until the launch has about m2l_min_waves workgroups per CU
+    if (op.m2l_split > 0) {
+        p->nsplit = op.m2l_split;
+    } else {
+        const int target = op.m2l_min_waves > 0 ? op.m2l_min_waves : 4;
+        const int64_t wgs = int64_t(p->ntiles) * ceil_div(p->max_kp, 64) * ceil_div(r, p->rc_m2l);
+        while (p->nsplit < 4 && wgs * p->nsplit < int64_t(target) * 256) p->nsplit *= 2;
+    }
+    for (int lvl = 2; lvl <= L; ++lvl) {
+        const int64_t C = t->lv[lvl].C;
+        p->Fh[lvl].alloc(int64_t(p->nsplit) * C * r * o->lv[lvl].set->kp);
+        ws += p->Fh[lvl].bytes();
+    }
     if (p->ntiles) {
         p->tiles.alloc(tl.size());
         BB_HIP(hipMemcpy(p->tiles.p, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -704,6 +806,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r) {
             const int cnt = he[a] - hb[a];
             int lgT = 0;
             while ((1 << lgT) < std::min(cnt, 64)) ++lgT;
+            const int cap = op.p2p_max_split > 0 ? std::min(op.p2p_max_split, 16) : 16;
+            while ((64 >> lgT) > cap) ++lgT;   // at most cap sub-lanes per target
             for (int s = hb[a]; s < he[a]; s += (1 << lgT)) {
                 w.push_back(a);
                 w.push_back(s);
@@ -834,8 +938,8 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
         const OpSet &set = *o.lv[lvl].set;
         const int64_t R = int64_t(t.lv[lvl].C) * r;
         dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(set.kp, 64)));
-        k_gemm_nt<<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, set.VT32.p, mp, p.Mh[lvl].p, set.kp, R,
-                                         set.kp, mp, 1.f, 0.f);
+        k_gemm_nt<<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp, p.Mh[lvl].p,
+                                         set.kp, R, set.kp, mp, 1.f, 0.f);
         BB_LAUNCH_CHECK();
     };
     if (L >= 2) compress(L);
@@ -858,14 +962,15 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
         for (int lvl = 2; lvl <= L; ++lvl) {
             const OpSet &set = *o.lv[lvl].set;
             g.lv[lvl] = M2LLevel{p.Mh[lvl].p, p.Fh[lvl].p, set.C32.p, t.lv[lvl].itab.p,
-                                 t.lv[lvl].oct_cells.p, set.kp};
+                                 t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
         }
         g.tiles = p.tiles.p;
         g.tables = t.tables.p;
         g.r = r;
         g.rc = p.rc_m2l;
         g.tpt = p.tpt;
-        dim3 gr(p.ntiles, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
+        g.nsplit = p.nsplit;
+        dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
         k_m2l<<<gr, kThreads, 0, s>>>(g);
         BB_LAUNCH_CHECK();
     }
@@ -885,9 +990,9 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
         }
         const int64_t R = int64_t(lv.C) * r;
         dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
-        k_gemm_nt<<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, set.U32.p, set.kp, p.F[lvl].p, mp,
-                                         R, mp, set.kp, float(o.lv[lvl].scale),
-                                         lvl > 2 ? 1.f : 0.f);
+        k_gemm_nt<<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp, set.U32.p,
+                                         set.kp, p.F[lvl].p, mp, R, mp, set.kp,
+                                         float(o.lv[lvl].scale), lvl > 2 ? 1.f : 0.f);
         BB_LAUNCH_CHECK();
     }
     if (L >= 2) FL = p.F[L].p;
