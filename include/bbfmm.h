@@ -55,9 +55,14 @@ enum {
                                degree 3 per coordinate, for exactness tests only     */
 };
 
-/* Arithmetic of the M2L contraction (the rest of the matvec is FP32). */
+/* Arithmetic of the M2L contraction (P2P, up/down passes, compression and
+ * decompression stay FP32; the operator precompute is FP64). */
 enum {
-    BBFMM_M2L_FP32 = 0
+    BBFMM_M2L_FP32 = 0,         /* FP32 operands, FP32 MFMA                          */
+    BBFMM_M2L_BF16X3 = 1,       /* operands split x = hi + lo in bf16; products
+                                   hi*hi + hi*lo + lo*hi on bf16 MFMA, FP32 accumulate */
+    BBFMM_M2L_FP16_SCALED = 2   /* fp16 operands with a power-of-two scale per operator
+                                   and per (cell, RHS, 64 ranks) block; FP32 accumulate */
 };
 
 typedef struct {
@@ -254,8 +259,54 @@ enum {
  * executions they cover; reset != 0 clears the totals afterwards.
  */
 bbfmm_status bbfmm_plan_set_timing(bbfmm_plan *plan, int32_t enable);
+
+/*
+ * Graph replay (enable = 1): the first plan_execute captures the whole
+ * launch sequence into a HIP graph on a private stream and every later call
+ * with the same sigma / phi pointers only launches that graph on the given
+ * stream (a new pointer pair is captured again).  The graph contains kernel
+ * nodes only.  Stage timing is not recorded in graph mode.
+ */
+bbfmm_status bbfmm_plan_set_graph(bbfmm_plan *plan, int32_t enable);
 bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *executions,
                                     int32_t reset);
+
+/*
+ * Serving loop (continuous batching).  A server keeps any number of built
+ * (tree, operators) models, accepts matvec requests of any model and r, and
+ * a scheduler thread groups the pending requests of one model (arrival
+ * order, total r <= r_max, rounded up to a power of two) into one product
+ * on one of max_inflight slots; slots run concurrently on their own streams.
+ * A batch is admitted when a slot is free and the device memory held by the
+ * slots (plan workspace + staging) stays within hbm_budget_bytes; idle
+ * slots release cached plans to make room.  A request larger than the
+ * budget on its own fails with BBFMM_ERR_BUDGET (reported by wait).
+ *   sigma, phi  device, N x r float32 (the model's N); must stay valid and
+ *               untouched until wait returns.
+ * Results equal a lone bbfmm_matvec of the request up to floating-point
+ * summation order.  Trees and operators must outlive the server.
+ */
+typedef struct bbfmm_server bbfmm_server;
+typedef struct {
+    double t_submit, t_admit, t_done;   /* steady-clock seconds              */
+    int32_t batch_r;                    /* total r of the batch it ran in    */
+    int32_t slot;                       /* slot (stream) index               */
+} bbfmm_request_stats;
+
+bbfmm_status bbfmm_server_create(int64_t hbm_budget_bytes, int32_t max_inflight,
+                                 int32_t r_max, bbfmm_server **out);
+bbfmm_status bbfmm_server_add(bbfmm_server *server, const bbfmm_tree *tree,
+                              const bbfmm_ops *ops, int32_t *model_id);
+/* Non-blocking; request_id identifies the request for wait. */
+bbfmm_status bbfmm_server_submit(bbfmm_server *server, int32_t model_id,
+                                 const float *sigma, int64_t r, float *phi,
+                                 uint64_t *request_id);
+/* Blocks until the request is complete; stats may be NULL.  Returns the
+ * request's own status (BUDGET, HIP) if it failed.  Each id is waited once. */
+bbfmm_status bbfmm_server_wait(bbfmm_server *server, uint64_t request_id,
+                               bbfmm_request_stats *stats);
+/* Drains in-flight batches and frees the server (NULL accepted). */
+bbfmm_status bbfmm_server_destroy(bbfmm_server *server);
 
 void bbfmm_tree_free(bbfmm_tree *tree);
 void bbfmm_ops_free(bbfmm_ops *ops);

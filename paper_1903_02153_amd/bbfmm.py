@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
 K_INV_R, K_EXP, K_GAUSS, K_POLY_TEST = 0, 1, 2, 100
-M2L_FP32 = 0
+M2L_FP32, M2L_BF16X3, M2L_FP16_SCALED = 0, 1, 2
 
 TA = dict(perm=0, keys=1, pb=2, pe=3, parent=4, cb=5, ce=6, nbr_off=7, nbr_idx=8,
           pair_t=9, pair_tgt=10, pair_src=11, pair_goff=12)
@@ -53,6 +53,12 @@ class TreeInfo(ctypes.Structure):
                 ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64)]
 
 
+class RequestStats(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("batch_r", ctypes.c_int32),
+                ("slot", ctypes.c_int32)]
+
+
 class PlanOptions(ctypes.Structure):
     _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
                 ("p2p_max_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
@@ -77,7 +83,13 @@ SIGNATURES = {
     "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
     "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
+    "bbfmm_plan_set_graph": (_I32, [_VP, _I32]),
     "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+    "bbfmm_server_create": (_I32, [_I64, _I32, _I32, _PVP]),
+    "bbfmm_server_add": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I32)]),
+    "bbfmm_server_submit": (_I32, [_VP, _I32, _VP, _I64, _VP, ctypes.POINTER(ctypes.c_uint64)]),
+    "bbfmm_server_wait": (_I32, [_VP, ctypes.c_uint64, _VP]),
+    "bbfmm_server_destroy": (_I32, [_VP]),
     "bbfmm_tree_free": (None, [_VP]),
     "bbfmm_ops_free": (None, [_VP]),
     "bbfmm_plan_free": (None, [_VP]),
@@ -215,6 +227,10 @@ class Plan:
         _check(lib().bbfmm_plan_workspace_bytes(self._h, ctypes.byref(b)))
         return b.value
 
+    def set_graph(self, enable: bool) -> None:
+        """Replay the captured launch sequence as one HIP graph."""
+        _check(lib().bbfmm_plan_set_graph(self._h, 1 if enable else 0))
+
     def set_timing(self, enable: bool) -> None:
         _check(lib().bbfmm_plan_set_timing(self._h, 1 if enable else 0))
 
@@ -297,3 +313,50 @@ def matvec(tree: Tree, ops: Ops, sigma, phi=None, stream=None):
     _check(lib().bbfmm_matvec(tree.handle, ops.handle, s2.data_ptr(), s2.shape[1],
                               phi.data_ptr(), _stream_handle(stream)))
     return phi.reshape(-1) if squeeze else phi
+
+
+class Server:
+    """Continuous-batching matvec server (see bbfmm_server_* in bbfmm.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8, r_max: int = 64):
+        h = _VP()
+        _check(lib().bbfmm_server_create(int(hbm_budget_bytes), int(max_inflight), int(r_max),
+                                         ctypes.byref(h)))
+        self._h = h.value
+        self._keep = {}          # request id -> (sigma, phi) kept alive until wait
+        self._models = []
+
+    def add(self, tree: Tree, ops: Ops) -> int:
+        mid = _I32(0)
+        _check(lib().bbfmm_server_add(self._h, tree.handle, ops.handle, ctypes.byref(mid)))
+        self._models.append((tree, ops))
+        return mid.value
+
+    def submit(self, model_id: int, sigma, phi) -> int:
+        _device_f32(sigma, "sigma")
+        _device_f32(phi, "phi", tuple(sigma.shape))
+        rid = ctypes.c_uint64(0)
+        _check(lib().bbfmm_server_submit(self._h, int(model_id), sigma.data_ptr(),
+                                         sigma.shape[1], phi.data_ptr(), ctypes.byref(rid)))
+        self._keep[rid.value] = (sigma, phi)
+        return rid.value
+
+    def wait(self, request_id: int) -> dict:
+        st = RequestStats()
+        try:
+            _check(lib().bbfmm_server_wait(self._h, ctypes.c_uint64(request_id), ctypes.byref(st)))
+        finally:
+            self._keep.pop(request_id, None)
+        return {"t_submit": st.t_submit, "t_admit": st.t_admit, "t_done": st.t_done,
+                "batch_r": st.batch_r, "slot": st.slot}
+
+    def close(self):
+        if self._h:
+            _check(lib().bbfmm_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -181,7 +181,9 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
     return guarded([&] {
         BB_REQUIRE(t != nullptr && out != nullptr, "tree / out is NULL");
         *out = nullptr;
-        BB_REQUIRE(precision == BBFMM_M2L_FP32, "unsupported M2L precision %d", precision);
+        BB_REQUIRE(precision == BBFMM_M2L_FP32 || precision == BBFMM_M2L_BF16X3 ||
+                       precision == BBFMM_M2L_FP16_SCALED,
+                   "unsupported M2L precision %d", precision);
         hipStream_t s = static_cast<hipStream_t>(stream);
         std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
         ops->tree = t;
@@ -208,7 +210,7 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
                              hipMemcpyHostToDevice));
             offUV += m * k;
             offC += int64_t(kNumT) * k * k;
-            finalize_opset(*set, int(m), ops->mp, s);
+            finalize_opset(*set, int(m), ops->mp, precision, s);
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0;
             ops->sets.push_back(std::move(set));
@@ -251,6 +253,13 @@ bbfmm_status bbfmm_plan_set_timing(bbfmm_plan *p, int32_t enable) {
     return guarded([&] {
         BB_REQUIRE(p != nullptr, "plan is NULL");
         plan_set_timing(p->impl, enable != 0);
+    });
+}
+
+bbfmm_status bbfmm_plan_set_graph(bbfmm_plan *p, int32_t enable) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr, "plan is NULL");
+        plan_set_graph(p->impl, enable != 0);
     });
 }
 

@@ -144,7 +144,10 @@ struct OpSet {
     DBuf<double> sv_fat, sv_thin;    // m each (empty when imported / eps = 0)
     DBuf<float> U32;                 // mp x kp: U, zero past (m, k)   (decompression)
     DBuf<float> VT32;                // kp x mp: V^T, zero past (k, m) (compression)
-    DBuf<float> C32;                 // 316 x kp x kp (zero-padded)
+    DBuf<float> C32;                 // 316 x kp x kp (zero-padded), FP32 M2L
+    DBuf<uint16_t> Chi, Clo;         // 316 x kp x kp bf16 halves, split-BF16 M2L
+    DBuf<uint16_t> C16;              // 316 x kp x kp fp16 scaled by 2^e_t, FP16 M2L
+    DBuf<float> Cinv;                // 316: 2^-e_t
 };
 
 struct OpsLevel {
@@ -171,7 +174,7 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
                             hipStream_t s);
 bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s);
 void cheb_setup(bbfmm_ops *ops, hipStream_t s);
-void finalize_opset(OpSet &set, int m, int mp, hipStream_t s);
+void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s);
 
 struct Plan;
 Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
@@ -180,6 +183,7 @@ void plan_execute_impl(Plan *p, const float *sigma, float *phi, hipStream_t s);
 int64_t plan_workspace_bytes(const Plan *p);
 void plan_destroy(Plan *p);
 void plan_set_timing(Plan *p, bool on);
+void plan_set_graph(Plan *p, bool on);
 void plan_stage_times(Plan *p, double *ms, int64_t *execs, bool reset);
 
 // --------------------------------------------------------- primitives ----

@@ -308,9 +308,18 @@ k_l2l(const int32_t *parent, const uint64_t *keys, const float *Fp, ChebConst cc
 // rows x 64 columns; operands are read straight from global memory with
 // 16-byte loads along K (same permuted-K trick as the M2L kernel).
 // Compression: Mh = M VT^T;  decompression: F = scale Fh U^T (+ F).
+// Output formats of the compression GEMM (the operand format of the M2L).
+enum { kOutF32 = 0, kOutBF16X3 = 1, kOutF16S = 2 };
+
+__device__ inline uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x)); }
+__device__ inline float from_bf16(uint16_t b) { return static_cast<float>(__builtin_bit_cast(__bf16, b)); }
+__device__ inline uint16_t to_f16(float x) { return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x)); }
+
+template <int OUT>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *Bt, int64_t ldb,
-          float *Y, int64_t ldy, int64_t R, int Ncol, int K, float alpha, float beta) {
+          float *Y, int64_t ldy, int64_t R, int Ncol, int K, float alpha, float beta,
+          uint16_t *Yh, uint16_t *Yl, float *Sinv, int nchunk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
     const int col0 = blockIdx.y * 64;
@@ -347,16 +356,55 @@ k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *B
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4[cb].w, acc[cb], 0, 0, 0);
     }
+    if constexpr (OUT == kOutF32) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        if (!bok[cb]) continue;
-        const int col = col0 + cb * 16 + (lane & 15);
+        for (int cb = 0; cb < 4; ++cb) {
+            if (!bok[cb]) continue;
+            const int col = col0 + cb * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + 4 * (lane >> 4) + v;
+                if (row < R) {
+                    float *y = Y + row * ldy + col;
+                    *y = alpha * acc[cb][v] + (beta != 0.f ? beta * *y : 0.f);
+                }
+            }
+        }
+    } else if constexpr (OUT == kOutBF16X3) {
+        // x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            if (!bok[cb]) continue;
+            const int col = col0 + cb * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + 4 * (lane >> 4) + v;
+                if (row < R) {
+                    const float x = alpha * acc[cb][v];
+                    const uint16_t h = to_bf16(x);
+                    Yh[row * ldy + col] = h;
+                    Yl[row * ldy + col] = to_bf16(x - from_bf16(h));
+                }
+            }
+        }
+    } else {
+        // one power-of-two scale per (row, 64-column chunk): max |x| 2^e in [2^14, 2^15)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+            float mx = 0.f;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) mx = fmaxf(mx, bok[cb] ? fabsf(alpha * acc[cb][v]) : 0.f);
+            for (int msk = 1; msk < 16; msk <<= 1) mx = fmaxf(mx, __shfl_xor(mx, msk, 64));
+            const int e = mx > 0.f ? max(-126, min(126, 14 - ilogbf(mx))) : 0;
             const int64_t row = row0 + 4 * (lane >> 4) + v;
             if (row < R) {
-                float *y = Y + row * ldy + col;
-                *y = alpha * acc[cb][v] + (beta != 0.f ? beta * *y : 0.f);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (!bok[cb]) continue;
+                    const int col = col0 + cb * 16 + (lane & 15);
+                    Yh[row * ldy + col] = to_f16(ldexpf(alpha * acc[cb][v], e));
+                }
+                if ((lane & 15) == 0) Sinv[row * nchunk + blockIdx.y] = ldexpf(1.f, -e);
             }
         }
     }
@@ -577,6 +625,235 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     }
 }
 
+// ----------------------------------------------- M2L, 16-bit operands ----
+// Same tiling, slot split and software pipeline as k_m2l, on the gfx950
+// 16x16x32 MFMAs.  Split-BF16: every operand is stored as hi + lo bf16
+// halves and each product is hi*hi + hi*lo + lo*hi (FP32 accumulate).
+// Scaled FP16: operands are fp16 scaled by powers of two (one per operator,
+// one per source (cell, rhs, 64 ranks) block); each 64-rank chunk is
+// accumulated from zero and folded into the FP32 result with the two
+// inverse scales.  Lane layout of 16x16x32: A[i][k] from lane i + 16 (k/8),
+// element k % 8; B[k][j] likewise; D as in 16x16x4.
+struct M2LLevelLP {
+    const uint16_t *Mh, *Ml;   // bf16 halves, or fp16 data in Mh  [rows][kp]
+    const float *Msinv;        // fp16: inverse scales [rows][nchunk]
+    float *Fh;                 // nsplit partial results [rows][kp]
+    const uint16_t *Ch, *Cl;   // operator halves, or fp16 data in Ch  [316][kp][kp]
+    const float *Cinv;         // fp16: operator inverse scales [316]
+    const int32_t *itab;
+    const int32_t *oct_cells;
+    int kp;
+    int64_t rows;
+};
+
+struct M2LArgsLP {
+    M2LLevelLP lv[kMaxLevels];
+    const int32_t *tiles;
+    const int32_t *tables;
+    int r, rc, tpt;
+    int nsplit;
+};
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+__global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
+    constexpr bool X3 = PREC == BBFMM_M2L_BF16X3;
+    constexpr int ldb = 64 + 8;                 // 144-byte rows: conflict-free 16-byte reads
+    constexpr int NB = X3 ? 4 : 2;              // 16-byte source loads per thread per step
+    constexpr int NA = X3 ? 4 : 2;              // 16-byte operator loads per lane per step
+    __shared__ uint4 Bstore[2][X3 ? 2 : 1][kM2LCols * ldb / 8];
+    __shared__ float Bsc[2][kM2LCols];
+    __shared__ int32_t tgt[kM2LCols], srcs[3][kM2LCols];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int vb = xcd_tile(blockIdx.x, gridDim.x);
+    const int split = vb % g.nsplit;
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[vb / g.nsplit];
+    const M2LLevelLP &L = g.lv[tile.x];
+    const int jbeg = split * kSlots / g.nsplit, jend = (split + 1) * kSlots / g.nsplit;
+    const int o = tile.y, start = tile.z, cnt = tile.w;
+    const int kp = L.kp;
+    if (int(blockIdx.y) * 64 >= kp) return;
+    const int32_t *itab = L.itab;
+    const int r = g.r, rc = g.rc;
+    const int rhs0 = blockIdx.z * rc;
+    const int row0 = blockIdx.y * 64 + wave * 16;
+    const bool active = row0 < kp;
+    const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
+    const int nkc = (kp + 63) / 64;
+    const int nsteps = (jend - jbeg) * nkc;
+
+    if (tid < kM2LCols) {
+        const int a = tid < cnt ? L.oct_cells[start + tid] : -1;
+        tgt[tid] = a;
+        for (int q = jbeg; q < min(jbeg + 3, jend); ++q)
+            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
+    }
+    __syncthreads();
+
+    // source element e = tid + 256 i: column e / (2 NB), 16-byte piece e % (2 NB)
+    // (X3: pieces 0..7 are hi, 8..15 lo; fp16: pieces 0..7)
+    constexpr int PPC = X3 ? 16 : 8;            // pieces per column
+    int bpart[NB], bsub[NB], btl[NB], bcol[NB];
+    int64_t boff[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int e = tid + i * kThreads;
+        const int col = e / PPC, q = e % PPC;
+        bcol[i] = col;
+        bpart[i] = q >> 3;
+        bsub[i] = q & 7;
+        btl[i] = col / rc;
+        const int c = col - btl[i] * rc;
+        boff[i] = (rhs0 + c < r) ? int64_t(rhs0 + c) * kp + 8 * bsub[i] : -1;
+    }
+    // per-column scale of the staged chunk (fp16): column tid & 63
+    const int scol = tid & 63, stl = scol / rc, sc_c = scol - (scol / rc) * rc;
+    const int nchunk = nkc;
+
+    auto load_b = [&](int j, int kc, uint4 *breg, float &bscale) {
+        const int lim = min(64, kp - kc * 64) / 8;     // 16-byte pieces per half-column
+        const int32_t *sj = srcs[j % 3];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int scl = sj[btl[i]];
+            const bool ok = scl >= 0 && boff[i] >= 0 && bsub[i] < lim;
+            const uint16_t *base = bpart[i] ? L.Ml : L.Mh;
+            const uint4 v = *reinterpret_cast<const uint4 *>(
+                base + (ok ? int64_t(scl) * r * kp + boff[i] + kc * 64 : 0));
+            const uint32_t w = ok ? 0xffffffffu : 0u;
+            breg[i] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+        }
+        if constexpr (!X3) {
+            const int scl = sj[stl];
+            const bool ok = scl >= 0 && rhs0 + sc_c < r;
+            const float v = L.Msinv[ok ? (int64_t(scl) * r + rhs0 + sc_c) * nchunk + kc : 0];
+            bscale = ok ? v : 0.f;
+        }
+    };
+    auto store_b = [&](int buf, const uint4 *breg, float bscale) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            Bstore[buf][bpart[i]][(bcol[i] * ldb + 8 * bsub[i]) / 8] = breg[i];
+        if constexpr (!X3) Bsc[buf][scol] = bscale;   // four waves store the same value
+    };
+    const int64_t arow = int64_t(active ? row0 + (lane & 15) : 0) * kp + 8 * (lane >> 4);
+    auto load_a = [&](int j, int kc, uint4 *areg) {
+        const int nks = min(64, kp - kc * 64) / 32;
+        const int64_t base = int64_t(slot_t[j]) * kp * kp + arow + kc * 64;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int ks = i & 1;
+            const bool ok = active && ks < nks;
+            const uint16_t *C = (X3 && i >= 2) ? L.Cl : L.Ch;
+            const uint4 v = *reinterpret_cast<const uint4 *>(C + (ok ? base + 32 * ks : 0));
+            const uint32_t w = ok ? 0xffffffffu : 0u;
+            areg[i] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+        }
+    };
+
+    v4f acc[4];
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    uint4 breg[NB], a0[NA], a1[NA];
+    float bscale = 0.f;
+    load_b(jbeg, 0, breg, bscale);
+    store_b(0, breg, bscale);
+    load_a(jbeg, 0, a0);
+    __syncthreads();
+    int32_t itab_next = -1;
+    int j = jbeg, kc = 0;
+    auto step = [&](auto more_c, int s, const uint4 *acur, uint4 *anxt) {
+        constexpr bool MORE = decltype(more_c)::value;
+        int j1 = j, kc1 = kc + 1;
+        if (kc1 == nkc) { kc1 = 0; ++j1; }
+        const bool new_slot = MORE && kc1 == 0 && j + 3 < jend;
+        float cinv = 0.f;
+        if constexpr (!X3) cinv = L.Cinv[slot_t[j]];
+        if constexpr (MORE) {
+            load_b(j1, kc1, breg, bscale);
+            load_a(j1, kc1, anxt);
+            const int a = tgt[tid & 63];
+            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + min(j + 3, kSlots - 1)];
+            itab_next = a >= 0 ? v : -1;
+        }
+        const uint4 *Bh = Bstore[s & 1][0];
+        const int bbase = ((lane & 15) * ldb + 8 * (lane >> 4)) / 8;
+        if constexpr (X3) {
+            const uint4 *Bl = Bstore[s & 1][1];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                v8bf bh[4], bl[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    bh[cb] = __builtin_bit_cast(v8bf, Bh[bbase + (cb * 16 * ldb + 32 * ks) / 8]);
+                    bl[cb] = __builtin_bit_cast(v8bf, Bl[bbase + (cb * 16 * ldb + 32 * ks) / 8]);
+                }
+                const v8bf ah = __builtin_bit_cast(v8bf, acur[ks]);
+                const v8bf al = __builtin_bit_cast(v8bf, acur[2 + ks]);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], acc[cb], 0, 0, 0);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], acc[cb], 0, 0, 0);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[cb], 0, 0, 0);
+            }
+        } else {
+            v4f part[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) part[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const v8h a16 = __builtin_bit_cast(v8h, acur[ks]);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const v8h b16 = __builtin_bit_cast(v8h, Bh[bbase + (cb * 16 * ldb + 32 * ks) / 8]);
+                    part[cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a16, b16, part[cb], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const float f = Bsc[s & 1][cb * 16 + (lane & 15)] * cinv;
+                acc[cb] += part[cb] * f;
+            }
+        }
+        if constexpr (MORE) {
+            store_b((s + 1) & 1, breg, bscale);
+            if (new_slot && tid < kM2LCols) srcs[j % 3][tid] = itab_next;
+        }
+        __syncthreads();
+        j = j1;
+        kc = kc1;
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    int s = 0;
+    for (; s + 2 < nsteps; s += 2) {
+        step(yes{}, s, a0, a1);
+        step(yes{}, s + 1, a1, a0);
+    }
+    if (s + 1 < nsteps) {
+        step(yes{}, s, a0, a1);
+        step(no{}, s + 1, a1, a0);
+    } else {
+        step(no{}, s, a0, a1);
+    }
+    if (!active) return;
+    for (int cb = 0; cb < 4; ++cb) {
+        const int col = cb * 16 + (lane & 15);
+        const int tl = col / rc, c = col % rc;
+        if (tl < cnt && rhs0 + c < r) {
+            float *dst = L.Fh + split * L.rows * kp +
+                         (int64_t(tgt[tl]) * r + rhs0 + c) * kp + row0 + 4 * (lane >> 4);
+            *reinterpret_cast<float4 *>(dst) = make_float4(acc[cb][0], acc[cb][1], acc[cb][2], acc[cb][3]);
+        }
+    }
+}
+
 // --------------------------------------------------------- L2P + P2P ----
 // One wave per work item (leaf a, first target t0, log2 S): the wave holds
 // T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes").
@@ -718,6 +995,8 @@ struct Plan {
     int rc_p2p = 1;
     DBuf<float> sig_s;
     DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
+    DBuf<uint16_t> Mh16[kMaxLevels], Ml16[kMaxLevels];   // 16-bit M2L operand formats
+    DBuf<float> Msinv[kMaxLevels];                       // fp16 block scales
     DBuf<int32_t> tiles;                // all M2L tiles of all levels
     int ntiles = 0, max_kp = 0;
     DBuf<int32_t> work;
@@ -729,8 +1008,16 @@ struct Plan {
     int ring_head = 0, ring_pending = 0;
     double stage_ms[BBFMM_NUM_STAGES] = {0};
     int64_t timed_execs = 0;
+    // graph replay: the launch sequence captured once per (sigma, phi) pair
+    bool graph_on = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const float *g_sigma = nullptr;
+    float *g_phi = nullptr;
     ~Plan() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
 
@@ -766,8 +1053,21 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->max_kp = std::max(p->max_kp, kp);
         p->M[lvl].alloc(C * r * mp);
         p->F[lvl].alloc(C * r * mp);
-        p->Mh[lvl].alloc(C * r * kp);
-        ws += p->M[lvl].bytes() + p->F[lvl].bytes() + p->Mh[lvl].bytes();
+        if (o->precision == BBFMM_M2L_FP32) {
+            p->Mh[lvl].alloc(C * r * kp);
+            ws += p->Mh[lvl].bytes();
+        } else {
+            p->Mh16[lvl].alloc(C * r * kp);
+            ws += p->Mh16[lvl].bytes();
+            if (o->precision == BBFMM_M2L_BF16X3) {
+                p->Ml16[lvl].alloc(C * r * kp);
+                ws += p->Ml16[lvl].bytes();
+            } else {
+                p->Msinv[lvl].alloc(C * r * ceil_div(kp, 64));
+                ws += p->Msinv[lvl].bytes();
+            }
+        }
+        ws += p->M[lvl].bytes() + p->F[lvl].bytes();
         // M2L tiles: runs of up to tpt cells of one octant
         for (int oc = 0; oc < 8; ++oc)
             for (int s = t->lv[lvl].oct_off[oc]; s < t->lv[lvl].oct_off[oc + 1]; s += p->tpt) {
@@ -893,10 +1193,55 @@ void plan_stage_times(Plan *p, double *ms, int64_t *execs, bool reset) {
     }
 }
 
+namespace {
+void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool timing);
+}
+
+void plan_set_graph(Plan *p, bool on) {
+    BB_REQUIRE(p != nullptr, "plan is NULL");
+    if (on && p->cap_stream == nullptr)
+        BB_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    if (!on && p->gexec) {
+        BB_HIP(hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
+    p->graph_on = on;
+}
+
 void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) {
     BB_REQUIRE(pp != nullptr, "plan is NULL");
     BB_REQUIRE(sigma != nullptr && phi != nullptr, "sigma / phi is NULL");
     Plan &p = *pp;
+    if (!p.graph_on) {
+        enqueue_matvec(p, sigma, phi, s, p.timing);
+        return;
+    }
+    if (p.gexec == nullptr || sigma != p.g_sigma || phi != p.g_phi) {
+        if (p.gexec) {
+            BB_HIP(hipGraphExecDestroy(p.gexec));
+            p.gexec = nullptr;
+        }
+        BB_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            enqueue_matvec(p, sigma, phi, p.cap_stream, false);
+        } catch (...) {
+            (void)hipStreamEndCapture(p.cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        BB_HIP(hipStreamEndCapture(p.cap_stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&p.gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        BB_HIP(e);
+        p.g_sigma = sigma;
+        p.g_phi = phi;
+    }
+    BB_HIP(hipGraphLaunch(p.gexec, s));
+}
+
+namespace {
+void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool timing) {
     const bbfmm_tree &t = *p.tree;
     const bbfmm_ops &o = *p.ops;
     const int L = t.leaf_level();
@@ -907,7 +1252,7 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     geo.inv_h = 1.0f / geo.h;
 
     hipEvent_t *ev = nullptr;
-    if (p.timing) {
+    if (timing) {
         if (p.ring_pending == kTimingRing) harvest_one(p);
         ev = &p.events[size_t(p.ring_head) * kEv];
         p.ring_head = (p.ring_head + 1) % kTimingRing;
@@ -937,9 +1282,21 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     auto compress = [&](int lvl) {
         const OpSet &set = *o.lv[lvl].set;
         const int64_t R = int64_t(t.lv[lvl].C) * r;
-        dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(set.kp, 64)));
-        k_gemm_nt<<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp, p.Mh[lvl].p,
-                                         set.kp, R, set.kp, mp, 1.f, 0.f);
+        const int nchunk = int(ceil_div(set.kp, 64));
+        dim3 g(unsigned(ceil_div(R, 64)), unsigned(nchunk));
+        if (o.precision == BBFMM_M2L_FP32)
+            k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+                                                     p.Mh[lvl].p, set.kp, R, set.kp, mp, 1.f, 0.f,
+                                                     nullptr, nullptr, nullptr, 0);
+        else if (o.precision == BBFMM_M2L_BF16X3)
+            k_gemm_nt<kOutBF16X3><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+                                                        nullptr, set.kp, R, set.kp, mp, 1.f, 0.f,
+                                                        p.Mh16[lvl].p, p.Ml16[lvl].p, nullptr, 0);
+        else
+            k_gemm_nt<kOutF16S><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+                                                      nullptr, set.kp, R, set.kp, mp, 1.f, 0.f,
+                                                      p.Mh16[lvl].p, nullptr, p.Msinv[lvl].p,
+                                                      nchunk);
         BB_LAUNCH_CHECK();
     };
     if (L >= 2) compress(L);
@@ -957,7 +1314,28 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
         compress(lvl);
     }
     mark(BBFMM_STAGE_M2L);
-    if (L >= 2) {
+    if (L >= 2 && o.precision != BBFMM_M2L_FP32) {
+        M2LArgsLP g{};
+        for (int lvl = 2; lvl <= L; ++lvl) {
+            const OpSet &set = *o.lv[lvl].set;
+            g.lv[lvl] = M2LLevelLP{p.Mh16[lvl].p, p.Ml16[lvl].p, p.Msinv[lvl].p, p.Fh[lvl].p,
+                                   o.precision == BBFMM_M2L_BF16X3 ? set.Chi.p : set.C16.p,
+                                   set.Clo.p, set.Cinv.p, t.lv[lvl].itab.p,
+                                   t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
+        }
+        g.tiles = p.tiles.p;
+        g.tables = t.tables.p;
+        g.r = r;
+        g.rc = p.rc_m2l;
+        g.tpt = p.tpt;
+        g.nsplit = p.nsplit;
+        dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
+        if (o.precision == BBFMM_M2L_BF16X3)
+            k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, 0, s>>>(g);
+        else
+            k_m2l_lp<BBFMM_M2L_FP16_SCALED><<<gr, kThreads, 0, s>>>(g);
+        BB_LAUNCH_CHECK();
+    } else if (L >= 2) {
         M2LArgs g{};
         for (int lvl = 2; lvl <= L; ++lvl) {
             const OpSet &set = *o.lv[lvl].set;
@@ -990,9 +1368,10 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
         }
         const int64_t R = int64_t(lv.C) * r;
         dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
-        k_gemm_nt<<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp, set.U32.p,
-                                         set.kp, p.F[lvl].p, mp, R, mp, set.kp,
-                                         float(o.lv[lvl].scale), lvl > 2 ? 1.f : 0.f);
+        k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp,
+                                                 set.U32.p, set.kp, p.F[lvl].p, mp, R, mp, set.kp,
+                                                 float(o.lv[lvl].scale), lvl > 2 ? 1.f : 0.f,
+                                                 nullptr, nullptr, nullptr, 0);
         BB_LAUNCH_CHECK();
     }
     if (L >= 2) FL = p.F[L].p;
@@ -1005,5 +1384,7 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     }
     mark(BBFMM_NUM_STAGES);
 }
+
+}  // namespace
 
 }  // namespace bbfmm

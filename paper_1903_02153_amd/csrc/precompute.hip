@@ -275,6 +275,63 @@ k_cast_pad_t(const double *src, int m, int k, int mp, int kp, float *dst) {
     dst[g] = (kk < k && i < m) ? float(src[int64_t(i) * k + kk]) : 0.f;
 }
 
+// bf16 round-to-nearest-even of a float, as raw bits
+__device__ inline uint16_t bf16_bits(float x) {
+    const __bf16 h = static_cast<__bf16>(x);
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float bf16_value(uint16_t b) {
+    return static_cast<float>(__builtin_bit_cast(__bf16, b));
+}
+
+// hi = bf16(c), lo = bf16(c - hi) of every operator entry (zero-padded)
+__global__ void __launch_bounds__(kThreads)
+k_split_bf16(const double *C, int k, int kp, int batches, uint16_t *hi, uint16_t *lo) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t per = int64_t(kp) * kp;
+    if (g >= per * batches) return;
+    const int64_t b = g / per;
+    const int i = int((g % per) / kp), j = int(g % kp);
+    const double c = (i < k && j < k) ? C[b * k * k + int64_t(i) * k + j] : 0.0;
+    const uint16_t h = bf16_bits(float(c));
+    hi[g] = h;
+    lo[g] = bf16_bits(float(c - double(bf16_value(h))));
+}
+
+// per operator t: inv[t] = 2^-e with e such that max|C_t| 2^e lies in [2^14, 2^15)
+__global__ void __launch_bounds__(kThreads) k_operator_scale(const double *C, int k, float *inv) {
+    __shared__ double red[kThreads];
+    const int t = blockIdx.x;
+    double mx = 0.0;
+    for (int64_t e = threadIdx.x; e < int64_t(k) * k; e += kThreads)
+        mx = fmax(mx, fabs(C[int64_t(t) * k * k + e]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = red[0];
+        // keep 2^-e a normal float; entries too small for fp16 then flush to 0
+        // (operators below ~1e-38 contribute nothing at FP32 accuracy)
+        const int e = m > 0.0 ? max(-126, min(126, 14 - ilogb(m))) : 0;
+        inv[t] = float(ldexp(1.0, -e));
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_cast_fp16(const double *C, int k, int kp, int batches, const float *inv, uint16_t *out) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t per = int64_t(kp) * kp;
+    if (g >= per * batches) return;
+    const int64_t b = g / per;
+    const int i = int((g % per) / kp), j = int(g % kp);
+    const double c = (i < k && j < k) ? C[b * k * k + int64_t(i) * k + j] : 0.0;
+    const _Float16 h = static_cast<_Float16>(float(c / double(inv[b])));
+    out[g] = __builtin_bit_cast(uint16_t, h);
+}
+
 inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
 
 int pad16(int k) { return int(ceil_div(k, 16) * 16); }
@@ -360,18 +417,29 @@ void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, hipStream_t s)
 
 }  // namespace
 
-void finalize_opset(OpSet &set, int m, int mp, hipStream_t s) {
+void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s) {
     const int k = set.k;
-    set.kp = pad16(k);
-    set.U32.alloc(int64_t(mp) * set.kp);
-    set.VT32.alloc(int64_t(set.kp) * mp);
-    set.C32.alloc(int64_t(kNumT) * set.kp * set.kp);
-    k_cast_pad<<<grid(int64_t(mp) * set.kp), kThreads, 0, s>>>(set.U64.p, m, k, mp, set.kp, 1,
-                                                              set.U32.p);
-    k_cast_pad_t<<<grid(int64_t(mp) * set.kp), kThreads, 0, s>>>(set.V64.p, m, k, mp, set.kp,
-                                                                set.VT32.p);
-    k_cast_pad<<<grid(int64_t(kNumT) * set.kp * set.kp), kThreads, 0, s>>>(
-        set.C64.p, k, k, set.kp, set.kp, kNumT, set.C32.p);
+    // MFMA K granularity: 16 for FP32 (16x16x4), 32 for the 16-bit paths (16x16x32)
+    set.kp = precision == BBFMM_M2L_FP32 ? pad16(k) : int(ceil_div(k, 32) * 32);
+    const int kp = set.kp;
+    set.U32.alloc(int64_t(mp) * kp);
+    set.VT32.alloc(int64_t(kp) * mp);
+    k_cast_pad<<<grid(int64_t(mp) * kp), kThreads, 0, s>>>(set.U64.p, m, k, mp, kp, 1, set.U32.p);
+    k_cast_pad_t<<<grid(int64_t(mp) * kp), kThreads, 0, s>>>(set.V64.p, m, k, mp, kp, set.VT32.p);
+    const int64_t nc = int64_t(kNumT) * kp * kp;
+    if (precision == BBFMM_M2L_FP32) {
+        set.C32.alloc(nc);
+        k_cast_pad<<<grid(nc), kThreads, 0, s>>>(set.C64.p, k, k, kp, kp, kNumT, set.C32.p);
+    } else if (precision == BBFMM_M2L_BF16X3) {
+        set.Chi.alloc(nc);
+        set.Clo.alloc(nc);
+        k_split_bf16<<<grid(nc), kThreads, 0, s>>>(set.C64.p, k, kp, kNumT, set.Chi.p, set.Clo.p);
+    } else {
+        set.C16.alloc(nc);
+        set.Cinv.alloc(kNumT);
+        k_operator_scale<<<kNumT, kThreads, 0, s>>>(set.C64.p, k, set.Cinv.p);
+        k_cast_fp16<<<grid(nc), kThreads, 0, s>>>(set.C64.p, k, kp, kNumT, set.Cinv.p, set.C16.p);
+    }
     BB_LAUNCH_CHECK();
     BB_HIP(hipStreamSynchronize(s));
 }
@@ -402,7 +470,9 @@ void cheb_setup(bbfmm_ops *ops, hipStream_t s) {
 bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s) {
     BB_REQUIRE(t != nullptr, "tree is NULL");
     BB_REQUIRE(std::isfinite(eps) && eps >= 0.0, "svd_eps must be finite and >= 0");
-    BB_REQUIRE(precision == BBFMM_M2L_FP32, "unsupported M2L precision %d", precision);
+    BB_REQUIRE(precision == BBFMM_M2L_FP32 || precision == BBFMM_M2L_BF16X3 ||
+                   precision == BBFMM_M2L_FP16_SCALED,
+               "unsupported M2L precision %d", precision);
     std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
     ops->tree = t;
     ops->n = t->params.cheb_order;
@@ -439,7 +509,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
         std::unique_ptr<OpSet> set(new OpSet());
         DBuf<double> K = sample(1.0);
         compress_set(*set, K, m, eps, s);
-        finalize_opset(*set, m, ops->mp, s);
+        finalize_opset(*set, m, ops->mp, precision, s);
         for (int lvl = 2; lvl <= L; ++lvl) {
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0 / t->half_width(lvl);
@@ -450,7 +520,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
             std::unique_ptr<OpSet> set(new OpSet());
             DBuf<double> K = sample(t->half_width(lvl));
             compress_set(*set, K, m, eps, s);
-            finalize_opset(*set, m, ops->mp, s);
+            finalize_opset(*set, m, ops->mp, precision, s);
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0;
             ops->sets.push_back(std::move(set));

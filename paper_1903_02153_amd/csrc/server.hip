@@ -1,0 +1,418 @@
+// Serving loop: several resident (tree, operators) models, requests of
+// different N and r, continuous batching along the right-hand-side axis
+// (the multiple-RHS grouping of Section 2.5 applied across requests).
+//
+// A scheduler thread repeatedly
+//   1. retires finished batches (event query) and wakes their waiters;
+//   2. takes the oldest pending request, gathers every pending request of
+//      the same model in arrival order while the total r fits r_max, and
+//      rounds the total up to a power of two (the batch width R);
+//   3. admits the batch when a slot (own stream, own plan and staging
+//      buffers) is free and the slots' device memory stays within the HBM
+//      budget, else waits for a retirement;
+//   4. packs the requests' sigma columns into the slot's N x R staging
+//      matrix (padding columns zero), runs the plan, unpacks phi columns.
+// Batches on different slots run concurrently on separate streams.  Each
+// column of a batch is computed by the same kernels as a lone request, so a
+// result in the mix equals the result alone up to floating-point summation
+// order (the launch shape of a batch depends on R).
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace bbfmm {
+namespace {
+
+constexpr int kThreads = 256;
+
+// dst[i][c0 + c] = src[i][c] for c < rs; dst has R columns
+__global__ void __launch_bounds__(kThreads)
+k_pack(const float *src, int64_t n, int rs, float *dst, int R, int c0) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= n * rs) return;
+    const int64_t i = g / rs;
+    const int c = int(g % rs);
+    dst[i * R + c0 + c] = src[g];
+}
+
+// dst[i][c] = 0 for c0 <= c < R
+__global__ void __launch_bounds__(kThreads)
+k_zero_cols(int64_t n, float *dst, int R, int c0) {
+    const int w = R - c0;
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= n * w) return;
+    dst[(g / w) * R + c0 + g % w] = 0.f;
+}
+
+// dst[i][c] = src[i][c0 + c]
+__global__ void __launch_bounds__(kThreads)
+k_unpack(const float *src, int64_t n, int R, int c0, float *dst, int rs) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= n * rs) return;
+    const int64_t i = g / rs;
+    const int c = int(g % rs);
+    dst[g] = src[i * R + c0 + c];
+}
+
+inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t id = 0;
+    int model = 0;
+    const float *sigma = nullptr;
+    float *phi = nullptr;
+    int64_t r = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int32_t batch_r = 0, slot = -1;
+    bool done = false;
+    bbfmm_status status = BBFMM_OK;
+    std::string error;
+};
+
+struct Model {
+    const bbfmm_tree *tree;
+    const bbfmm_ops *ops;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int model = -1, R = 0;
+    Plan *plan = nullptr;
+    DBuf<float> sig, phi;
+    int64_t bytes = 0;                 // plan workspace + staging
+    std::vector<Request *> batch;
+};
+
+}  // namespace
+
+struct Server {
+    int64_t budget;
+    int max_inflight, r_max;
+    std::vector<Model> models;
+    std::vector<Slot> slots;
+    std::deque<Request *> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+    uint64_t next_id = 1;
+    int64_t in_use = 0;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    std::string fatal;
+
+    ~Server() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        if (worker.joinable()) worker.join();
+        for (Slot &s : slots) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            plan_destroy(s.plan);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+        }
+    }
+
+    // called with mu held
+    void retire() {
+        for (size_t k = 0; k < slots.size(); ++k) {
+            Slot &s = slots[k];
+            if (!s.busy) continue;
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            const double t = now_s();
+            for (Request *rq : s.batch) {
+                rq->t_done = t;
+                rq->done = true;
+                if (q != hipSuccess) {
+                    rq->status = BBFMM_ERR_HIP;
+                    rq->error = hipGetErrorString(q);
+                }
+            }
+            s.batch.clear();
+            s.busy = false;
+            cv_done.notify_all();
+        }
+    }
+
+    // Launch the batch on slot k; called with mu held.  Returns false when
+    // the batch does not fit the budget right now.
+    bool launch(size_t k, std::vector<Request *> &batch, int R) {
+        Slot &s = slots[k];
+        const int mdl = batch.front()->model;
+        const Model &m = models[mdl];
+        if (s.model != mdl || s.R != R) {
+            in_use -= s.bytes;
+            plan_destroy(s.plan);
+            s.plan = nullptr;
+            s.sig.release();
+            s.phi.release();
+            s.bytes = 0;
+            s.model = -1;
+            struct PlanDel {
+                void operator()(Plan *q) const { plan_destroy(q); }
+            };
+            std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, nullptr));
+            const int64_t need = plan_workspace_bytes(plan.get()) + 2 * m.tree->n * R * int64_t(sizeof(float));
+            if (need > budget) {
+                for (Request *rq : batch) {
+                    rq->status = BBFMM_ERR_BUDGET;
+                    rq->error = "request does not fit the HBM budget";
+                    rq->done = true;
+                    rq->t_admit = rq->t_done = now_s();
+                }
+                cv_done.notify_all();
+                return true;     // consumed (rejected)
+            }
+            // idle slots give back their cached plans before the batch waits
+            for (size_t q = 0; q < slots.size() && in_use + need > budget; ++q) {
+                Slot &o = slots[q];
+                if (q == k || o.busy || o.plan == nullptr) continue;
+                plan_destroy(o.plan);
+                o.plan = nullptr;
+                o.sig.release();
+                o.phi.release();
+                in_use -= o.bytes;
+                o.bytes = 0;
+                o.model = -1;
+                o.R = 0;
+            }
+            if (in_use + need > budget) return false;
+            s.sig.alloc(m.tree->n * R);
+            s.phi.alloc(m.tree->n * R);
+            s.plan = plan.release();
+            s.bytes = need;
+            s.model = mdl;
+            s.R = R;
+            in_use += need;
+        }
+        const int64_t n = m.tree->n;
+        const double t = now_s();
+        int c0 = 0;
+        for (Request *rq : batch) {
+            k_pack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(rq->sigma, n, int(rq->r), s.sig.p, R, c0);
+            c0 += int(rq->r);
+        }
+        if (c0 < R) k_zero_cols<<<grid(n * (R - c0)), kThreads, 0, s.stream>>>(n, s.sig.p, R, c0);
+        BB_LAUNCH_CHECK();
+        plan_execute_impl(s.plan, s.sig.p, s.phi.p, s.stream);
+        c0 = 0;
+        for (Request *rq : batch) {
+            k_unpack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(s.phi.p, n, R, c0, rq->phi, int(rq->r));
+            c0 += int(rq->r);
+            rq->t_admit = t;
+            rq->batch_r = c0;       // overwritten below with the batch total
+            rq->slot = int(k);
+        }
+        BB_LAUNCH_CHECK();
+        for (Request *rq : batch) rq->batch_r = c0;
+        BB_HIP(hipEventRecord(s.done, s.stream));
+        s.batch = batch;
+        s.busy = true;
+        return true;
+    }
+
+    void loop() {
+        if (hipSetDevice(device) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            fatal = "hipSetDevice failed in the scheduler";
+            return;
+        }
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stop) {
+            retire();
+            bool progressed = false;
+            if (!pending.empty()) {
+                // batch: the oldest request and later ones of the same model
+                const int mdl = pending.front()->model;
+                std::vector<Request *> batch;
+                int64_t tot = 0;
+                for (Request *rq : pending) {
+                    if (rq->model != mdl) continue;
+                    if (tot + rq->r > r_max) break;
+                    batch.push_back(rq);
+                    tot += rq->r;
+                }
+                int R = 1;
+                while (R < tot) R *= 2;
+                // prefer a free slot that already holds this (model, R) plan
+                int pick = -1;
+                for (size_t k = 0; k < slots.size(); ++k)
+                    if (!slots[k].busy && slots[k].model == mdl && slots[k].R == R) { pick = int(k); break; }
+                if (pick < 0)
+                    for (size_t k = 0; k < slots.size(); ++k)
+                        if (!slots[k].busy) { pick = int(k); break; }
+                if (pick >= 0) {
+                    bool ok = false;
+                    try {
+                        ok = launch(size_t(pick), batch, R);
+                    } catch (const Exception &) {
+                        const std::string msg = bbfmm_last_error();
+                        for (Request *rq : batch) {
+                            rq->status = BBFMM_ERR_HIP;
+                            rq->error = msg;
+                            rq->done = true;
+                        }
+                        cv_done.notify_all();
+                        ok = true;
+                    }
+                    if (ok) {
+                        for (Request *rq : batch)
+                            for (auto it = pending.begin(); it != pending.end(); ++it)
+                                if (*it == rq) { pending.erase(it); break; }
+                        progressed = true;
+                    }
+                }
+            }
+            if (!progressed) {
+                bool any_busy = false;
+                for (Slot &s : slots) any_busy |= s.busy;
+                if (any_busy)
+                    cv_work.wait_for(lk, std::chrono::microseconds(50));
+                else
+                    cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+            }
+        }
+    }
+};
+
+}  // namespace bbfmm
+
+struct bbfmm_server {
+    std::unique_ptr<bbfmm::Server> impl;
+};
+
+using namespace bbfmm;
+
+extern "C" {
+
+bbfmm_status bbfmm_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, int32_t r_max,
+                                 bbfmm_server **out) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        BB_REQUIRE(hbm_budget_bytes > 0, "hbm_budget_bytes must be positive");
+        BB_REQUIRE(max_inflight >= 1 && max_inflight <= 64, "max_inflight must be in [1, 64]");
+        BB_REQUIRE(r_max >= 1 && r_max <= 4096, "r_max must be in [1, 4096]");
+        std::unique_ptr<bbfmm_server> sv(new bbfmm_server());
+        sv->impl.reset(new Server());
+        Server &s = *sv->impl;
+        s.budget = hbm_budget_bytes;
+        s.max_inflight = max_inflight;
+        s.r_max = r_max;
+        BB_HIP(hipGetDevice(&s.device));
+        s.slots.resize(max_inflight);
+        for (Slot &sl : s.slots) {
+            BB_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+            BB_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+        }
+        s.worker = std::thread([&s] { s.loop(); });
+        *out = sv.release();
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    } catch (...) {
+        return BBFMM_ERR_INTERNAL;
+    }
+}
+
+bbfmm_status bbfmm_server_add(bbfmm_server *sv, const bbfmm_tree *tree, const bbfmm_ops *ops,
+                              int32_t *model_id) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(sv && tree && ops && model_id, "NULL argument");
+        BB_REQUIRE(ops->tree == tree, "operators were built for another tree");
+        Server &s = *sv->impl;
+        std::lock_guard<std::mutex> lk(s.mu);
+        s.models.push_back(Model{tree, ops});
+        *model_id = int32_t(s.models.size() - 1);
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    }
+}
+
+bbfmm_status bbfmm_server_submit(bbfmm_server *sv, int32_t model_id, const float *sigma, int64_t r,
+                                 float *phi, uint64_t *request_id) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(sv && sigma && phi && request_id, "NULL argument");
+        Server &s = *sv->impl;
+        std::lock_guard<std::mutex> lk(s.mu);
+        BB_REQUIRE(s.fatal.empty(), "%s", s.fatal.c_str());
+        BB_REQUIRE(model_id >= 0 && model_id < int32_t(s.models.size()), "unknown model %d", model_id);
+        BB_REQUIRE(r >= 1 && r <= s.r_max, "r must be in [1, r_max]");
+        for (const void *ptr : {static_cast<const void *>(sigma), static_cast<const void *>(phi)}) {
+            hipPointerAttribute_t attr{};
+            BB_REQUIRE(hipPointerGetAttributes(&attr, ptr) == hipSuccess &&
+                           (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged),
+                       "sigma / phi must be device pointers");
+        }
+        std::unique_ptr<Request> rq(new Request());
+        rq->id = s.next_id++;
+        rq->model = model_id;
+        rq->sigma = sigma;
+        rq->phi = phi;
+        rq->r = r;
+        rq->t_submit = now_s();
+        *request_id = rq->id;
+        s.pending.push_back(rq.get());
+        s.requests[rq->id] = std::move(rq);
+        s.cv_work.notify_all();
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    }
+}
+
+bbfmm_status bbfmm_server_wait(bbfmm_server *sv, uint64_t request_id, bbfmm_request_stats *stats) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(sv != nullptr, "server is NULL");
+        Server &s = *sv->impl;
+        std::unique_lock<std::mutex> lk(s.mu);
+        auto it = s.requests.find(request_id);
+        if (it == s.requests.end()) fail(BBFMM_ERR_NOT_FOUND, "unknown request %llu", (unsigned long long)request_id);
+        Request *rq = it->second.get();
+        s.cv_done.wait(lk, [&] { return rq->done || !s.fatal.empty(); });
+        BB_REQUIRE(rq->done, "%s", s.fatal.c_str());
+        if (stats) {
+            stats->t_submit = rq->t_submit;
+            stats->t_admit = rq->t_admit;
+            stats->t_done = rq->t_done;
+            stats->batch_r = rq->batch_r;
+            stats->slot = rq->slot;
+        }
+        const bbfmm_status st = rq->status;
+        const std::string err = rq->error;
+        s.requests.erase(it);
+        if (st != BBFMM_OK) fail(st, "%s", err.c_str());
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    }
+}
+
+bbfmm_status bbfmm_server_destroy(bbfmm_server *sv) {
+    bbfmm::clear_error();
+    delete sv;
+    return BBFMM_OK;
+}
+
+}  // extern "C"

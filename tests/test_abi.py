@@ -73,3 +73,13 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(bbfmm, "LIB_PATH", "/nonexistent/libbbfmm.so")
     with pytest.raises(RuntimeError, match="missing"):
         bbfmm.lib()
+
+
+def test_server_rejects_invalid_arguments_without_gpu():
+    lib = bbfmm.lib()
+    out = ctypes.c_void_p()
+    assert lib.bbfmm_server_create(0, 4, 16, ctypes.byref(out)) == 1
+    assert lib.bbfmm_server_create(1 << 30, 0, 16, ctypes.byref(out)) == 1
+    assert lib.bbfmm_server_create(1 << 30, 4, 0, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert lib.bbfmm_server_destroy(None) == 0

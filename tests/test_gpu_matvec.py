@@ -145,3 +145,59 @@ def test_full_size_uniform_1m_sampled_rows():
     ex = ofmm.direct(w.points, w.sigma, 0, 1.0, rows=w.sample_rows)
     print(f"uniform-1M: rel err vs oracle {ofmm.rel_l2(got, ref):.2e}, "
           f"vs direct {ofmm.rel_l2(got, ex):.2e}")
+
+
+# Mixed-precision M2L (P2P, up/down passes and (de)compression stay FP32).
+# Split-BF16: each operand is hi + lo with |x - hi - lo| <= 2^-18 |x|; the
+# dropped lo*lo term and the residuals bound a product's relative error by
+# ~3 * 2^-18 = 1.1e-5, and errors of the k terms of a row average out, so the
+# FP32 bar applies.  Scaled FP16: two roundings of 2^-11 per product bound a
+# term by ~1e-3 relative; only the far field carries it.
+@pytest.mark.parametrize("prec,tol", [(1, TOL), (2, 1e-3)])
+@pytest.mark.parametrize("kid,prm,n,kind,r", [(1, 0.1, 6, "clustered", 3),
+                                              (2, 0.05, 7, "slab", 2),
+                                              (0, 1.0, 5, "uniform", 1),
+                                              (1, 0.3, 4, "uniform", 5)])
+def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(12000, 40 + n, r=r, kind=kind)
+    gt = gpu_tree(pts, kid, prm, n, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5, prec)
+    ot = oracle_tree(pts, fixed_depth=5)
+    oo = oops.precompute(ot, kid, prm, n, 1e-5)
+    got = gpu_matvec(gt, go, sig)
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    far = ref - ofmm.matvec(ot, oo, pts, sig, kid, prm, far=False)
+    err = ofmm.rel_l2_cols(got, ref).max()
+    err_far = np.linalg.norm(got - ref) / np.linalg.norm(far)
+    print(f"precision {prec} kernel {kid} n {n}: rel err {err:.2e} (relative to far field {err_far:.2e})")
+    assert err < tol
+
+
+def test_graph_replay_matches_eager():
+    """HIP-graph replay of a plan equals eager execution on every replay,
+    with unrelated eager work and synchronisations between replays."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(30000, 60, r=3, kind="clustered")
+    gt = gpu_tree(pts, 1, 0.2, 5, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5)
+    ts = torch.from_numpy(sig).cuda()
+    eager = bbfmm.Plan(gt, go, 3)
+    ref = torch.empty_like(ts)
+    eager.execute(ts, ref)
+    graph = bbfmm.Plan(gt, go, 3)
+    graph.set_graph(True)
+    out = torch.empty_like(ts)
+    for rep in range(4):
+        out.fill_(float("nan"))
+        graph.execute(ts, out)
+        junk = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        del junk
+    # a new output buffer is captured again
+    out2 = torch.empty_like(ts)
+    graph.execute(ts, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, ref)
