@@ -43,6 +43,13 @@ def direct(points: np.ndarray, sigma: np.ndarray, kernel_id: int,
     return direct_sum(tgt, pts, sig, kernel_id, param)
 
 
+def _left(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Y[c, i, r] = sum_j A[i, j] X[c, j, r], evaluated as one matrix product."""
+    c, j, r = X.shape
+    Y = A @ X.transpose(1, 0, 2).reshape(j, c * r)
+    return np.ascontiguousarray(Y.reshape(A.shape[0], c, r).transpose(1, 0, 2))
+
+
 def _as_2d(sigma) -> np.ndarray:
     s = np.asarray(sigma, dtype=np.float64)
     return s[:, None] if s.ndim == 1 else s
@@ -70,7 +77,7 @@ def upward(tree: Tree, ops: Ops, Y: np.ndarray, S: np.ndarray) -> dict:
         for o in range(8):
             sel = np.nonzero(octant == o)[0]
             # a parent has at most one child per octant: no repeated index
-            Mp[child.parent[sel]] += np.einsum("ij,cjr->cir", T3[o], M[lvl + 1][sel])
+            Mp[child.parent[sel]] += _left(T3[o], M[lvl + 1][sel])
         M[lvl] = Mp
     return M
 
@@ -80,7 +87,7 @@ def m2l(tree: Tree, ops: Ops, M: dict) -> dict:
     F = {}
     for lvl in range(2, tree.depth):
         op = ops.levels[lvl]
-        Mh = np.einsum("ik,cir->ckr", op.V, M[lvl])
+        Mh = _left(op.V.T, M[lvl])
         Fh = np.zeros_like(Mh)
         pr = tree.pairs[lvl]
         g = pr["group_off"]
@@ -89,9 +96,8 @@ def m2l(tree: Tree, ops: Ops, M: dict) -> dict:
             if s == e:
                 continue
             # within one transfer vector each target occurs at most once
-            Fh[pr["tgt"][s:e]] += np.einsum("ab,pbr->par", op.C[ti],
-                                            Mh[pr["src"][s:e]])
-        F[lvl] = np.einsum("ik,ckr->cir", op.U, Fh)
+            Fh[pr["tgt"][s:e]] += _left(op.C[ti], Mh[pr["src"][s:e]])
+        F[lvl] = _left(op.U, Fh)
     return F
 
 
@@ -104,8 +110,7 @@ def downward(tree: Tree, ops: Ops, F: dict) -> dict:
         octant = (child.keys & np.uint64(7)).astype(np.int64)
         for o in range(8):
             sel = np.nonzero(octant == o)[0]
-            F[lvl][sel] += np.einsum("ji,cjr->cir", T3[o],
-                                     F[lvl - 1][child.parent[sel]])
+            F[lvl][sel] += _left(T3[o].T, F[lvl - 1][child.parent[sel]])
     return F
 
 
@@ -136,7 +141,7 @@ def matvec(tree: Tree, ops: Optional[Ops], points: np.ndarray,
         hL = tree.half_width(L)
         xi = (Y[want_pos] - cL[leaf_of]) / hL
         Sx = cheb.lagrange_3d(n, xi)                       # (targets, n^3)
-        out += np.einsum("pi,pir->pr", Sx, F[L][leaf_of])
+        out += np.matmul(Sx[:, None, :], F[L][leaf_of])[:, 0, :]
 
     if near:
         order = np.argsort(leaf_of, kind="stable")
