@@ -11,7 +11,10 @@ decompression + L2L, L2P + P2P, scatter) on inputs already resident in HBM.
 Prints one JSON line: throughput in points x RHS per second, per-step
 latency percentiles, per-stage device time from HIP events recorded inside
 the timed steps, the roofline of the dominant kernel, and the FP64 oracle
-timed on the host cores on a bounded sample of the same workload.
+timed on the host cores on a bounded sample of the same workload.  Beside
+it: the batched mixed-precision forms against plain single-RHS FP32 on the
+clustered 2M-point (r = 16) and slab 1M-point (r = 64) workloads, and the
+8-tree serving mix (Poisson arrivals, p50/p99 latency, throughput).
 """
 import argparse
 import json
@@ -68,12 +71,174 @@ def cpu_baseline(w, gpu_phi_rows):
     }
 
 
+def time_plan(plan, sig, phi, steps: int, warmup: int):
+    """Per-execution device time (ms, HIP events on the launching stream)."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        plan.execute(sig, phi)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        plan.execute(sig, phi)
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def batched_variants(steps: int, warmup: int):
+    """Batched mixed-precision forms against plain single-RHS FP32 on the
+    two batched workloads: points x RHS/s of the single-RHS FP32 form, the
+    r-column FP32 form and the r-column low-precision forms (HIP-graph
+    replay), with each form's largest per-column relative difference from
+    the r-column FP32 result (whose own error against the FP64 oracle is
+    pinned by the full-size parity tests)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1903_02153_amd import bbfmm
+    out = []
+    for make, precs in ((synth.cfg_clustered_2m, (bbfmm.M2L_BF16X3, bbfmm.M2L_FP16_SCALED)),
+                        (synth.cfg_slab_1m, (bbfmm.M2L_BF16X3, bbfmm.M2L_FP16_SCALED))):
+        w = make()
+        dev = torch.device("cuda:0")
+        pts = torch.from_numpy(w.points).to(dev)
+        sig = torch.from_numpy(w.sigma).to(dev)
+        tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
+                                leaf_size=w.leaf_size, max_depth=w.max_depth,
+                                fixed_depth=w.fixed_depth)
+        info = tree.info()
+        rec = {"workload": w.name, "N": w.n, "r": w.r, "depth": info.depth,
+               "near_pairs": info.near_pairs, "forms": {}}
+
+        def run(tag, prec, r):
+            ops = bbfmm.precompute_operators(tree, w.eps, prec)
+            plan = bbfmm.Plan(tree, ops, r)
+            plan.set_graph(True)
+            s = sig[:, :r].contiguous()
+            phi = torch.empty_like(s)
+            n_steps = steps if r > 1 else max(steps, 10)
+            lat = time_plan(plan, s, phi, n_steps, warmup)
+            med = float(np.median(lat))
+            rec["forms"][tag] = {"precision": ("fp32", "bf16x3", "fp16-scaled")[prec], "r": r,
+                                 "ms_median": round(med, 4),
+                                 "ms_p99": round(float(np.percentile(lat, 99)), 4),
+                                 "points_rhs_per_s": w.n * r / (med * 1e-3),
+                                 "ranks": {lvl: ops.rank(lvl) for lvl in range(2, info.depth)}}
+            plan.close()
+            return phi
+
+        run("fp32_r1", bbfmm.M2L_FP32, 1)
+        ref = run(f"fp32_r{w.r}", bbfmm.M2L_FP32, w.r)
+        for prec in precs:
+            tag = ("fp32", "bf16x3", "fp16s")[prec] + f"_r{w.r}"
+            got = run(tag, prec, w.r)
+            d = ((got - ref).norm(dim=0) / ref.norm(dim=0)).max().item()
+            rec["forms"][tag]["max_col_rel_diff_vs_fp32"] = d
+            del got
+        base = rec["forms"]["fp32_r1"]["points_rhs_per_s"]
+        for f in rec["forms"].values():
+            f["speedup_vs_fp32_r1"] = round(f["points_rhs_per_s"] / base, 3)
+        out.append(rec)
+        del ref, sig, pts, tree
+        torch.cuda.empty_cache()
+    return out
+
+
+def serving_mix(n_requests: int, budget_gib: float, load: float):
+    """The 8-tree serving mix: calibrate capacity with closed-loop bursts,
+    then replay a Poisson stream at `load` x capacity and report latency
+    percentiles (submit to completion, server clock) and throughput."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1903_02153_amd import bbfmm
+    dev = torch.device("cuda:0")
+    models, ids, classes = [], [], {}
+    srv = bbfmm.Server(hbm_budget_bytes=int(budget_gib * (1 << 30)), max_inflight=8, r_max=32)
+    rng = np.random.default_rng(5)
+    ring = 8
+    for i in range(len(synth.SERVING_SIZES)):
+        w = synth.serving_tree(i)
+        t = bbfmm.build_tree(torch.from_numpy(w.points).to(dev), w.kernel_id, w.kernel_param,
+                             cheb_order=w.order, leaf_size=w.leaf_size, max_depth=w.max_depth)
+        o = bbfmm.precompute_operators(t, w.eps)
+        models.append((t, o, w.n))
+        ids.append(srv.add(t, o))
+        for r in synth.SERVING_R:
+            s = torch.from_numpy(rng.standard_normal((w.n, r)).astype(np.float32)).to(dev)
+            classes[(i, r)] = (s, [torch.empty_like(s) for _ in range(ring)])
+    torch.cuda.synchronize()
+    counter = {}
+
+    def submit(i, r):
+        s, outs = classes[(i, r)]
+        c = counter.get((i, r), 0)
+        counter[(i, r)] = c + 1
+        # outputs rotate over a ring per (tree, r) class; they are not inspected
+        return srv.submit(ids[i], s, outs[c % ring])
+
+    tree_ix, rs, gaps = synth.serving_requests(n_requests, seed=5)
+
+    def burst(lo, hi):
+        t0 = time.perf_counter()
+        rids = [submit(int(tree_ix[q]), int(rs[q])) for q in range(lo, hi)]
+        st = [srv.wait(q) for q in rids]
+        return time.perf_counter() - t0, st
+
+    nb = min(200, n_requests)
+    burst(0, nb)                       # creates and captures the plans
+    t_burst, st = burst(0, nb)
+    work = float(sum(models[int(tree_ix[q])][2] * int(rs[q]) for q in range(nb)))
+    capacity = nb / t_burst
+    lam = load * capacity
+    arrivals = np.cumsum(gaps) / lam
+    t0 = time.perf_counter()
+    rids = []
+    for q in range(n_requests):
+        dt = arrivals[q] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        rids.append(submit(int(tree_ix[q]), int(rs[q])))
+    stats = [srv.wait(q) for q in rids]
+    srv.close()
+    lat = np.array([s["t_done"] - s["t_submit"] for s in stats]) * 1e3
+    queue = np.array([s["t_admit"] - s["t_submit"] for s in stats]) * 1e3
+    span = max(s["t_done"] for s in stats) - min(s["t_submit"] for s in stats)
+    total = float(sum(models[int(tree_ix[q])][2] * int(rs[q]) for q in range(n_requests)))
+    batched = np.array([s["batch_r"] for s in stats]) > rs
+    out = {"trees": [m[2] for m in models], "requests": n_requests, "r_choices": list(synth.SERVING_R),
+           "hbm_budget_gib": budget_gib, "max_inflight": 8, "r_max": 32,
+           "capacity_req_per_s": round(capacity, 2),
+           "capacity_points_rhs_per_s": work / t_burst,
+           "arrival_rate_req_per_s": round(lam, 2), "load": load,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "mean": float(lat.mean()), "max": float(lat.max())},
+           "queue_ms": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
+           "throughput_points_rhs_per_s": total / span,
+           "throughput_req_per_s": n_requests / span,
+           "batched_fraction": float(batched.mean())}
+    del classes
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the batched mixed-precision comparison (clustered-2M, slab-1M)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 8-tree serving mix")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-budget-gib", type=float, default=96.0)
+    ap.add_argument("--serving-load", type=float, default=0.7)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -159,6 +324,11 @@ def main() -> int:
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
+    if not args.no_variants:
+        out["batched_variants"] = batched_variants(max(5, min(args.steps, 20)), 2)
+    if not args.no_serving:
+        out["serving"] = serving_mix(args.serving_requests, args.serving_budget_gib,
+                                     args.serving_load)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         plan.execute(sig, phi)

@@ -278,13 +278,17 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  * order, total r <= r_max, rounded up to a power of two) into one product
  * on one of max_inflight slots; slots run concurrently on their own streams.
  * A batch is admitted when a slot is free and the device memory held by the
- * slots (plan workspace + staging) stays within hbm_budget_bytes; idle
- * slots release cached plans to make room.  A request larger than the
- * budget on its own fails with BBFMM_ERR_BUDGET (reported by wait).
+ * server's cached plans (workspace + N x R staging, one plan per (model, R),
+ * replayed as a HIP graph) stays within hbm_budget_bytes; idle plans are
+ * evicted least recently used first to make room.  A request larger than
+ * the budget on its own fails with BBFMM_ERR_BUDGET (reported by wait).
  *   sigma, phi  device, N x r float32 (the model's N); must stay valid and
  *               untouched until wait returns.
- * Results equal a lone bbfmm_matvec of the request up to floating-point
- * summation order.  Trees and operators must outlive the server.
+ * Batch invariance: every server plan uses m2l_split = 2, and with the split
+ * fixed the arithmetic of one column does not depend on the other columns
+ * or on R, so a request's phi is bit-identical to bbfmm_plan_execute of a
+ * lone plan for that request with m2l_split = 2, whatever batch it ran in.
+ * Trees and operators must outlive the server.
  */
 typedef struct bbfmm_server bbfmm_server;
 typedef struct {

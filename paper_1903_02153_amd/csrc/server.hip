@@ -12,13 +12,23 @@
 //      budget, else waits for a retirement;
 //   4. packs the requests' sigma columns into the slot's N x R staging
 //      matrix (padding columns zero), runs the plan, unpacks phi columns.
-// Batches on different slots run concurrently on separate streams.  Each
-// column of a batch is computed by the same kernels as a lone request, so a
-// result in the mix equals the result alone up to floating-point summation
-// order (the launch shape of a batch depends on R).
+// Batches on different slots run concurrently on separate streams.  Plans
+// (workspace, staging and the captured graph of one (model, R)) live in a
+// cache shared by the slots, reused while idle and evicted least recently
+// used first when the budget needs room.
+//
+// Batch invariance: every plan the server makes splits the M2L slot range
+// over the same kServeSplit workgroups.  With that fixed, the arithmetic of
+// one right-hand side does not depend on the batch width R or on the other
+// columns (P2M/M2M/L2L run one wave per (cell, column), the (de)compression
+// GEMMs and the M2L accumulate each column in a fixed order, and the P2P
+// assigns sources to sub-lanes by leaf size only), so a request's phi is
+// bit-identical to a lone plan execution with m2l_split = kServeSplit,
+// whatever batch it ran in.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -29,6 +39,7 @@ namespace bbfmm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kServeSplit = 2;
 
 // dst[i][c0 + c] = src[i][c] for c < rs; dst has R columns
 __global__ void __launch_bounds__(kThreads)
@@ -84,14 +95,23 @@ struct Model {
     const bbfmm_ops *ops;
 };
 
-struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    bool busy = false;
+// A plan and its N x R staging matrices for one (model, R); used by one
+// slot at a time, cached while idle.
+struct Entry {
     int model = -1, R = 0;
     Plan *plan = nullptr;
     DBuf<float> sig, phi;
     int64_t bytes = 0;                 // plan workspace + staging
+    uint64_t last_use = 0;
+    bool busy = false;
+    ~Entry() { plan_destroy(plan); }
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    Entry *entry = nullptr;
     std::vector<Request *> batch;
 };
 
@@ -102,9 +122,11 @@ struct Server {
     int max_inflight, r_max;
     std::vector<Model> models;
     std::vector<Slot> slots;
+    std::vector<std::unique_ptr<Entry>> cache;
+    std::map<std::pair<int, int>, int64_t> need;   // bytes of a (model, R) entry, once known
     std::deque<Request *> pending;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
-    uint64_t next_id = 1;
+    uint64_t next_id = 1, tick = 0;
     int64_t in_use = 0;
     int device = 0;
     std::mutex mu;
@@ -120,9 +142,10 @@ struct Server {
         }
         cv_work.notify_all();
         if (worker.joinable()) worker.join();
-        for (Slot &s : slots) {
+        for (Slot &s : slots)
             if (s.stream) (void)hipStreamSynchronize(s.stream);
-            plan_destroy(s.plan);
+        cache.clear();
+        for (Slot &s : slots) {
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
         }
@@ -146,8 +169,64 @@ struct Server {
             }
             s.batch.clear();
             s.busy = false;
+            s.entry->busy = false;
+            s.entry = nullptr;
             cv_done.notify_all();
         }
+    }
+
+    // An idle cached entry for (model, R), or a new one if the budget allows
+    // after evicting idle entries (least recently used first).  Returns
+    // nullptr when the batch must wait; sets *reject when it can never fit.
+    Entry *acquire(int mdl, int R, bool *reject) {
+        *reject = false;
+        for (auto &e : cache)
+            if (!e->busy && e->model == mdl && e->R == R) return e.get();
+        const auto key = std::make_pair(mdl, R);
+        auto known = need.find(key);
+        if (known != need.end()) {
+            if (known->second > budget) {
+                *reject = true;
+                return nullptr;
+            }
+            int64_t idle = 0;
+            for (auto &e : cache)
+                if (!e->busy) idle += e->bytes;
+            if (in_use - idle + known->second > budget) return nullptr;   // wait for a retirement
+        }
+        const Model &m = models[mdl];
+        bbfmm_plan_options opt{};
+        opt.m2l_split = kServeSplit;
+        struct PlanDel {
+            void operator()(Plan *q) const { plan_destroy(q); }
+        };
+        std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, &opt));
+        const int64_t bytes = plan_workspace_bytes(plan.get()) + 2 * m.tree->n * R * int64_t(sizeof(float));
+        need[key] = bytes;
+        if (bytes > budget) {
+            *reject = true;
+            return nullptr;
+        }
+        while (in_use + bytes > budget) {
+            size_t victim = cache.size();
+            for (size_t q = 0; q < cache.size(); ++q)
+                if (!cache[q]->busy && (victim == cache.size() || cache[q]->last_use < cache[victim]->last_use))
+                    victim = q;
+            if (victim == cache.size()) return nullptr;     // everything cached is running
+            in_use -= cache[victim]->bytes;
+            cache.erase(cache.begin() + victim);
+        }
+        std::unique_ptr<Entry> e(new Entry());
+        e->model = mdl;
+        e->R = R;
+        e->sig.alloc(m.tree->n * R);
+        e->phi.alloc(m.tree->n * R);
+        plan_set_graph(plan.get(), true);
+        e->plan = plan.release();
+        e->bytes = bytes;
+        in_use += bytes;
+        cache.push_back(std::move(e));
+        return cache.back().get();
     }
 
     // Launch the batch on slot k; called with mu held.  Returns false when
@@ -155,73 +234,42 @@ struct Server {
     bool launch(size_t k, std::vector<Request *> &batch, int R) {
         Slot &s = slots[k];
         const int mdl = batch.front()->model;
-        const Model &m = models[mdl];
-        if (s.model != mdl || s.R != R) {
-            in_use -= s.bytes;
-            plan_destroy(s.plan);
-            s.plan = nullptr;
-            s.sig.release();
-            s.phi.release();
-            s.bytes = 0;
-            s.model = -1;
-            struct PlanDel {
-                void operator()(Plan *q) const { plan_destroy(q); }
-            };
-            std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, nullptr));
-            const int64_t need = plan_workspace_bytes(plan.get()) + 2 * m.tree->n * R * int64_t(sizeof(float));
-            if (need > budget) {
-                for (Request *rq : batch) {
-                    rq->status = BBFMM_ERR_BUDGET;
-                    rq->error = "request does not fit the HBM budget";
-                    rq->done = true;
-                    rq->t_admit = rq->t_done = now_s();
-                }
-                cv_done.notify_all();
-                return true;     // consumed (rejected)
+        bool reject = false;
+        Entry *e = acquire(mdl, R, &reject);
+        if (reject) {
+            for (Request *rq : batch) {
+                rq->status = BBFMM_ERR_BUDGET;
+                rq->error = "request does not fit the HBM budget";
+                rq->done = true;
+                rq->t_admit = rq->t_done = now_s();
             }
-            // idle slots give back their cached plans before the batch waits
-            for (size_t q = 0; q < slots.size() && in_use + need > budget; ++q) {
-                Slot &o = slots[q];
-                if (q == k || o.busy || o.plan == nullptr) continue;
-                plan_destroy(o.plan);
-                o.plan = nullptr;
-                o.sig.release();
-                o.phi.release();
-                in_use -= o.bytes;
-                o.bytes = 0;
-                o.model = -1;
-                o.R = 0;
-            }
-            if (in_use + need > budget) return false;
-            s.sig.alloc(m.tree->n * R);
-            s.phi.alloc(m.tree->n * R);
-            s.plan = plan.release();
-            s.bytes = need;
-            s.model = mdl;
-            s.R = R;
-            in_use += need;
+            cv_done.notify_all();
+            return true;     // consumed (rejected)
         }
-        const int64_t n = m.tree->n;
+        if (e == nullptr) return false;
+        const int64_t n = models[mdl].tree->n;
         const double t = now_s();
         int c0 = 0;
         for (Request *rq : batch) {
-            k_pack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(rq->sigma, n, int(rq->r), s.sig.p, R, c0);
+            k_pack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(rq->sigma, n, int(rq->r), e->sig.p, R, c0);
             c0 += int(rq->r);
         }
-        if (c0 < R) k_zero_cols<<<grid(n * (R - c0)), kThreads, 0, s.stream>>>(n, s.sig.p, R, c0);
+        if (c0 < R) k_zero_cols<<<grid(n * (R - c0)), kThreads, 0, s.stream>>>(n, e->sig.p, R, c0);
         BB_LAUNCH_CHECK();
-        plan_execute_impl(s.plan, s.sig.p, s.phi.p, s.stream);
+        plan_execute_impl(e->plan, e->sig.p, e->phi.p, s.stream);
         c0 = 0;
         for (Request *rq : batch) {
-            k_unpack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(s.phi.p, n, R, c0, rq->phi, int(rq->r));
+            k_unpack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(e->phi.p, n, R, c0, rq->phi, int(rq->r));
             c0 += int(rq->r);
             rq->t_admit = t;
-            rq->batch_r = c0;       // overwritten below with the batch total
             rq->slot = int(k);
         }
         BB_LAUNCH_CHECK();
         for (Request *rq : batch) rq->batch_r = c0;
         BB_HIP(hipEventRecord(s.done, s.stream));
+        e->busy = true;
+        e->last_use = ++tick;
+        s.entry = e;
         s.batch = batch;
         s.busy = true;
         return true;
@@ -250,13 +298,9 @@ struct Server {
                 }
                 int R = 1;
                 while (R < tot) R *= 2;
-                // prefer a free slot that already holds this (model, R) plan
                 int pick = -1;
                 for (size_t k = 0; k < slots.size(); ++k)
-                    if (!slots[k].busy && slots[k].model == mdl && slots[k].R == R) { pick = int(k); break; }
-                if (pick < 0)
-                    for (size_t k = 0; k < slots.size(); ++k)
-                        if (!slots[k].busy) { pick = int(k); break; }
+                    if (!slots[k].busy) { pick = int(k); break; }
                 if (pick >= 0) {
                     bool ok = false;
                     try {

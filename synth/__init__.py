@@ -154,6 +154,21 @@ def serving_tree(i: int) -> Workload:
                     max_depth=7)
 
 
+SERVING_R = (1, 4, 16, 32)
+
+
+def serving_requests(n_req: int = 2000, seed: int = 5):
+    """Request stream of the serving mix: tree index uniform over the 8
+    trees, r uniform over SERVING_R, and unit-rate exponential inter-arrival
+    gaps (divide by the arrival rate lambda to get seconds).  Returns
+    (tree (n_req,) int, r (n_req,) int, gap (n_req,) float64)."""
+    rng = np.random.default_rng(seed)
+    tree = rng.integers(0, len(SERVING_SIZES), n_req)
+    r = np.asarray(SERVING_R)[rng.integers(0, len(SERVING_R), n_req)]
+    gap = rng.exponential(1.0, n_req)
+    return tree, r, gap
+
+
 def random_cloud(n: int, seed: int, r: int = 1, kind: str = "uniform"):
     """Small generic clouds for tests: returns (points f32 (n,3), sigma f32 (n,r))."""
     rng = np.random.default_rng(seed)
