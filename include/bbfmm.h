@@ -224,7 +224,9 @@ typedef struct {
     int32_t m2l_split;      /* workgroups sharing one M2L tile's 189 slots, 1..8   */
     int32_t m2l_min_waves;  /* heuristic target of M2L workgroups per CU, 1..16   */
     int32_t p2p_max_split;  /* cap on sub-lanes per P2P target, 1..64 (power of 2) */
-    int32_t reserved[5];    /* must be 0                                          */
+    int32_t p2p_mfma;       /* near field + L2P: 1 per-lane FMA kernel, 2 on MFMA  */
+                            /* (kernel values as the A operand); 0 picks by r     */
+    int32_t reserved[4];    /* must be 0                                          */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults).  The
@@ -284,10 +286,11 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  * the budget on its own fails with BBFMM_ERR_BUDGET (reported by wait).
  *   sigma, phi  device, N x r float32 (the model's N); must stay valid and
  *               untouched until wait returns.
- * Batch invariance: every server plan uses m2l_split = 2, and with the split
- * fixed the arithmetic of one column does not depend on the other columns
- * or on R, so a request's phi is bit-identical to bbfmm_plan_execute of a
- * lone plan for that request with m2l_split = 2, whatever batch it ran in.
+ * Batch invariance: every server plan uses m2l_split = 2 and p2p_mfma = 2,
+ * and with these fixed the arithmetic of one column does not depend on the
+ * other columns or on R, so a request's phi is bit-identical to
+ * bbfmm_plan_execute of a lone plan for that request with the same two
+ * options, whatever batch it ran in.
  * Trees and operators must outlive the server.
  */
 typedef struct bbfmm_server bbfmm_server;

@@ -61,7 +61,8 @@ class RequestStats(ctypes.Structure):
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
-                ("p2p_max_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("p2p_max_split", ctypes.c_int32), ("p2p_mfma", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 _lib_handle = None
@@ -210,7 +211,7 @@ class Plan:
     """Reusable matvec for a fixed (tree, ops, r); owns its workspace."""
 
     def __init__(self, tree: Tree, ops: Ops, r: int, **options):
-        """options: m2l_split, m2l_min_waves, p2p_max_split (0 = heuristic)."""
+        """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma (0 = heuristic)."""
         h = _VP()
         opt = PlanOptions()
         for k, v in options.items():

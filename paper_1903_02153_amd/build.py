@@ -25,7 +25,10 @@ SOURCES = ["api.hip", "primitives.hip", "tree_build.hip", "precompute.hip", "mat
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
-EXTRA = {"tree_build.hip": ["-ffp-contract=off"]}
+# MFMA accumulators in VGPRs: without this the register allocator may keep
+# them in VGPRs across loops and copy them to AGPRs around every MFMA.
+MFMA_VGPR = ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form=1"]
+EXTRA = {"tree_build.hip": ["-ffp-contract=off"], "matvec.hip": MFMA_VGPR}
 
 
 def _compile(src: str) -> str:

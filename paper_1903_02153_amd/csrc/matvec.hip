@@ -88,7 +88,7 @@ __device__ inline float kernel_eval(float dx, float dy, float dz, float ia, floa
     if constexpr (KID == BBFMM_K_INV_R) {
         return r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
     } else if constexpr (KID == BBFMM_K_EXP) {
-        return __expf(-__fsqrt_rn(r2) * ia);
+        return __expf(-__builtin_amdgcn_sqrtf(r2) * ia);   // v_sqrt_f32: 1 ulp, no denormal rescaling
     } else if constexpr (KID == BBFMM_K_GAUSS) {
         return __expf(-r2 * ia2);
     } else {
@@ -101,13 +101,14 @@ __device__ inline float kernel_eval(float dx, float dy, float dz, float ia, floa
 }
 
 // ------------------------------------------------------------ gather ----
+// sig_s[i][c] = sigma[perm[i]][c] for c < r, 0 for r <= c < ld
 __global__ void __launch_bounds__(kThreads)
-k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, float *sig_s) {
+k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, int ld, float *sig_s) {
     const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (g >= n * r) return;
-    const int64_t i = g / r;
-    const int c = int(g % r);
-    sig_s[g] = sigma[int64_t(perm[i]) * r + c];
+    if (g >= n * ld) return;
+    const int64_t i = g / ld;
+    const int c = int(g % ld);
+    sig_s[g] = c < r ? sigma[int64_t(perm[i]) * r + c] : 0.f;
 }
 
 // ----------------------------------------------------- up / down ----
@@ -126,7 +127,8 @@ struct NodeIdx {
 template <int N>
 __global__ void __launch_bounds__(64)
 k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int r, int mp, float *M) {
+      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int ld, int r, int mp,
+      float *M) {
     constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
     __shared__ float lv[64][3][N];
     __shared__ float sg[64];
@@ -157,7 +159,7 @@ k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
 #pragma unroll
                 for (int k = 0; k < N; ++k) lv[lane][d][k] = l[k];
             }
-            sg[lane] = sig_s[int64_t(p0 + lane) * r + c];
+            sg[lane] = sig_s[int64_t(p0 + lane) * ld + c];
         }
         __syncthreads();
 #pragma unroll
@@ -421,6 +423,36 @@ k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *B
 // of four consecutive MFMAs is permuted identically for A and B so each lane
 // reads 4 consecutive K values with one 16-byte load.
 constexpr int kM2LCols = 64;
+constexpr int kMaskWords = (kSlots + 31) / 32;
+
+// Visited slots of one workgroup: the set bits of the tile's mask within
+// [jlo, jhi), in ascending order, as slot index and transfer-table index.
+// Returns their number.  Called by all threads; ends with a barrier.
+__device__ inline int tile_slot_list(const uint32_t *mask, int jlo, int jhi, const int32_t *slot_t,
+                                     uint8_t *sl, int16_t *st) {
+    uint32_t m[kMaskWords];
+    int before[kMaskWords + 1];
+    before[0] = 0;
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) {
+        const int lo = max(jlo - 32 * w, 0), hi = min(jhi - 32 * w, 32);
+        uint32_t range = 0;
+        if (hi > lo) range = (hi - lo == 32 ? 0xffffffffu : ((1u << (hi - lo)) - 1u)) << lo;
+        m[w] = mask[w] & range;
+        before[w + 1] = before[w] + __popc(m[w]);
+    }
+    const int j = threadIdx.x;
+    if (j < kSlots) {
+        const int w = j >> 5, b = j & 31;
+        if ((m[w] >> b) & 1u) {
+            const int q = before[w] + __popc(m[w] & ((1u << b) - 1u));
+            sl[q] = uint8_t(j);
+            st[q] = int16_t(slot_t[j]);
+        }
+    }
+    __syncthreads();
+    return before[kMaskWords];
+}
 
 struct M2LLevel {
     const float *Mh;
@@ -435,6 +467,7 @@ struct M2LLevel {
 struct M2LArgs {
     M2LLevel lv[kMaxLevels];
     const int32_t *tiles;       // [ntiles][4]: level, octant, first in oct_cells, count
+    const uint32_t *masks;      // [ntiles][kMaskWords]: slots with a source in the tile
     const int32_t *tables;      // slot_t[8][189] at offset 3 * 316
     int r, rc, tpt;
     int nsplit;                 // the 189 slots are split over this many workgroups
@@ -456,6 +489,14 @@ __device__ inline int xcd_tile(int bid, int nblocks) {
 // buffer after the MFMAs, followed by the step's only barrier.  The source
 // index of slot j+3 is fetched during the last step of slot j into the
 // three-deep ring entry that slot j no longer needs.
+//
+// Only the slots in which some target of the tile has a source are visited
+// (a per-tile 189-bit mask made when the plan is built; a slot without a
+// source would add exact zeros).  The slot range of a split is fixed in
+// slot space, so which products land in which partial sum does not depend
+// on how targets are grouped into tiles.  The last K chunk of a rank that
+// is not a multiple of 64 issues only its nonzero 16-deep MFMA blocks, and
+// waves whose 16 rows lie past the rank issue no MFMAs.
 __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     constexpr int ldb = 64 + 4;
     __shared__ float Bs[2][kM2LCols * ldb];
@@ -463,11 +504,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const int tid = threadIdx.x, lane = tid & 63;
     // wave-uniform, so that per-wave conditions compile to scalar branches
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    __shared__ uint8_t sl[kSlots];
+    __shared__ int16_t st[kSlots];
     const int vb = xcd_tile(blockIdx.x, gridDim.x);
     const int split = vb % g.nsplit;
-    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[vb / g.nsplit];
+    const int tix = vb / g.nsplit;
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevel &L = g.lv[tile.x];
-    const int jbeg = split * kSlots / g.nsplit, jend = (split + 1) * kSlots / g.nsplit;
     const int o = tile.y, start = tile.z, cnt = tile.w;
     const int kp = L.kp;
     if (int(blockIdx.y) * 64 >= kp) return;       // row group beyond this level's rank
@@ -477,16 +520,20 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const int rhs0 = blockIdx.z * rc;
     const int row0 = blockIdx.y * 64 + wave * 16;
     const bool active = row0 < kp;
-    const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
     const int nkc = (kp + 63) / 64;
-    const int nsteps = (jend - jbeg) * nkc;
+    // visited slots of this split, compacted: index q runs over [0, jend)
+    const int jbeg = 0;
+    const int jend = tile_slot_list(g.masks + int64_t(tix) * kMaskWords, split * kSlots / g.nsplit,
+                                    (split + 1) * kSlots / g.nsplit,
+                                    g.tables + 3 * kNumT + o * kSlots, sl, st);
+    const int nsteps = jend * nkc;
     (void)lane;
 
     if (tid < kM2LCols) {
         const int a = tid < cnt ? L.oct_cells[start + tid] : -1;
         tgt[tid] = a;
         for (int q = jbeg; q < min(jbeg + 3, jend); ++q)
-            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
+            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + sl[q]] : -1;
     }
     __syncthreads();
 
@@ -533,7 +580,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const float *Arow = L.C32 + int64_t(active ? row0 + (lane & 15) : 0) * kp + 4 * (lane >> 4);
     auto load_a = [&](int j, int kc, float4 *areg) {
         const int nkb = min(64, kp - kc * 64) / 16;
-        const float *A = Arow + int64_t(slot_t[j]) * kp * kp + kc * 64;
+        const float *A = Arow + int64_t(st[j]) * kp * kp + kc * 64;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             const bool ok = active && kb < nkb;    // wave-uniform
@@ -546,10 +593,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     v4f acc[4];
     for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
     float4 breg[4], a0[4], a1[4];
-    load_b(jbeg, 0, breg);
-    store_b(0, breg);
-    load_a(jbeg, 0, a0);
-    __syncthreads();
     int32_t itab_next = -1;
     int j = jbeg, kc = 0;
     // One step: prefetch step s+1 (sources into breg, C_t rows into anxt,
@@ -566,15 +609,17 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
             load_b(j1, kc1, breg);
             load_a(j1, kc1, anxt);
             const int a = tgt[tid & 63];
-            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + min(j + 3, kSlots - 1)];
+            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + sl[min(j + 3, jend - 1)]];
             itab_next = a >= 0 ? v : -1;
         }
-        // Straight-line MFMA block: a K chunk shorter than 64 (the tail of a
-        // rank that is not a multiple of 64) multiplies zeros in both
-        // operands, and idle waves (rows past the rank) multiply zero A.
+        // MFMA block: the 16-deep K blocks of this chunk that hold nonzero
+        // rank (the zero-padded tail of a rank is skipped); waves whose rows
+        // lie past the rank skip it entirely.  Both conditions are uniform.
+        const int nkb = active ? min(64, kp - kc * 64) / 16 : 0;
         const float *B = Bs[s & 1] + (lane & 15) * ldb + 4 * (lane >> 4);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
+            if (kb >= nkb) break;
             float4 b4[4];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
@@ -602,16 +647,22 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     };
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
-    int s = 0;
-    for (; s + 2 < nsteps; s += 2) {
-        step(yes{}, s, a0, a1);
-        step(yes{}, s + 1, a1, a0);
-    }
-    if (s + 1 < nsteps) {
-        step(yes{}, s, a0, a1);
-        step(no{}, s + 1, a1, a0);
-    } else {
-        step(no{}, s, a0, a1);
+    if (nsteps > 0) {                    // uniform: no slot of this split has a source -> zeros
+        load_b(jbeg, 0, breg);
+        store_b(0, breg);
+        load_a(jbeg, 0, a0);
+        __syncthreads();
+        int s = 0;
+        for (; s + 2 < nsteps; s += 2) {
+            step(yes{}, s, a0, a1);
+            step(yes{}, s + 1, a1, a0);
+        }
+        if (s + 1 < nsteps) {
+            step(yes{}, s, a0, a1);
+            step(no{}, s + 1, a1, a0);
+        } else {
+            step(no{}, s, a0, a1);
+        }
     }
     if (!active) return;
     for (int cb = 0; cb < 4; ++cb) {
@@ -649,6 +700,7 @@ struct M2LLevelLP {
 struct M2LArgsLP {
     M2LLevelLP lv[kMaxLevels];
     const int32_t *tiles;
+    const uint32_t *masks;
     const int32_t *tables;
     int r, rc, tpt;
     int nsplit;
@@ -666,13 +718,15 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     __shared__ uint4 Bstore[2][X3 ? 2 : 1][kM2LCols * ldb / 8];
     __shared__ float Bsc[2][kM2LCols];
     __shared__ int32_t tgt[kM2LCols], srcs[3][kM2LCols];
+    __shared__ uint8_t sl[kSlots];
+    __shared__ int16_t st[kSlots];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int vb = xcd_tile(blockIdx.x, gridDim.x);
     const int split = vb % g.nsplit;
-    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[vb / g.nsplit];
+    const int tix = vb / g.nsplit;
+    const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevelLP &L = g.lv[tile.x];
-    const int jbeg = split * kSlots / g.nsplit, jend = (split + 1) * kSlots / g.nsplit;
     const int o = tile.y, start = tile.z, cnt = tile.w;
     const int kp = L.kp;
     if (int(blockIdx.y) * 64 >= kp) return;
@@ -681,15 +735,18 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     const int rhs0 = blockIdx.z * rc;
     const int row0 = blockIdx.y * 64 + wave * 16;
     const bool active = row0 < kp;
-    const int32_t *slot_t = g.tables + 3 * kNumT + o * kSlots;
     const int nkc = (kp + 63) / 64;
-    const int nsteps = (jend - jbeg) * nkc;
+    const int jbeg = 0;
+    const int jend = tile_slot_list(g.masks + int64_t(tix) * kMaskWords, split * kSlots / g.nsplit,
+                                    (split + 1) * kSlots / g.nsplit,
+                                    g.tables + 3 * kNumT + o * kSlots, sl, st);
+    const int nsteps = jend * nkc;
 
     if (tid < kM2LCols) {
         const int a = tid < cnt ? L.oct_cells[start + tid] : -1;
         tgt[tid] = a;
         for (int q = jbeg; q < min(jbeg + 3, jend); ++q)
-            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + q] : -1;
+            srcs[q % 3][tid] = a >= 0 ? itab[int64_t(a) * kSlots + sl[q]] : -1;
     }
     __syncthreads();
 
@@ -742,7 +799,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     const int64_t arow = int64_t(active ? row0 + (lane & 15) : 0) * kp + 8 * (lane >> 4);
     auto load_a = [&](int j, int kc, uint4 *areg) {
         const int nks = min(64, kp - kc * 64) / 32;
-        const int64_t base = int64_t(slot_t[j]) * kp * kp + arow + kc * 64;
+        const int64_t base = int64_t(st[j]) * kp * kp + arow + kc * 64;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int ks = i & 1;
@@ -758,10 +815,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
     uint4 breg[NB], a0[NA], a1[NA];
     float bscale = 0.f;
-    load_b(jbeg, 0, breg, bscale);
-    store_b(0, breg, bscale);
-    load_a(jbeg, 0, a0);
-    __syncthreads();
     int32_t itab_next = -1;
     int j = jbeg, kc = 0;
     auto step = [&](auto more_c, int s, const uint4 *acur, uint4 *anxt) {
@@ -770,20 +823,23 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
         if (kc1 == nkc) { kc1 = 0; ++j1; }
         const bool new_slot = MORE && kc1 == 0 && j + 3 < jend;
         float cinv = 0.f;
-        if constexpr (!X3) cinv = L.Cinv[slot_t[j]];
+        if constexpr (!X3) cinv = L.Cinv[st[j]];
         if constexpr (MORE) {
             load_b(j1, kc1, breg, bscale);
             load_a(j1, kc1, anxt);
             const int a = tgt[tid & 63];
-            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + min(j + 3, kSlots - 1)];
+            const int32_t v = itab[int64_t(a >= 0 ? a : 0) * kSlots + sl[min(j + 3, jend - 1)]];
             itab_next = a >= 0 ? v : -1;
         }
+        // 32-deep K blocks holding nonzero rank; none for waves past the rank
+        const int nks = active ? min(64, kp - kc * 64) / 32 : 0;
         const uint4 *Bh = Bstore[s & 1][0];
         const int bbase = ((lane & 15) * ldb + 8 * (lane >> 4)) / 8;
         if constexpr (X3) {
             const uint4 *Bl = Bstore[s & 1][1];
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
+                if (ks >= nks) break;
                 v8bf bh[4], bl[4];
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
@@ -802,12 +858,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
                 for (int cb = 0; cb < 4; ++cb)
                     acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[cb], 0, 0, 0);
             }
-        } else {
+        } else if (nks > 0) {
             v4f part[4];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) part[cb] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
+                if (ks >= nks) break;
                 const v8h a16 = __builtin_bit_cast(v8h, acur[ks]);
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
@@ -831,16 +888,22 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     };
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
-    int s = 0;
-    for (; s + 2 < nsteps; s += 2) {
-        step(yes{}, s, a0, a1);
-        step(yes{}, s + 1, a1, a0);
-    }
-    if (s + 1 < nsteps) {
-        step(yes{}, s, a0, a1);
-        step(no{}, s + 1, a1, a0);
-    } else {
-        step(no{}, s, a0, a1);
+    if (nsteps > 0) {
+        load_b(jbeg, 0, breg, bscale);
+        store_b(0, breg, bscale);
+        load_a(jbeg, 0, a0);
+        __syncthreads();
+        int s = 0;
+        for (; s + 2 < nsteps; s += 2) {
+            step(yes{}, s, a0, a1);
+            step(yes{}, s + 1, a1, a0);
+        }
+        if (s + 1 < nsteps) {
+            step(yes{}, s, a0, a1);
+            step(no{}, s + 1, a1, a0);
+        } else {
+            step(no{}, s, a0, a1);
+        }
     }
     if (!active) return;
     for (int cb = 0; cb < 4; ++cb) {
@@ -979,12 +1042,242 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         if (c < nr) out[c] = acc[c];
 }
 
+// -------------------------------------------- L2P + P2P on MFMA ----
+// For a block of right-hand sides the near field is a product,
+// phi[i][c] += sum_j K(x_i, y_j) sigma[j][c].  One wave takes up to 64
+// targets of a leaf (four 16-row blocks) and 16 NCB columns.  Each
+// v_mfma_f32_16x16x4f32 multiplies a 16 x 4 block of kernel values, which
+// lane i + 16 k evaluates itself (target i, source k) straight into its A
+// operand, by the 4 x 16 block of the sources' sigma staged in LDS, so one
+// kernel evaluation serves 16 NCB columns.  The far field (L2P) is the
+// same product with the Lagrange basis S[i][node] in place of K and the
+// leaf's local expansion F in place of sigma, accumulated first into the
+// same registers.  A column's arithmetic does not depend on the other
+// columns, on NCB or on r.
+template <int NCB>
+struct P2PMfmaCap {   // source records per LDS pass (coordinates + NCB x 16 sigma)
+    static constexpr int value = NCB == 1 ? 128 : 64;
+};
+
+template <int KID, int NCB, int NRB>
+__global__ void __launch_bounds__(64)
+k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
+           const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
+           const int32_t *work, const float *sig_s, int ld, int r, float ia, float ia2,
+           const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
+    constexpr int CW = 16 * NCB;            // columns of this wave
+    constexpr int SST = CW == 16 ? 16 : CW + 16;   // = 16 mod 32: rows k, k+1 on disjoint banks
+    constexpr int CAP = P2PMfmaCap<NCB>::value;
+    constexpr int RPL = CAP / 64;           // staged records per lane (coordinates)
+    constexpr int QPR = CW / 4;             // 16-byte sigma pieces per record
+    constexpr int SPL = CAP * QPR / 64;     // sigma pieces per lane
+    static_assert(CAP * SST >= 4 * 16 * 3 * kMaxOrder, "Lagrange values share the sigma buffer");
+    __shared__ float4 sp[CAP];
+    __shared__ __align__(16) float ss[CAP * SST];
+    __shared__ int32_t sidx[CAP];
+    __shared__ int16_t ntab[kMaxOrder * kMaxOrder * kMaxOrder];
+    // Lagrange values of the targets, [4][16][3 kMaxOrder]; used before the
+    // first staging pass, whose barrier retires them
+    float (*Ls)[16][3 * kMaxOrder] = reinterpret_cast<float (*)[16][3 * kMaxOrder]>(ss);
+    const int lane = threadIdx.x, row = lane & 15, kq = lane >> 4;
+    const int a = work[2 * blockIdx.x], t0 = work[2 * blockIdx.x + 1];
+    const int tend = pe[a];
+    const int col0 = blockIdx.y * CW;
+    float tx[NRB], ty[NRB], tz[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+        const int ti = t0 + 16 * rb + row;
+        const int tc = ti < tend ? ti : t0;   // rows past the leaf repeat a target; not written
+        tx[rb] = xs[tc];
+        ty[rb] = ys[tc];
+        tz[rb] = zs[tc];
+    }
+    v4f acc[NRB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    if (FL != nullptr) {
+        const int n = cc.n, m = n * n * n;
+        for (int i = lane; i < m; i += 64)
+            ntab[i] = int16_t((i % n) | ((i / n) % n) << 4 | (i / (n * n)) << 8);
+        if (kq == 0) {
+            const uint64_t key = keys[a];
+            float chi[3], clo[3];
+            for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
+            for (int rb = 0; rb < NRB; ++rb) {
+                const float p3[3] = {tx[rb], ty[rb], tz[rb]};
+                for (int d = 0; d < 3; ++d) {
+                    float l[kMaxOrder];
+                    lagrange(cc, local_coord(p3[d], chi[d], clo[d], geo.inv_h), l);
+                    for (int q = 0; q < n; ++q) Ls[rb][row][d * kMaxOrder + q] = l[q];
+                }
+            }
+        }
+        __syncthreads();
+        const float *Fa = FL + int64_t(a) * r * mp;
+        int64_t fcol[NCB];
+        float fw[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int c = col0 + cb * 16 + row;
+            fw[cb] = c < r ? 1.f : 0.f;        // F is finite: 0 * v == 0
+            fcol[cb] = int64_t(c < r ? c : 0) * mp;
+        }
+        // U node steps per batch: their F loads are issued together
+        constexpr int U = 4;
+        for (int nb = 0; nb < m; nb += 4 * U) {
+            float bv[U][NCB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int node = nb + 4 * u + kq;
+                const int nd = node < m ? node : 0;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) bv[u][cb] = Fa[fcol[cb] + nd] * fw[cb];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int node = nb + 4 * u + kq;
+                const bool nok = node < m;
+                const int code = ntab[nok ? node : 0];
+                const int k1 = code & 15, k2 = (code >> 4) & 15, k3 = code >> 8;
+                float sv[NRB];
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) {
+                    const float *L3 = Ls[rb][row];
+                    const float v = L3[k1] * L3[kMaxOrder + k2] * L3[2 * kMaxOrder + k3];
+                    sv[rb] = nok ? v : 0.f;
+                }
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sv[rb], bv[u][cb], acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+
+    // Near field over the neighbour leaves, staged in LDS passes of CAP
+    // records.  Passes are software-pipelined: the global loads of pass p+1
+    // are in flight in registers while pass p is multiplied out of LDS.
+    const int q1 = nbr_off[a + 1];
+    int q = nbr_off[a], off = 0;
+    float cx[RPL], cy[RPL], cz[RPL];
+    float4 sv[SPL];
+    // source indices of the next pass into sidx, then its loads into registers
+    auto fetch = [&]() -> int {
+        int cnt_all = 0;
+        while (q < q1 && cnt_all < CAP) {
+            const int b = nbr_idx[q];
+            const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - cnt_all);
+            for (int e = lane; e < cnt; e += 64) sidx[cnt_all + e] = sb + e;
+            cnt_all += cnt;
+            if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int e = lane + 64 * u;
+            const int src = e < cnt_all ? sidx[e] : 0;
+            cx[u] = xs[src];
+            cy[u] = ys[src];
+            cz[u] = zs[src];
+        }
+#pragma unroll
+        for (int u = 0; u < SPL; ++u) {
+            const int g = lane + 64 * u, e = g / QPR, part = g % QPR;
+            const int src = e < cnt_all ? sidx[e] : 0;
+            sv[u] = *reinterpret_cast<const float4 *>(sig_s + int64_t(src) * ld + col0 + 4 * part);
+        }
+        return cnt_all;
+    };
+    // the fetched records into LDS; records past cnt (the pad to a multiple of 4) are zero
+    auto publish = [&](int cnt) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int e = lane + 64 * u;
+            sp[e] = e < cnt ? make_float4(cx[u], cy[u], cz[u], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < SPL; ++u) {
+            const int g = lane + 64 * u, e = g / QPR, part = g % QPR;
+            const float w = e < cnt ? 1.f : 0.f;       // sigma is finite: 0 * v == 0
+            *reinterpret_cast<float4 *>(&ss[e * SST + 4 * part]) =
+                make_float4(sv[u].x * w, sv[u].y * w, sv[u].z * w, sv[u].w * w);
+        }
+    };
+    __syncthreads();                    // Lagrange values (in ss) are consumed
+    int cnt = q < q1 ? fetch() : 0;
+    while (cnt > 0) {
+        publish(cnt);
+        __syncthreads();
+        const int npad = (cnt + 3) & ~3;
+        cnt = q < q1 ? fetch() : 0;     // loads of the next pass overlap the products below
+        for (int s0 = 0; s0 < npad; s0 += 4) {
+            const float4 sq = sp[s0 + kq];
+            float bv[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bv[cb] = ss[(s0 + kq) * SST + cb * 16 + row];
+            float kv[NRB];
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+                kv[rb] = kernel_eval<KID>(tx[rb] - sq.x, ty[rb] - sq.y, tz[rb] - sq.z, ia, ia2);
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+        }
+        __syncthreads();                // this pass is consumed before the next publish
+    }
+    // D[i][j] sits in lane j + 16 (i / 4), register i % 4
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ti = t0 + 16 * rb + 4 * kq + v;
+            if (ti >= tend) continue;
+            float *out = phi + int64_t(perm[ti]) * r;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int c = col0 + cb * 16 + row;
+                if (c < r) out[c] = acc[rb][cb][v];
+            }
+        }
+    }
+}
+
 inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
 
 }  // namespace
 
 // -------------------------------------------------------------- plan ----
 constexpr int kTimingRing = 64;
+constexpr int kP2PMfmaMinR = 4;         // r from which the near field runs on MFMA by default
+
+struct MaskArgs {
+    const int32_t *itab[kMaxLevels];
+    const int32_t *oct_cells[kMaxLevels];
+};
+
+// masks[tile] bit j = some target of the tile has a source in slot j
+__global__ void __launch_bounds__(kThreads) k_tile_masks(const int32_t *tiles, MaskArgs a, uint32_t *masks) {
+    __shared__ uint32_t words[kMaskWords];
+    const int4 tile = reinterpret_cast<const int4 *>(tiles)[blockIdx.x];
+    if (threadIdx.x < kMaskWords) words[threadIdx.x] = 0u;
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j < kSlots) {
+        const int32_t *itab = a.itab[tile.x];
+        const int32_t *cells = a.oct_cells[tile.x] + tile.z;
+        bool any = false;
+        for (int c = 0; c < tile.w && !any; ++c) any = itab[int64_t(cells[c]) * kSlots + j] >= 0;
+        if (any) atomicOr(&words[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaskWords) masks[int64_t(blockIdx.x) * kMaskWords + threadIdx.x] = words[threadIdx.x];
+}
 
 struct Plan {
     const bbfmm_tree *tree = nullptr;
@@ -993,11 +1286,16 @@ struct Plan {
     int rc_m2l = 1, tpt = 64;           // M2L column tile: tpt targets x rc_m2l rhs
     int nsplit = 1;                     // M2L slot split (partial F^ summed in decompression)
     int rc_p2p = 1;
-    DBuf<float> sig_s;
+    bool p2p_mfma = false;              // near field + L2P on MFMA (k_p2p_mfma)
+    int ncb_p2p = 1;                    // its 16-column blocks per wave
+    int mfma_off[5] = {0};              // its work items with 1..4 row blocks: [off[i], off[i+1])
+    DBuf<float> sig_s;                  // sigma in tree order, [N][ld_s]
+    int ld_s = 1;                       // r, or whole MFMA column blocks (zero padded)
     DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
     DBuf<uint16_t> Mh16[kMaxLevels], Ml16[kMaxLevels];   // 16-bit M2L operand formats
     DBuf<float> Msinv[kMaxLevels];                       // fp16 block scales
     DBuf<int32_t> tiles;                // all M2L tiles of all levels
+    DBuf<uint32_t> masks;               // per tile: slots in which some target has a source
     int ntiles = 0, max_kp = 0;
     DBuf<int32_t> work;
     int nwork = 0;
@@ -1031,7 +1329,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.p2p_max_split >= 0 && op.p2p_max_split <= 64 &&
                    (op.p2p_max_split & (op.p2p_max_split - 1)) == 0,
                "p2p_max_split must be 0 or a power of two <= 64");
-    for (int i = 0; i < 5; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
+    BB_REQUIRE(op.p2p_mfma >= 0 && op.p2p_mfma <= 2, "p2p_mfma must be 0, 1 or 2");
+    for (int i = 0; i < 4; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -1044,7 +1343,10 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     p->tpt = kM2LCols / p->rc_m2l;
     p->rc_p2p = 1;
     while (p->rc_p2p < r && p->rc_p2p < 64) p->rc_p2p *= 2;
-    p->sig_s.alloc(t->n * r);
+    p->p2p_mfma = op.p2p_mfma == 0 ? r >= kP2PMfmaMinR : op.p2p_mfma == 2;
+    p->ncb_p2p = r <= 16 ? 1 : (r <= 32 ? 2 : 4);
+    p->ld_s = p->p2p_mfma ? int(16 * p->ncb_p2p * ceil_div(r, 16 * p->ncb_p2p)) : int(r);
+    p->sig_s.alloc(t->n * p->ld_s);
     int64_t ws = p->sig_s.bytes();
     std::vector<int32_t> tl;
     for (int lvl = 2; lvl <= L; ++lvl) {
@@ -1094,10 +1396,41 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     if (p->ntiles) {
         p->tiles.alloc(tl.size());
         BB_HIP(hipMemcpy(p->tiles.p, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        p->masks.alloc(int64_t(p->ntiles) * kMaskWords);
+        MaskArgs ma{};
+        for (int lvl = 2; lvl <= L; ++lvl) {
+            ma.itab[lvl] = t->lv[lvl].itab.p;
+            ma.oct_cells[lvl] = t->lv[lvl].oct_cells.p;
+        }
+        k_tile_masks<<<p->ntiles, kThreads, 0, nullptr>>>(p->tiles.p, ma, p->masks.p);
+        BB_LAUNCH_CHECK();
+        BB_HIP(hipStreamSynchronize(nullptr));
+        ws += p->tiles.bytes() + p->masks.bytes();
     }
-    // P2P work items (leaf, first target, log2 S): leaves of at most 64
-    // points take one wave with 64 / next_pow2(count) sub-lanes per target
-    {
+    if (p->p2p_mfma) {
+        // MFMA near field: one wave per (leaf, up to 64 consecutive
+        // targets), grouped by the number of 16-row blocks they need
+        const LevelData &leaf = t->lv[L];
+        std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
+        BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        BB_HIP(hipMemcpy(he.data(), leaf.pe.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int nrb = 1; nrb <= 4; ++nrb) {
+            p->mfma_off[nrb - 1] = int(w.size() / 2);
+            for (int a = 0; a < leaf.C; ++a)
+                for (int s = hb[a]; s < he[a]; s += 64)
+                    if (std::min(4, (he[a] - s + 15) / 16) == nrb) {
+                        w.push_back(a);
+                        w.push_back(s);
+                    }
+        }
+        p->mfma_off[4] = int(w.size() / 2);
+        p->nwork = int(w.size() / 2);
+        p->work.alloc(w.size());
+        BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    } else {
+        // per-lane P2P work items (leaf, first target, log2 S): leaves of at
+        // most 64 points take one wave with 64 / next_pow2(count) sub-lanes
+        // per target
         const LevelData &leaf = t->lv[L];
         std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
         BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1149,6 +1482,34 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
     const LevelData &leaf = t.lv[t.leaf_level()];
     const double a = t.params.kernel_param;
     const float ia = float(1.0 / a), ia2 = float(1.0 / (a * a));
+    if (p.p2p_mfma) {
+        for (int nrb = 1; nrb <= 4; ++nrb) {
+            const int w0 = p.mfma_off[nrb - 1], nw = p.mfma_off[nrb] - w0;
+            if (nw == 0) continue;
+            dim3 g(unsigned(nw), unsigned(ceil_div(p.r, 16 * p.ncb_p2p)));
+            const int32_t *wk = p.work.p + 2 * int64_t(w0);
+#define BB_P2PM(NCB, NRB)                                                                     \
+            k_p2p_mfma<KID, NCB, NRB><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p,        \
+                leaf.pe.p, t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p, wk, p.sig_s.p,       \
+                p.ld_s, int(p.r), ia, ia2, FL, p.ops->mp, geo, p.ops->cheb, phi)
+#define BB_P2PM_R(NCB)                                                                        \
+            switch (nrb) {                                                                    \
+            case 1: BB_P2PM(NCB, 1); break;                                                   \
+            case 2: BB_P2PM(NCB, 2); break;                                                   \
+            case 3: BB_P2PM(NCB, 3); break;                                                   \
+            default: BB_P2PM(NCB, 4); break;                                                  \
+            }
+            switch (p.ncb_p2p) {
+            case 1: BB_P2PM_R(1); break;
+            case 2: BB_P2PM_R(2); break;
+            default: BB_P2PM_R(4); break;
+            }
+#undef BB_P2PM_R
+#undef BB_P2PM
+            BB_LAUNCH_CHECK();
+        }
+        return;
+    }
     dim3 g(p.nwork, unsigned(ceil_div(p.r, p.rc_p2p)));
 #define BB_P2P(RCV)                                                                          \
     k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
@@ -1263,7 +1624,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
     };
 
     mark(BBFMM_STAGE_GATHER);
-    k_gather_sigma<<<grid(t.n * r), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.sig_s.p);
+    k_gather_sigma<<<grid(t.n * p.ld_s), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.ld_s, p.sig_s.p);
     BB_LAUNCH_CHECK();
     const float *FL = nullptr;
     const int n = o.n, mp = o.mp;
@@ -1273,7 +1634,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         dim3 g(leaf.C, r);
         switch (n) {
 #define BB_P2M(NN) case NN: k_p2m<NN><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, \
-            leaf.keys.p, geo, o.cheb, p.sig_s.p, r, mp, p.M[L].p); break;
+            leaf.keys.p, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
         BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
 #undef BB_P2M
         }
@@ -1324,6 +1685,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
                                    t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
         }
         g.tiles = p.tiles.p;
+        g.masks = p.masks.p;
         g.tables = t.tables.p;
         g.r = r;
         g.rc = p.rc_m2l;
@@ -1343,6 +1705,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
                                  t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
         }
         g.tiles = p.tiles.p;
+        g.masks = p.masks.p;
         g.tables = t.tables.p;
         g.r = r;
         g.rc = p.rc_m2l;

@@ -18,13 +18,13 @@
 // used first when the budget needs room.
 //
 // Batch invariance: every plan the server makes splits the M2L slot range
-// over the same kServeSplit workgroups.  With that fixed, the arithmetic of
-// one right-hand side does not depend on the batch width R or on the other
-// columns (P2M/M2M/L2L run one wave per (cell, column), the (de)compression
-// GEMMs and the M2L accumulate each column in a fixed order, and the P2P
-// assigns sources to sub-lanes by leaf size only), so a request's phi is
-// bit-identical to a lone plan execution with m2l_split = kServeSplit,
-// whatever batch it ran in.
+// over the same kServeSplit workgroups and runs the near field on MFMA for
+// every R.  With those fixed, the arithmetic of one right-hand side does
+// not depend on the batch width R or on the other columns (P2M/M2M/L2L run
+// one wave per (cell, column), the (de)compression GEMMs, the M2L and the
+// MFMA near field accumulate each column in a fixed order), so a request's
+// phi is bit-identical to a lone plan execution with m2l_split = kServeSplit
+// and p2p_mfma = 2, whatever batch it ran in.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -197,6 +197,7 @@ struct Server {
         const Model &m = models[mdl];
         bbfmm_plan_options opt{};
         opt.m2l_split = kServeSplit;
+        opt.p2p_mfma = 2;
         struct PlanDel {
             void operator()(Plan *q) const { plan_destroy(q); }
         };

@@ -127,10 +127,17 @@ def test_deterministic_and_plan_reuse():
     c = bbfmm.matvec(gt, go, ts)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(a, c)
-    # columns are independent: one column alone equals the same column in the block
-    one = bbfmm.matvec(gt, go, ts[:, 1:2].contiguous())
+    # columns are independent: with the M2L slot split and the near-field
+    # path fixed, one column alone equals the same column of the block bit
+    # for bit (the default launch shapes depend on r)
+    fixed = dict(m2l_split=2, p2p_mfma=2)
+    blk = torch.empty_like(ts)
+    bbfmm.Plan(gt, go, 4, **fixed).execute(ts, blk)
+    col = ts[:, 1:2].contiguous()
+    one = torch.empty_like(col)
+    bbfmm.Plan(gt, go, 1, **fixed).execute(col, one)
     torch.cuda.synchronize()
-    assert torch.allclose(one[:, 0], a[:, 1], rtol=1e-6, atol=1e-6)
+    assert torch.equal(one[:, 0], blk[:, 1])
 
 
 def test_full_size_uniform_1m_sampled_rows():
@@ -172,6 +179,31 @@ def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
     err_far = np.linalg.norm(got - ref) / np.linalg.norm(far)
     print(f"precision {prec} kernel {kid} n {n}: rel err {err:.2e} (relative to far field {err_far:.2e})")
     assert err < tol
+
+
+@pytest.mark.parametrize("r", [1, 4, 20, 40, 70])
+def test_near_field_paths_agree(r):
+    """The per-lane FMA near field and the MFMA near field (kernel values as
+    the A operand, L2P as a product with the Lagrange basis) against the
+    oracle, on leaves of several hundred points (several 64-target work
+    items per leaf) and column counts that leave partial 16-column blocks."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(20000, 80 + r, r=r, kind="clustered")
+    gt, go, ot, oo = _both(pts, sig, 1, 0.2, 4, 1e-5, fixed_depth=3)
+    ref = ofmm.matvec(ot, oo, pts, sig, 1, 0.2)
+    ts = torch.from_numpy(sig).cuda()
+    outs = []
+    for path in (1, 2):
+        phi = torch.empty_like(ts)
+        bbfmm.Plan(gt, go, r, p2p_mfma=path).execute(ts, phi)
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy().astype(np.float64)
+        err = ofmm.rel_l2_cols(got, ref).max()
+        print(f"r {r} near-field path {path}: max column rel err {err:.2e}")
+        assert err < TOL
+        outs.append(got)
+    assert ofmm.rel_l2_cols(outs[0], outs[1]).max() < TOL
 
 
 def test_graph_replay_matches_eager():

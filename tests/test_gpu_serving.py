@@ -45,15 +45,16 @@ def test_mix_equals_alone_and_batches():
     reqs = [(m, sig, phi, srv.submit(ids[m], sig, phi)) for m, sig, phi in inputs]
     stats = [srv.wait(rid) for _, _, _, rid in reqs]
     torch.cuda.synchronize()
-    # Batch invariance: with the M2L slot split fixed (the server uses 2), a
-    # column's arithmetic does not depend on the batch, so every request
-    # equals a lone plan execution bit for bit.
+    # Batch invariance: with the M2L slot split and the near-field path fixed
+    # (the server uses split 2 and the MFMA near field), a column's
+    # arithmetic does not depend on the batch, so every request equals a
+    # lone plan execution bit for bit.
     lone = {}
     for (m, sig, phi, _), st in zip(reqs, stats):
         t, o = models[m][:2]
         r = sig.shape[1]
         if (m, r) not in lone:
-            lone[(m, r)] = bbfmm.Plan(t, o, r, m2l_split=2)
+            lone[(m, r)] = bbfmm.Plan(t, o, r, m2l_split=2, p2p_mfma=2)
         alone = torch.empty_like(sig)
         lone[(m, r)].execute(sig, alone)
         torch.cuda.synchronize()
