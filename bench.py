@@ -31,6 +31,28 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector (counts packed FP32)
 PEAK_HBM_GBS = 8000.0
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain device copy of known size), or None when the summary
+    is for another kernel or workload or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    if ent is None or rec.get("workload") != workload:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return (ent["fetch_kib"] * rec["fetch_scale"] + ent["write_kib"] * rec["write_scale"]) * 1024.0
+
+
 def flops_per_pair_p2p(kernel_id: int, r: int) -> int:
     """Flop convention for one kernel evaluation + accumulation: 3 sub,
     3 mul + 2 add for r^2, 1 for the kernel (rsqrt) = 9 for 1/r; exp(-r/a)
@@ -299,7 +321,8 @@ def main() -> int:
         kern, flop, peak, bound = "p2p", p2p_flop, PEAK_FP32_VECTOR_TFLOPS, "alu"
     achieved = flop / (stage_avg[kern] * 1e-3) / 1e12
     roofline = {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic("k_m2l" if kern == "m2l" else "k_p2p", w.name),
                 "flop_per_launch": flop,
                 "other": {"m2l_tflops": round(m2l_flop / (stage_avg["m2l"] * 1e-3) / 1e12, 3),
                           "p2p_tflops": round(p2p_flop / (stage_avg["p2p"] * 1e-3) / 1e12, 3)}}

@@ -88,9 +88,10 @@ __device__ inline float kernel_eval(float dx, float dy, float dz, float ia, floa
     if constexpr (KID == BBFMM_K_INV_R) {
         return r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
     } else if constexpr (KID == BBFMM_K_EXP) {
-        return __expf(-__builtin_amdgcn_sqrtf(r2) * ia);   // v_sqrt_f32: 1 ulp, no denormal rescaling
+        // v_sqrt_f32 and v_exp_f32 (1 ulp); the scale is loop-invariant
+        return __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * (ia * -1.44269504088896341f));
     } else if constexpr (KID == BBFMM_K_GAUSS) {
-        return __expf(-r2 * ia2);
+        return __builtin_amdgcn_exp2f(r2 * (ia2 * -1.44269504088896341f));
     } else {
         const float u[3] = {dx * ia, dy * ia, dz * ia};
         float p = 1.f;
@@ -1214,11 +1215,20 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
         __syncthreads();
         const int npad = (cnt + 3) & ~3;
         cnt = q < q1 ? fetch() : 0;     // loads of the next pass overlap the products below
+        // LDS operands one step ahead (the last step re-reads its own)
+        float4 sq_n = sp[kq];
+        float bv_n[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) bv_n[cb] = ss[kq * SST + cb * 16 + row];
         for (int s0 = 0; s0 < npad; s0 += 4) {
-            const float4 sq = sp[s0 + kq];
+            const float4 sq = sq_n;
             float bv[NCB];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) bv[cb] = ss[(s0 + kq) * SST + cb * 16 + row];
+            for (int cb = 0; cb < NCB; ++cb) bv[cb] = bv_n[cb];
+            const int nx = min(s0 + 4, npad - 4) + kq;
+            sq_n = sp[nx];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bv_n[cb] = ss[nx * SST + cb * 16 + row];
             float kv[NRB];
 #pragma unroll
             for (int rb = 0; rb < NRB; ++rb)
@@ -1370,13 +1380,21 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             }
         }
         ws += p->M[lvl].bytes() + p->F[lvl].bytes();
-        // M2L tiles: runs of up to tpt cells of one octant
-        for (int oc = 0; oc < 8; ++oc)
-            for (int s = t->lv[lvl].oct_off[oc]; s < t->lv[lvl].oct_off[oc + 1]; s += p->tpt) {
+        // M2L tiles: runs of up to tpt cells of one octant (Morton order
+        // within the octant), interleaved over the octants run by run, so
+        // that consecutive tiles -- which the launch deals to one XCD --
+        // cover one region of space and share their sources in that L2
+        const int *oo = t->lv[lvl].oct_off;
+        int nrun = 0;
+        for (int oc = 0; oc < 8; ++oc) nrun = std::max(nrun, int(ceil_div(oo[oc + 1] - oo[oc], p->tpt)));
+        for (int j = 0; j < nrun; ++j)
+            for (int oc = 0; oc < 8; ++oc) {
+                const int s = oo[oc] + j * p->tpt;
+                if (s >= oo[oc + 1]) continue;
                 tl.push_back(lvl);
                 tl.push_back(oc);
                 tl.push_back(s);
-                tl.push_back(std::min(p->tpt, t->lv[lvl].oct_off[oc + 1] - s));
+                tl.push_back(std::min(p->tpt, oo[oc + 1] - s));
             }
     }
     p->ntiles = int(tl.size() / 4);
