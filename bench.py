@@ -110,7 +110,7 @@ def time_plan(plan, sig, phi, steps: int, warmup: int):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
-def batched_variants(steps: int, warmup: int):
+def batched_variants(steps: int, warmup: int, tune: bool):
     """Batched mixed-precision forms against plain single-RHS FP32 on the
     two batched workloads: points x RHS/s of the single-RHS FP32 form, the
     r-column FP32 form and the r-column low-precision forms (HIP-graph
@@ -138,10 +138,11 @@ def batched_variants(steps: int, warmup: int):
 
         def run(tag, prec, r):
             ops = bbfmm.precompute_operators(tree, w.eps, prec)
-            plan = bbfmm.Plan(tree, ops, r)
-            plan.set_graph(True)
             s = sig[:, :r].contiguous()
             phi = torch.empty_like(s)
+            opts = bbfmm.autotune(tree, ops, s, phi, reps=3)[0] if tune else {}
+            plan = bbfmm.Plan(tree, ops, r, **opts)
+            plan.set_graph(True)
             n_steps = steps if r > 1 else max(steps, 10)
             lat = time_plan(plan, s, phi, n_steps, warmup)
             med = float(np.median(lat))
@@ -149,6 +150,7 @@ def batched_variants(steps: int, warmup: int):
                                  "ms_median": round(med, 4),
                                  "ms_p99": round(float(np.percentile(lat, 99)), 4),
                                  "points_rhs_per_s": w.n * r / (med * 1e-3),
+                                 "plan_options": opts or "heuristic",
                                  "ranks": {lvl: ops.rank(lvl) for lvl in range(2, info.depth)}}
             plan.close()
             return phi
@@ -255,6 +257,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in launch-shape heuristic instead of bbfmm_plan_autotune")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the batched mixed-precision comparison (clustered-2M, slab-1M)")
     ap.add_argument("--no-serving", action="store_true", help="skip the 8-tree serving mix")
@@ -283,7 +287,10 @@ def main() -> int:
     tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
                             fixed_depth=w.fixed_depth)
     ops = bbfmm.precompute_operators(tree, w.eps, bbfmm.M2L_FP32)
-    plan = bbfmm.Plan(tree, ops, w.r)
+    opts = {}
+    if not args.no_autotune:     # launch shapes only; outside the timed region
+        opts, _ = bbfmm.autotune(tree, ops, sig, phi, reps=5)
+    plan = bbfmm.Plan(tree, ops, w.r, **opts)
     info = tree.info()
     L = info.depth - 1
 
@@ -334,7 +341,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.n, "r": w.r, "kernel": "1/r", "order": w.order,
                    "depth": info.depth, "leaf_cells": info.cells[L], "svd_eps": w.eps,
-                   "ranks": ranks, "m2l": "fp32-mfma", "parallelism": "single-gpu"},
+                   "ranks": ranks, "m2l": "fp32-mfma", "parallelism": "single-gpu",
+                   "plan_options": opts or "heuristic"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
@@ -348,7 +356,8 @@ def main() -> int:
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
     if not args.no_variants:
-        out["batched_variants"] = batched_variants(max(5, min(args.steps, 20)), 2)
+        out["batched_variants"] = batched_variants(max(5, min(args.steps, 20)), 2,
+                                                   not args.no_autotune)
     if not args.no_serving:
         out["serving"] = serving_mix(args.serving_requests, args.serving_budget_gib,
                                      args.serving_load)

@@ -274,6 +274,27 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
                                     int32_t reset);
 
 /*
+ * Launch-shape autotuner for a (tree, operators, r): times whole products
+ * on the caller's data and returns the fastest options found.  Candidates,
+ * by coordinate descent from the built-in heuristic: M2L slot split 1..4;
+ * then the near-field kernel (per-lane FMA or MFMA); then, for the
+ * per-lane kernel, the sub-lane cap 4, 8 or 16.  Each candidate runs one
+ * untimed product and `reps` timed ones (HIP events on `stream`); its
+ * time is the median.  Options only change launch shapes (and with them
+ * the floating-point summation order), never the arithmetic precision.
+ *   sigma, phi  device, N x r float32; phi is overwritten by every trial.
+ *   reps        1..100.
+ *   best        out: the chosen options (m2l_split, p2p_mfma and
+ *               p2p_max_split explicit).
+ *   best_ms     out (may be NULL): its median milliseconds per product.
+ * Allocates and frees one plan workspace per candidate; synchronizes
+ * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *tree, const bbfmm_ops *ops, int64_t r,
+                                 const float *sigma, float *phi, void *stream, int32_t reps,
+                                 bbfmm_plan_options *best, double *best_ms);
+
+/*
  * Serving loop (continuous batching).  A server keeps any number of built
  * (tree, operators) models, accepts matvec requests of any model and r, and
  * a scheduler thread groups the pending requests of one model (arrival

@@ -86,6 +86,8 @@ SIGNATURES = {
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
     "bbfmm_plan_set_graph": (_I32, [_VP, _I32]),
     "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+    "bbfmm_plan_autotune": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _I32, ctypes.POINTER(PlanOptions),
+                                   ctypes.POINTER(ctypes.c_double)]),
     "bbfmm_server_create": (_I32, [_I64, _I32, _I32, _PVP]),
     "bbfmm_server_add": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I32)]),
     "bbfmm_server_submit": (_I32, [_VP, _I32, _VP, _I64, _VP, ctypes.POINTER(ctypes.c_uint64)]),
@@ -259,6 +261,23 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
+    """Fastest launch-shape options for (tree, ops, r = sigma.shape[1]) on this
+    data (bbfmm_plan_autotune); returns (options dict for Plan, median ms)."""
+    import torch
+    _device_f32(sigma, "sigma")
+    if phi is None:
+        phi = torch.empty_like(sigma)
+    _device_f32(phi, "phi", tuple(sigma.shape))
+    best = PlanOptions()
+    ms = ctypes.c_double(0.0)
+    _check(lib().bbfmm_plan_autotune(tree.handle, ops.handle, sigma.shape[1], sigma.data_ptr(),
+                                     phi.data_ptr(), _stream_handle(stream), int(reps),
+                                     ctypes.byref(best), ctypes.byref(ms)))
+    return {"m2l_split": best.m2l_split, "p2p_max_split": best.p2p_max_split,
+            "p2p_mfma": best.p2p_mfma}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,

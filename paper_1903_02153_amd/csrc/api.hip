@@ -1,7 +1,9 @@
 // C-ABI entry points of libbbfmm (declared in include/bbfmm.h).
 // Each entry point converts internal exceptions into a bbfmm_status and a
 // thread-local message; nothing propagates across the ABI.
+#include <algorithm>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "common.h"
@@ -268,6 +270,87 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *p, double *ms, int64_t *executio
     return guarded([&] {
         BB_REQUIRE(p != nullptr, "plan is NULL");
         plan_stage_times(p->impl, ms, executions, reset != 0);
+    });
+}
+
+namespace {
+
+bool is_device_ptr(const void *ptr) {
+    hipPointerAttribute_t attr{};
+    return ptr != nullptr && hipPointerGetAttributes(&attr, ptr) == hipSuccess &&
+           (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+}
+
+// median milliseconds of `reps` products with these options (after one untimed)
+double time_options(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r, const bbfmm_plan_options &op,
+                    const float *sigma, float *phi, hipStream_t s, int reps) {
+    std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
+    p->impl = plan_create_impl(t, o, r, &op);
+    plan_execute_impl(p->impl, sigma, phi, s);
+    std::vector<hipEvent_t> ev(size_t(2 * reps), nullptr);
+    struct Events {
+        std::vector<hipEvent_t> &e;
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } guard{ev};
+    for (hipEvent_t &e : ev) BB_HIP(hipEventCreate(&e));
+    for (int i = 0; i < reps; ++i) {
+        BB_HIP(hipEventRecord(ev[2 * i], s));
+        plan_execute_impl(p->impl, sigma, phi, s);
+        BB_HIP(hipEventRecord(ev[2 * i + 1], s));
+    }
+    BB_HIP(hipEventSynchronize(ev.back()));
+    std::vector<float> ms(static_cast<size_t>(reps));
+    for (int i = 0; i < reps; ++i) BB_HIP(hipEventElapsedTime(&ms[i], ev[2 * i], ev[2 * i + 1]));
+    std::sort(ms.begin(), ms.end());
+    BB_HIP(hipStreamSynchronize(s));    // the workspace is released after the stream used it
+    return ms[size_t(reps / 2)];
+}
+
+}  // namespace
+
+bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
+                                 const float *sigma, float *phi, void *stream, int32_t reps,
+                                 bbfmm_plan_options *best, double *best_ms) {
+    return guarded([&] {
+        BB_REQUIRE(t != nullptr && o != nullptr && best != nullptr, "NULL argument");
+        BB_REQUIRE(reps >= 1 && reps <= 100, "reps must be in [1, 100]");
+        BB_REQUIRE(is_device_ptr(sigma) && is_device_ptr(phi), "sigma / phi must be device pointers");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        bbfmm_plan_options cur{};
+        double cur_ms = time_options(t, o, r, cur, sigma, phi, s, reps);   // the heuristic
+        auto consider = [&](const bbfmm_plan_options &c) {
+            const double ms = time_options(t, o, r, c, sigma, phi, s, reps);
+            if (ms < cur_ms) {
+                cur_ms = ms;
+                cur = c;
+            }
+        };
+        for (int split = 1; split <= 4; ++split) {
+            bbfmm_plan_options c = cur;
+            c.m2l_split = split;
+            consider(c);
+        }
+        for (int path = 1; path <= 2; ++path) {
+            bbfmm_plan_options c = cur;
+            c.p2p_mfma = path;
+            consider(c);
+        }
+        if (cur.p2p_mfma != 2)
+            for (int cap : {4, 8, 16}) {
+                bbfmm_plan_options c = cur;
+                c.p2p_mfma = 1;
+                c.p2p_max_split = cap;
+                consider(c);
+            }
+        // make every choice explicit: what the heuristic picked for the zeros
+        std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
+        p->impl = plan_create_impl(t, o, r, &cur);
+        plan_resolved_options(p->impl, &cur);
+        *best = cur;
+        if (best_ms) *best_ms = cur_ms;
     });
 }
 

@@ -181,6 +181,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                        const bbfmm_plan_options *opt);
 void plan_execute_impl(Plan *p, const float *sigma, float *phi, hipStream_t s);
 int64_t plan_workspace_bytes(const Plan *p);
+void plan_resolved_options(const Plan *p, bbfmm_plan_options *out);   // the choices in effect
 void plan_destroy(Plan *p);
 void plan_set_timing(Plan *p, bool on);
 void plan_set_graph(Plan *p, bool on);

@@ -1474,6 +1474,12 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
 }
 
 int64_t plan_workspace_bytes(const Plan *p) { return p->ws_bytes; }
+
+void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
+    out->m2l_split = p->nsplit;
+    out->p2p_mfma = p->p2p_mfma ? 2 : 1;
+    if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
+}
 void plan_destroy(Plan *p) { delete p; }
 
 namespace {

@@ -206,6 +206,26 @@ def test_near_field_paths_agree(r):
     assert ofmm.rel_l2_cols(outs[0], outs[1]).max() < TOL
 
 
+@pytest.mark.parametrize("r", [1, 6])
+def test_autotune_options_are_valid_and_exact(r):
+    """The autotuner returns explicit, valid options whose plan meets the
+    FP32 bar against the oracle, with a positive median time."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(30000, 90 + r, r=r, kind="clustered")
+    gt, go, ot, oo = _both(pts, sig, 0, 1.0, 5, 1e-5, fixed_depth=5)
+    ts = torch.from_numpy(sig).cuda()
+    opts, ms = bbfmm.autotune(gt, go, ts, reps=3)
+    assert ms > 0
+    assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
+    assert opts["p2p_max_split"] in (4, 8, 16)
+    phi = torch.empty_like(ts)
+    bbfmm.Plan(gt, go, r, **opts).execute(ts, phi)
+    torch.cuda.synchronize()
+    ref = ofmm.matvec(ot, oo, pts, sig, 0, 1.0)
+    assert ofmm.rel_l2_cols(phi.cpu().numpy().astype(np.float64), ref).max() < TOL
+
+
 def test_graph_replay_matches_eager():
     """HIP-graph replay of a plan equals eager execution on every replay,
     with unrelated eager work and synchronisations between replays."""
