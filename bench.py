@@ -327,12 +327,31 @@ def main() -> int:
     else:
         kern, flop, peak, bound = "p2p", p2p_flop, PEAK_FP32_VECTOR_TFLOPS, "alu"
     achieved = flop / (stage_avg[kern] * 1e-3) / 1e12
+    # the same kernel alone: a short run with the one-stream schedule (the
+    # timed region above may overlap the near field with the far field)
+    isolated = None
+    if opts.get("overlap", 1) == 2:
+        solo = bbfmm.Plan(tree, ops, w.r, **dict(opts, overlap=1))
+        for _ in range(3):
+            solo.execute(sig, phi)
+        solo.set_timing(True)
+        solo.stage_times(reset=True)
+        for _ in range(20):
+            solo.execute(sig, phi)
+        torch.cuda.synchronize()
+        sms, sn = solo.stage_times(reset=True)
+        solo.close()
+        t_iso = sms[kern] / sn
+        isolated = {"ms": round(t_iso, 4), "achieved": round(flop / (t_iso * 1e-3) / 1e12, 3),
+                    "frac": round(flop / (t_iso * 1e-3) / 1e12 / peak, 4),
+                    "note": "same plan options with the one-stream schedule, 20 launches"}
     roofline = {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic("k_m2l" if kern == "m2l" else "k_p2p", w.name),
                 "flop_per_launch": flop,
                 "other": {"m2l_tflops": round(m2l_flop / (stage_avg["m2l"] * 1e-3) / 1e12, 3),
-                          "p2p_tflops": round(p2p_flop / (stage_avg["p2p"] * 1e-3) / 1e12, 3)}}
+                          "p2p_tflops": round(p2p_flop / (stage_avg["p2p"] * 1e-3) / 1e12, 3)},
+                "isolated": isolated}
 
     out = {
         "metric": METRIC, "value": value, "unit": "points*RHS/s", "n_gpus": 1,

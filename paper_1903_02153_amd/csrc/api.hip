@@ -345,6 +345,11 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.p2p_max_split = cap;
                 consider(c);
             }
+        for (int ov = 1; ov <= 2; ++ov) {
+            bbfmm_plan_options c = cur;
+            c.overlap = ov;
+            consider(c);
+        }
         // make every choice explicit: what the heuristic picked for the zeros
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
         p->impl = plan_create_impl(t, o, r, &cur);

@@ -1258,6 +1258,55 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
     }
 }
 
+// ---------------------------------------------------------------- L2P ----
+// Far field added to phi, one thread per point (tree order):
+// phi[perm[i]][c] += sum_node S[i][node] F[leaf(i)][c][node], with the
+// separable Lagrange product summed x fastest.  Runs after the near field
+// has written phi (the overlapped schedule).
+template <int N>
+__global__ void __launch_bounds__(kThreads)
+k_l2p(const float *xs, const float *ys, const float *zs, const int32_t *pleaf, const uint64_t *keys,
+      const int32_t *perm, int64_t npts, int r, const float *FL, int mp, Geo geo, ChebConst cc,
+      float *phi) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= npts) return;
+    const int a = pleaf[i];
+    const uint64_t key = keys[a];
+    const float p3[3] = {xs[i], ys[i], zs[i]};
+    float l[3][kMaxOrder];
+    for (int d = 0; d < 3; ++d) {
+        float chi, clo;
+        center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
+        lagrange(cc, local_coord(p3[d], chi, clo, geo.inv_h), l[d]);
+    }
+    float *out = phi + int64_t(perm[i]) * r;
+    for (int c = 0; c < r; ++c) {
+        const float *f = FL + (int64_t(a) * r + c) * mp;
+        float sacc = 0.f;
+#pragma unroll
+        for (int i3 = 0; i3 < N; ++i3) {
+            float s2 = 0.f;
+#pragma unroll
+            for (int i2 = 0; i2 < N; ++i2) {
+                float s1 = 0.f;
+#pragma unroll
+                for (int i1 = 0; i1 < N; ++i1) s1 += l[0][i1] * f[(i3 * N + i2) * N + i1];
+                s2 += l[1][i2] * s1;
+            }
+            sacc += l[2][i3] * s2;
+        }
+        out[c] += sacc;
+    }
+}
+
+// pleaf[i] = leaf holding point i (tree order)
+__global__ void __launch_bounds__(kThreads)
+k_point_leaf(const int32_t *pb, const int32_t *pe, int nleaf, int32_t *pleaf) {
+    const int a = blockIdx.x * kThreads + threadIdx.x;
+    if (a >= nleaf) return;
+    for (int i = pb[a]; i < pe[a]; ++i) pleaf[i] = a;
+}
+
 inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
 
 }  // namespace
@@ -1299,6 +1348,12 @@ struct Plan {
     bool p2p_mfma = false;              // near field + L2P on MFMA (k_p2p_mfma)
     int ncb_p2p = 1;                    // its 16-column blocks per wave
     int mfma_off[5] = {0};              // its work items with 1..4 row blocks: [off[i], off[i+1])
+    // overlapped schedule: the near field on a side stream while the far
+    // field runs on the caller's stream, then L2P adds the far field
+    bool overlap = false;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    DBuf<int32_t> pleaf;                // point -> leaf (tree order), for k_l2p
     DBuf<float> sig_s;                  // sigma in tree order, [N][ld_s]
     int ld_s = 1;                       // r, or whole MFMA column blocks (zero padded)
     DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
@@ -1323,6 +1378,10 @@ struct Plan {
     const float *g_sigma = nullptr;
     float *g_phi = nullptr;
     ~Plan() {
+        if (side) (void)hipStreamSynchronize(side);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -1340,7 +1399,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                    (op.p2p_max_split & (op.p2p_max_split - 1)) == 0,
                "p2p_max_split must be 0 or a power of two <= 64");
     BB_REQUIRE(op.p2p_mfma >= 0 && op.p2p_mfma <= 2, "p2p_mfma must be 0, 1 or 2");
-    for (int i = 0; i < 4; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
+    BB_REQUIRE(op.overlap >= 0 && op.overlap <= 2, "overlap must be 0, 1 or 2");
+    for (int i = 0; i < 3; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -1469,6 +1529,20 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->work.alloc(w.size());
         BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    // overlapped near field: by default with the per-lane near field (whose
+    // VALU work complements the MFMA-bound far field); needs a far field
+    p->overlap = L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
+    if (p->overlap) {
+        const LevelData &leaf = t->lv[L];
+        p->pleaf.alloc(t->n);
+        ws += p->pleaf.bytes();
+        k_point_leaf<<<grid(leaf.C), kThreads, 0, nullptr>>>(leaf.pb.p, leaf.pe.p, leaf.C, p->pleaf.p);
+        BB_LAUNCH_CHECK();
+        BB_HIP(hipStreamSynchronize(nullptr));
+        BB_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+        BB_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+        BB_HIP(hipEventCreateWithFlags(&p->join, hipEventDisableTiming));
+    }
     p->ws_bytes = ws;
     return p.release();
 }
@@ -1478,22 +1552,35 @@ int64_t plan_workspace_bytes(const Plan *p) { return p->ws_bytes; }
 void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_split = p->nsplit;
     out->p2p_mfma = p->p2p_mfma ? 2 : 1;
+    out->overlap = p->overlap ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
 
 namespace {
 
-constexpr int kEv = BBFMM_NUM_STAGES + 1;
+// per execution: the stage boundaries on the caller's stream, then (the
+// overlapped schedule) P2P start / end on the side stream and the point
+// after the join where L2P starts
+constexpr int kEv = BBFMM_NUM_STAGES + 1 + 3;
+constexpr int kEvSideBeg = BBFMM_NUM_STAGES + 1, kEvSideEnd = kEvSideBeg + 1, kEvJoined = kEvSideBeg + 2;
 
 // fold the oldest pending execution's stage times into the totals
 void harvest_one(Plan &p) {
     const int slot = (p.ring_head - p.ring_pending + kTimingRing) % kTimingRing;
     hipEvent_t *ev = &p.events[size_t(slot) * kEv];
-    BB_HIP(hipEventSynchronize(ev[kEv - 1]));
+    BB_HIP(hipEventSynchronize(ev[BBFMM_NUM_STAGES]));
     for (int st = 0; st < BBFMM_NUM_STAGES; ++st) {
         float ms = 0.f;
-        BB_HIP(hipEventElapsedTime(&ms, ev[st], ev[st + 1]));
+        if (p.overlap && st == BBFMM_STAGE_P2P) {
+            // near field on the side stream + L2P after the join
+            float l2p = 0.f;
+            BB_HIP(hipEventElapsedTime(&ms, ev[kEvSideBeg], ev[kEvSideEnd]));
+            BB_HIP(hipEventElapsedTime(&l2p, ev[kEvJoined], ev[BBFMM_NUM_STAGES]));
+            ms += l2p;
+        } else {
+            BB_HIP(hipEventElapsedTime(&ms, ev[st], ev[st + 1]));
+        }
         p.stage_ms[st] += ms;
     }
     --p.ring_pending;
@@ -1652,6 +1739,23 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
     BB_LAUNCH_CHECK();
     const float *FL = nullptr;
     const int n = o.n, mp = o.mp;
+    auto near_field = [&](const float *fl, hipStream_t st) {
+        switch (t.params.kernel_id) {
+        case BBFMM_K_INV_R: launch_p2p<BBFMM_K_INV_R>(p, fl, geo, phi, st); break;
+        case BBFMM_K_EXP: launch_p2p<BBFMM_K_EXP>(p, fl, geo, phi, st); break;
+        case BBFMM_K_GAUSS: launch_p2p<BBFMM_K_GAUSS>(p, fl, geo, phi, st); break;
+        default: launch_p2p<BBFMM_K_POLY_TEST>(p, fl, geo, phi, st); break;
+        }
+    };
+    if (p.overlap) {
+        // the near field writes phi on the side stream meanwhile
+        BB_HIP(hipEventRecord(p.fork, s));
+        BB_HIP(hipStreamWaitEvent(p.side, p.fork, 0));
+        if (ev) BB_HIP(hipEventRecord(ev[kEvSideBeg], p.side));
+        near_field(nullptr, p.side);
+        if (ev) BB_HIP(hipEventRecord(ev[kEvSideEnd], p.side));
+        BB_HIP(hipEventRecord(p.join, p.side));
+    }
     mark(BBFMM_STAGE_P2M);
     if (L >= 2) {
         const LevelData &leaf = t.lv[L];
@@ -1763,11 +1867,19 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
     }
     if (L >= 2) FL = p.F[L].p;
     mark(BBFMM_STAGE_P2P);
-    switch (t.params.kernel_id) {
-    case BBFMM_K_INV_R: launch_p2p<BBFMM_K_INV_R>(p, FL, geo, phi, s); break;
-    case BBFMM_K_EXP: launch_p2p<BBFMM_K_EXP>(p, FL, geo, phi, s); break;
-    case BBFMM_K_GAUSS: launch_p2p<BBFMM_K_GAUSS>(p, FL, geo, phi, s); break;
-    default: launch_p2p<BBFMM_K_POLY_TEST>(p, FL, geo, phi, s); break;
+    if (p.overlap) {
+        BB_HIP(hipStreamWaitEvent(s, p.join, 0));
+        if (ev) BB_HIP(hipEventRecord(ev[kEvJoined], s));
+        const LevelData &leaf = t.lv[L];
+        switch (n) {
+#define BB_L2P(NN) case NN: k_l2p<NN><<<grid(t.n), kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, p.pleaf.p, \
+            leaf.keys.p, t.perm.p, t.n, r, FL, mp, geo, o.cheb, phi); break;
+        BB_L2P(2) BB_L2P(3) BB_L2P(4) BB_L2P(5) BB_L2P(6) BB_L2P(7) BB_L2P(8)
+#undef BB_L2P
+        }
+        BB_LAUNCH_CHECK();
+    } else {
+        near_field(FL, s);
     }
     mark(BBFMM_NUM_STAGES);
 }

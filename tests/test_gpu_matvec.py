@@ -218,12 +218,48 @@ def test_autotune_options_are_valid_and_exact(r):
     opts, ms = bbfmm.autotune(gt, go, ts, reps=3)
     assert ms > 0
     assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
-    assert opts["p2p_max_split"] in (4, 8, 16)
+    assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
     phi = torch.empty_like(ts)
     bbfmm.Plan(gt, go, r, **opts).execute(ts, phi)
     torch.cuda.synchronize()
     ref = ofmm.matvec(ot, oo, pts, sig, 0, 1.0)
     assert ofmm.rel_l2_cols(phi.cpu().numpy().astype(np.float64), ref).max() < TOL
+
+
+@pytest.mark.parametrize("kid,prm,r,path", [(0, 1.0, 1, 1), (1, 0.2, 2, 1), (2, 0.1, 5, 2)])
+def test_overlapped_schedule(kid, prm, r, path):
+    """Near field on a second stream while the far field runs, then L2P as
+    its own kernel: against the oracle, against the one-stream schedule,
+    eagerly with stage timing and as a replayed HIP graph."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(25000, 100 + r, r=r, kind="clustered")
+    gt, go, ot, oo = _both(pts, sig, kid, prm, 5, 1e-5, fixed_depth=5)
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    ts = torch.from_numpy(sig).cuda()
+    outs = {}
+    for ov in (1, 2):
+        plan = bbfmm.Plan(gt, go, r, overlap=ov, p2p_mfma=path)
+        plan.set_timing(True)
+        phi = torch.empty_like(ts)
+        for _ in range(3):
+            plan.execute(ts, phi)
+        torch.cuda.synchronize()
+        stage_ms, execs = plan.stage_times()
+        assert execs == 3 and all(v >= 0 for v in stage_ms.values()) and stage_ms["p2p"] > 0
+        got = phi.cpu().numpy().astype(np.float64)
+        err = ofmm.rel_l2_cols(got, ref).max()
+        print(f"kernel {kid} r {r} overlap {ov}: max column rel err {err:.2e}")
+        assert err < TOL
+        outs[ov] = got
+        plan.set_timing(False)
+        plan.set_graph(True)
+        for rep in range(3):
+            g = torch.full_like(ts, float("nan"))
+            plan.execute(ts, g)
+            torch.cuda.synchronize()
+            assert torch.equal(g, phi), (ov, rep)
+    assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
 
 
 def test_graph_replay_matches_eager():
