@@ -180,6 +180,104 @@ k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
     for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
 }
 
+// P2M for blocks of right-hand sides on FP32 MFMA: M[leaf][c][node] =
+// sum_p S[p][node] sigma[p][c] as D = A B with A[node][p] = S[p][node]
+// (lane node + 16 (p % 4) forms the Lagrange product itself from the
+// points' 1D values in LDS) and B[p][c] = sigma (staged in LDS).  One
+// workgroup per (leaf, 16 NCB columns); wave w owns the 16-node row blocks
+// w, w + 4, ...  A column's arithmetic does not depend on the others.
+template <int N, int NCB>
+__global__ void __launch_bounds__(kThreads)
+k_p2m_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
+           const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int ld, int r, int mp,
+           float *M) {
+    constexpr int m = N * N * N;
+    constexpr int NRBT = (m + 15) / 16;         // 16-node row blocks (mp = 16 NRBT)
+    constexpr int RBQ = (NRBT + 3) / 4;         // row blocks per wave
+    constexpr int CW = 16 * NCB;
+    constexpr int SST = CW == 16 ? 16 : CW + 16;   // = 16 mod 32: rows k, k+1 on disjoint banks
+    constexpr int PC = 64;                      // points per LDS chunk
+    __shared__ float lv[PC][3][N];
+    __shared__ __align__(16) float ss[PC * SST];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int a = blockIdx.x, col0 = blockIdx.y * CW;
+    const uint64_t key = keys[a];
+    float chi[3], clo[3];
+    for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
+    int n1[RBQ], n2[RBQ], n3[RBQ];
+    float nw[RBQ];                              // 0 for the padding nodes m <= node < mp
+#pragma unroll
+    for (int q = 0; q < RBQ; ++q) {
+        const int node = 16 * (wave + 4 * q) + (lane & 15);
+        const int nd = node < m ? node : 0;
+        nw[q] = node < m ? 1.f : 0.f;
+        n1[q] = nd % N;
+        n2[q] = (nd / N) % N;
+        n3[q] = nd / (N * N);
+    }
+    v4f acc[RBQ][NCB];
+#pragma unroll
+    for (int q = 0; q < RBQ; ++q)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int b = pb[a], e = pe[a];
+    for (int p0 = b; p0 < e; p0 += PC) {
+        const int np = min(PC, e - p0), npad = (np + 3) & ~3;
+        __syncthreads();
+        if (tid < PC) {
+            if (tid < np) {
+                const float p3[3] = {xs[p0 + tid], ys[p0 + tid], zs[p0 + tid]};
+                for (int d = 0; d < 3; ++d) {
+                    float l[kMaxOrder];
+                    lagrange(cc, local_coord(p3[d], chi[d], clo[d], geo.inv_h), l);
+#pragma unroll
+                    for (int k = 0; k < N; ++k) lv[tid][d][k] = l[k];
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int k = 0; k < N; ++k) lv[tid][d][k] = 0.f;
+            }
+        }
+        for (int g = tid; g < PC * (CW / 4); g += kThreads) {
+            const int pe4 = g / (CW / 4), part = g % (CW / 4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pe4 < np) v = *reinterpret_cast<const float4 *>(sig_s + int64_t(p0 + pe4) * ld + col0 + 4 * part);
+            *reinterpret_cast<float4 *>(&ss[pe4 * SST + 4 * part]) = v;
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < npad; k0 += 4) {
+            const int pp = k0 + (lane >> 4);
+            float bv[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bv[cb] = ss[pp * SST + cb * 16 + (lane & 15)];
+#pragma unroll
+            for (int q = 0; q < RBQ; ++q) {
+                if (wave + 4 * q >= NRBT) break;
+                const float av = lv[pp][0][n1[q]] * lv[pp][1][n2[q]] * lv[pp][2][n3[q]] * nw[q];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[cb], acc[q][cb], 0, 0, 0);
+            }
+        }
+    }
+    // D[i][j] sits in lane j + 16 (i / 4), register i % 4: four consecutive nodes
+#pragma unroll
+    for (int q = 0; q < RBQ; ++q) {
+        if (wave + 4 * q >= NRBT) break;
+        const int node0 = 16 * (wave + 4 * q) + 4 * (lane >> 4);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int c = col0 + cb * 16 + (lane & 15);
+            if (c < r)
+                *reinterpret_cast<float4 *>(M + (int64_t(a) * r + c) * mp + node0) =
+                    make_float4(acc[q][cb][0], acc[q][cb][1], acc[q][cb][2], acc[q][cb][3]);
+        }
+    }
+}
+
 // One child -> parent translation (trans = false) or parent -> child
 // (trans = true) of an n^3 block held in LDS `A`, as three n x n mode
 // products; the result is returned in registers (node slots of the lane).
@@ -1757,7 +1855,24 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         BB_HIP(hipEventRecord(p.join, p.side));
     }
     mark(BBFMM_STAGE_P2M);
-    if (L >= 2) {
+    if (L >= 2 && p.p2p_mfma) {
+        // blocks of right-hand sides: P2M on MFMA (sigma padded to whole column blocks)
+        const LevelData &leaf = t.lv[L];
+        dim3 g(leaf.C, unsigned(p.ld_s / (16 * p.ncb_p2p)));
+#define BB_P2MM(NN, NCB) k_p2m_mfma<NN, NCB><<<g, kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, \
+            leaf.pe.p, leaf.keys.p, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p)
+#define BB_P2MN(NN) case NN:                                                                  \
+            if (p.ncb_p2p == 1) BB_P2MM(NN, 1);                                               \
+            else if (p.ncb_p2p == 2) BB_P2MM(NN, 2);                                          \
+            else BB_P2MM(NN, 4);                                                              \
+            break;
+        switch (n) {
+            BB_P2MN(2) BB_P2MN(3) BB_P2MN(4) BB_P2MN(5) BB_P2MN(6) BB_P2MN(7) BB_P2MN(8)
+        }
+#undef BB_P2MN
+#undef BB_P2MM
+        BB_LAUNCH_CHECK();
+    } else if (L >= 2) {
         const LevelData &leaf = t.lv[L];
         dim3 g(leaf.C, r);
         switch (n) {

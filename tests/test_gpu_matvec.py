@@ -48,12 +48,24 @@ def test_matvec_matches_oracle(nn, seed, kind, kid, prm, n, depth, r, eps):
 
 @pytest.mark.parametrize("n", range(2, 9))
 def test_every_order(n):
-    """Each Chebyshev order has its own compiled up/down kernels."""
-    pts, sig = synth.random_cloud(5000, 30 + n, r=2, kind="clustered")
+    """Each Chebyshev order has its own compiled up/down kernels: the
+    per-lane path at r = 2 and the MFMA P2M / near-field path at r = 2 and
+    r = 37 (three column blocks, the last one partial)."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(5000, 30 + n, r=37, kind="clustered")
     gt, go, ot, oo = _both(pts, sig, 1, 0.3, n, 1e-5, fixed_depth=4)
-    got = gpu_matvec(gt, go, sig)
     ref = ofmm.matvec(ot, oo, pts, sig, 1, 0.3)
-    assert ofmm.rel_l2_cols(got, ref).max() < TOL
+    got = gpu_matvec(gt, go, sig[:, :2])
+    assert ofmm.rel_l2_cols(got, ref[:, :2]).max() < TOL
+    for r in (2, 37):
+        ts = torch.from_numpy(np.ascontiguousarray(sig[:, :r])).cuda()
+        phi = torch.empty_like(ts)
+        bbfmm.Plan(gt, go, r, p2p_mfma=2).execute(ts, phi)
+        torch.cuda.synchronize()
+        err = ofmm.rel_l2_cols(phi.cpu().numpy().astype(np.float64), ref[:, :r]).max()
+        print(f"n {n} r {r} MFMA paths: max column rel err {err:.2e}")
+        assert err < TOL
 
 
 @pytest.mark.parametrize("depth", [1, 2])
