@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "bbFMM matvec points x RHS/sec at rel err 1e-5 vs plain FP32; p99 latency"
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector (counts packed FP32)
+PEAK_16BIT_MFMA_TFLOPS = 2500.0   # MI355X dense BF16 / FP16 matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -64,31 +65,37 @@ def flops_per_pair_p2p(kernel_id: int, r: int) -> int:
 
 def cpu_baseline(w, gpu_phi_rows):
     """The oracle as it stands on this host: full upward pass and M2L, L2P
-    and P2P on the sampled targets; P2P time scaled to all N targets."""
+    and P2P on the sampled targets; P2P time scaled to all N targets.  For
+    a block of right-hand sides the oracle runs the first column only (the
+    columns are independent) and the rate is per column."""
     import numpy as np
     from oracle import fmm as ofmm, operators as oops, tree as otree
-    rows = w.sample_rows
+    rows = w.sample_rows if w.r == 1 else w.sample_rows[::4]
+    sig = w.sigma[:, :1]
     t0 = time.perf_counter()
-    tr = otree.build_tree(w.points, fixed_depth=w.fixed_depth)
+    tr = otree.build_tree(w.points, leaf_size=w.leaf_size, max_depth=w.max_depth,
+                          fixed_depth=w.fixed_depth)
     ops = oops.precompute(tr, w.kernel_id, w.kernel_param, w.order, w.eps)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ref = ofmm.matvec(tr, ops, w.points, w.sigma, w.kernel_id, w.kernel_param, rows=rows)
+    ref = ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rows)
     t_sample = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ofmm.matvec(tr, ops, w.points, w.sigma, w.kernel_id, w.kernel_param, rows=rows, far=False)
+    ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rows, far=False)
     t_near = time.perf_counter() - t0
     est = t_sample + t_near * (w.n / len(rows) - 1.0)
-    exact = ofmm.direct(w.points, w.sigma, w.kernel_id, w.kernel_param, rows=rows)
+    exact = ofmm.direct(w.points, sig, w.kernel_id, w.kernel_param, rows=rows)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    got = gpu_phi_rows[:len(rows)] if w.r == 1 else gpu_phi_rows[::4][:, :1]
     return {
-        "value": w.n * w.r / est, "unit": "points*RHS/s", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 oracle bbFMM on the same workload: upward pass and M2L over all "
-                   f"cells plus L2P+P2P on {len(rows)} sampled targets took {t_sample:.2f} s; "
-                   f"its P2P part ({t_near:.2f} s) scaled by N/{len(rows)} gives "
-                   f"{est:.1f} s per matvec (tree + operator setup {t_setup:.1f} s excluded)"),
-        "rel_err_gpu_vs_oracle": ofmm.rel_l2(gpu_phi_rows, ref),
-        "rel_err_gpu_vs_direct": ofmm.rel_l2(gpu_phi_rows, exact),
+        "value": w.n / est, "unit": "points*RHS/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 oracle bbFMM on the same workload (first right-hand side): upward "
+                   f"pass and M2L over all cells plus L2P+P2P on {len(rows)} sampled targets "
+                   f"took {t_sample:.2f} s; its P2P part ({t_near:.2f} s) scaled by "
+                   f"N/{len(rows)} gives {est:.1f} s per matvec (tree + operator setup "
+                   f"{t_setup:.1f} s excluded)"),
+        "rel_err_gpu_vs_oracle": ofmm.rel_l2(got, ref),
+        "rel_err_gpu_vs_direct": ofmm.rel_l2(got, exact),
         "rel_err_oracle_vs_direct": ofmm.rel_l2(ref, exact),
     }
 
@@ -257,6 +264,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="uniform-1M",
+                    choices=["uniform-1M", "clustered-2M", "slab-1M"],
+                    help="uniform-1M: the headline plain FP32 single-RHS workload; the other two "
+                         "are the batched workloads (r = 16 and r = 64)")
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16x3", "fp16s"],
+                    help="M2L precision (default: fp32 for uniform-1M, else the workload's own)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in launch-shape heuristic instead of bbfmm_plan_autotune")
     ap.add_argument("--no-variants", action="store_true",
@@ -279,14 +292,19 @@ def main() -> int:
     import synth
     from paper_1903_02153_amd import bbfmm
 
-    w = synth.cfg_uniform_1m()
+    w = {"uniform-1M": synth.cfg_uniform_1m, "clustered-2M": synth.cfg_clustered_2m,
+         "slab-1M": synth.cfg_slab_1m}[args.workload]()
+    prec_names = ("fp32", "bf16x3", "fp16s")
+    prec = (prec_names.index(args.precision) if args.precision else
+            (bbfmm.M2L_FP32 if args.workload == "uniform-1M" else w.precision))
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(w.points).to(dev)
     sig = torch.from_numpy(w.sigma).to(dev)
     phi = torch.empty_like(sig)
     tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
+                            leaf_size=w.leaf_size, max_depth=w.max_depth,
                             fixed_depth=w.fixed_depth)
-    ops = bbfmm.precompute_operators(tree, w.eps, bbfmm.M2L_FP32)
+    ops = bbfmm.precompute_operators(tree, w.eps, prec)
     opts = {}
     if not args.no_autotune:     # launch shapes only; outside the timed region
         opts, _ = bbfmm.autotune(tree, ops, sig, phi, reps=5)
@@ -323,7 +341,8 @@ def main() -> int:
     m2l_flop = sum(info.pairs[lvl] * 2 * ranks[lvl] ** 2 * w.r for lvl in ranks)
     p2p_flop = info.near_pairs * flops_per_pair_p2p(w.kernel_id, w.r)
     if stage_avg["m2l"] >= stage_avg["p2p"]:
-        kern, flop, peak, bound = "m2l", m2l_flop, PEAK_FP32_MFMA_TFLOPS, "mfma"
+        kern, flop, bound = "m2l", m2l_flop, "mfma"
+        peak = PEAK_FP32_MFMA_TFLOPS if prec == bbfmm.M2L_FP32 else PEAK_16BIT_MFMA_TFLOPS
     else:
         kern, flop, peak, bound = "p2p", p2p_flop, PEAK_FP32_VECTOR_TFLOPS, "alu"
     achieved = flop / (stage_avg[kern] * 1e-3) / 1e12
@@ -356,11 +375,17 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": value, "unit": "points*RHS/s", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == bbfmm.M2L_FP32 else ("f32+bf16x3" if prec == bbfmm.M2L_BF16X3
+                                                       else "f32+f16"),
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.n, "r": w.r, "kernel": "1/r", "order": w.order,
-                   "depth": info.depth, "leaf_cells": info.cells[L], "svd_eps": w.eps,
-                   "ranks": ranks, "m2l": "fp32-mfma", "parallelism": "single-gpu",
+        "config": {"workload": w.name, "N": w.n, "r": w.r,
+                   "kernel": {0: "1/r", 1: f"exp(-r/{w.kernel_param})",
+                              2: f"exp(-r^2/{w.kernel_param}^2)"}[w.kernel_id],
+                   "order": w.order, "depth": info.depth, "leaf_cells": info.cells[L],
+                   "svd_eps": w.eps, "ranks": ranks,
+                   "m2l": ("fp32", "split-bf16x3", "scaled-fp16")[prec] + "-mfma",
+                   "parallelism": "single-gpu",
                    "plan_options": opts or "heuristic"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
@@ -374,6 +399,8 @@ def main() -> int:
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
+    if args.workload != "uniform-1M":
+        args.no_variants = args.no_serving = True     # sections of the headline run only
     if not args.no_variants:
         out["batched_variants"] = batched_variants(max(5, min(args.steps, 20)), 2,
                                                    not args.no_autotune)

@@ -350,6 +350,14 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
             c.overlap = ov;
             consider(c);
         }
+        if (cur.overlap == 2 && cur.p2p_mfma != 2)
+            for (int nw : {512, 1024, 2048, 4096}) {
+                bbfmm_plan_options c = cur;
+                c.overlap = 2;
+                c.p2p_mfma = 1;
+                c.p2p_waves = nw;
+                consider(c);
+            }
         // make every choice explicit: what the heuristic picked for the zeros
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
         p->impl = plan_create_impl(t, o, r, &cur);

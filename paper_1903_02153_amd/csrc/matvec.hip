@@ -1052,93 +1052,99 @@ template <int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
       const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
-      const int32_t *work, const float *sig_s, int r, float ia, float ia2, const float *FL,
-      int mp, Geo geo, ChebConst cc, float *phi) {
+      const int32_t *work, int nwork, const float *sig_s, int r, float ia, float ia2,
+      const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
     constexpr int CAP = P2PCap<RC>::value;
     __shared__ float4 sp[CAP];                        // x, y, z, sigma of the first rhs
     __shared__ float ss[CAP][RC > 1 ? RC - 1 : 1];    // remaining rhs
     const int lane = threadIdx.x;
-    const int a = work[3 * blockIdx.x], t0 = work[3 * blockIdx.x + 1];
-    const int lgS = min(work[3 * blockIdx.x + 2], 4);   // at most 16 sub-lanes
-    const int S = 1 << lgS, sub = lane & (S - 1);
-    const int rhs0 = blockIdx.y * RC;
-    const int nr = min(RC, r - rhs0);
-    const int i = t0 + (lane >> lgS);
-    const bool valid = i < pe[a];
-    const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
-    float acc[RC];
+    // grid-stride over the work items: a launch of fewer workgroups than items
+    // keeps the near field to a share of the chip (overlapped schedule)
+    for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const int a = work[3 * item], t0 = work[3 * item + 1];
+        const int lgS = min(work[3 * item + 2], 4);   // at most 16 sub-lanes
+        const int S = 1 << lgS, sub = lane & (S - 1);
+        const int rhs0 = blockIdx.y * RC;
+        const int nr = min(RC, r - rhs0);
+        const int i = t0 + (lane >> lgS);
+        const bool valid = i < pe[a];
+        const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
+        float acc[RC];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0.f;
-    // walk the neighbour list, filling LDS passes of up to CAP records
-    const int q0 = nbr_off[a], q1 = nbr_off[a + 1];
-    int q = q0, off = 0;   // next neighbour and offset within it
-    while (q < q1) {
-        int n = 0;
-        __syncthreads();
-        while (q < q1 && n < CAP) {
-            const int b = nbr_idx[q];
-            const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - n);
-            for (int e = lane; e < cnt; e += 64) {
-                const float *sg = sig_s + int64_t(sb + e) * r + rhs0;
-                sp[n + e] = make_float4(xs[sb + e], ys[sb + e], zs[sb + e], sg[0]);
+        for (int c = 0; c < RC; ++c) acc[c] = 0.f;
+        // walk the neighbour list, filling LDS passes of up to CAP records
+        const int q0 = nbr_off[a], q1 = nbr_off[a + 1];
+        int q = q0, off = 0;   // next neighbour and offset within it
+        while (q < q1) {
+            int n = 0;
+            __syncthreads();
+            while (q < q1 && n < CAP) {
+                const int b = nbr_idx[q];
+                const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - n);
+                for (int e = lane; e < cnt; e += 64) {
+                    const float *sg = sig_s + int64_t(sb + e) * r + rhs0;
+                    sp[n + e] = make_float4(xs[sb + e], ys[sb + e], zs[sb + e], sg[0]);
 #pragma unroll
-                for (int c = 1; c < RC; ++c) ss[n + e][c - 1] = c < nr ? sg[c] : 0.f;
-            }
-            n += cnt;
-            if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
-        }
-        // CAP is a multiple of 64 >= 4 S, so the padded count stays within LDS
-        const int npad = min(CAP, (n + 4 * S - 1) / (4 * S) * (4 * S));
-        for (int e = n + lane; e < npad; e += 64) {
-            sp[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-            for (int c = 1; c < RC; ++c) ss[e][c - 1] = 0.f;
-        }
-        __syncthreads();
-        switch (lgS) {
-        case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-        case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-        case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-        case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-        default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-        }
-    }
-    if (FL != nullptr && valid) {
-        const int n = cc.n;
-        const uint64_t key = keys[a];
-        float l[3][kMaxOrder];
-        const float p[3] = {x, y, z};
-        for (int d = 0; d < 3; ++d) {
-            float chi, clo;
-            center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
-            lagrange(cc, local_coord(p[d], chi, clo, geo.inv_h), l[d]);
-        }
-#pragma unroll
-        for (int c = 0; c < RC; ++c) {
-            if (c >= nr) break;
-            const float *f = FL + (int64_t(a) * r + rhs0 + c) * mp;
-            float sacc = 0.f;
-            for (int i3 = sub; i3 < n; i3 += S) {
-                float s2 = 0.f;
-                for (int i2 = 0; i2 < n; ++i2) {
-                    float s1 = 0.f;
-                    for (int i1 = 0; i1 < n; ++i1) s1 += l[0][i1] * f[(i3 * n + i2) * n + i1];
-                    s2 += l[1][i2] * s1;
+                    for (int c = 1; c < RC; ++c) ss[n + e][c - 1] = c < nr ? sg[c] : 0.f;
                 }
-                sacc += l[2][i3] * s2;
+                n += cnt;
+                if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
             }
-            acc[c] += sacc;
+            // CAP is a multiple of 64 >= 4 S, so the padded count stays within LDS
+            const int npad = min(CAP, (n + 4 * S - 1) / (4 * S) * (4 * S));
+            for (int e = n + lane; e < npad; e += 64) {
+                sp[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int c = 1; c < RC; ++c) ss[e][c - 1] = 0.f;
+            }
+            __syncthreads();
+            switch (lgS) {
+            case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+            case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+            case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+            case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+            default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+            }
         }
-    }
-    for (int msk = 1; msk < S; msk <<= 1) {
+        if (FL != nullptr && valid) {
+            const int n = cc.n;
+            const uint64_t key = keys[a];
+            float l[3][kMaxOrder];
+            const float p[3] = {x, y, z};
+            for (int d = 0; d < 3; ++d) {
+                float chi, clo;
+                center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
+                lagrange(cc, local_coord(p[d], chi, clo, geo.inv_h), l[d]);
+            }
 #pragma unroll
-        for (int c = 0; c < RC; ++c) acc[c] += __shfl_xor(acc[c], msk, 64);
-    }
-    if (!valid || sub != 0) return;
-    float *out = phi + int64_t(perm[i]) * r + rhs0;
+            for (int c = 0; c < RC; ++c) {
+                if (c >= nr) break;
+                const float *f = FL + (int64_t(a) * r + rhs0 + c) * mp;
+                float sacc = 0.f;
+                for (int i3 = sub; i3 < n; i3 += S) {
+                    float s2 = 0.f;
+                    for (int i2 = 0; i2 < n; ++i2) {
+                        float s1 = 0.f;
+                        for (int i1 = 0; i1 < n; ++i1) s1 += l[0][i1] * f[(i3 * n + i2) * n + i1];
+                        s2 += l[1][i2] * s1;
+                    }
+                    sacc += l[2][i3] * s2;
+                }
+                acc[c] += sacc;
+            }
+        }
+        for (int msk = 1; msk < S; msk <<= 1) {
 #pragma unroll
-    for (int c = 0; c < RC; ++c)
-        if (c < nr) out[c] = acc[c];
+            for (int c = 0; c < RC; ++c) acc[c] += __shfl_xor(acc[c], msk, 64);
+        }
+        if (valid && sub == 0) {
+            float *out = phi + int64_t(perm[i]) * r + rhs0;
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < nr) out[c] = acc[c];
+        }
+        __syncthreads();                  // LDS of this item is consumed
+    }
 }
 
 // -------------------------------------------- L2P + P2P on MFMA ----
@@ -1449,6 +1455,7 @@ struct Plan {
     // overlapped schedule: the near field on a side stream while the far
     // field runs on the caller's stream, then L2P adds the far field
     bool overlap = false;
+    int p2p_waves = 0;                  // per-lane near field: workgroups launched (0 = one per item)
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     DBuf<int32_t> pleaf;                // point -> leaf (tree order), for k_l2p
@@ -1498,7 +1505,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                "p2p_max_split must be 0 or a power of two <= 64");
     BB_REQUIRE(op.p2p_mfma >= 0 && op.p2p_mfma <= 2, "p2p_mfma must be 0, 1 or 2");
     BB_REQUIRE(op.overlap >= 0 && op.overlap <= 2, "overlap must be 0, 1 or 2");
-    for (int i = 0; i < 3; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
+    BB_REQUIRE(op.p2p_waves >= 0, "p2p_waves must be >= 0");
+    for (int i = 0; i < 2; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -1630,6 +1638,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     // overlapped near field: by default with the per-lane near field (whose
     // VALU work complements the MFMA-bound far field); needs a far field
     p->overlap = L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
+    p->p2p_waves = op.p2p_waves;
     if (p->overlap) {
         const LevelData &leaf = t->lv[L];
         p->pleaf.alloc(t->n);
@@ -1651,6 +1660,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_split = p->nsplit;
     out->p2p_mfma = p->p2p_mfma ? 2 : 1;
     out->overlap = p->overlap ? 2 : 1;
+    out->p2p_waves = p->p2p_waves;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -1719,12 +1729,13 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
         }
         return;
     }
-    dim3 g(p.nwork, unsigned(ceil_div(p.r, p.rc_p2p)));
+    const int nwg = p.p2p_waves > 0 ? std::min(p.p2p_waves, p.nwork) : p.nwork;
+    dim3 g(unsigned(nwg), unsigned(ceil_div(p.r, p.rc_p2p)));
 #define BB_P2P(RCV)                                                                          \
     k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
                                      t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p,         \
-                                     p.work.p, p.sig_s.p, int(p.r), ia, ia2, FL, p.ops->mp,   \
-                                     geo, p.ops->cheb, phi)
+                                     p.work.p, p.nwork, p.sig_s.p, int(p.r), ia, ia2, FL,     \
+                                     p.ops->mp, geo, p.ops->cheb, phi)
     switch (p.rc_p2p) {
     case 1: BB_P2P(1); break;
     case 2: BB_P2P(2); break;

@@ -231,6 +231,7 @@ def test_autotune_options_are_valid_and_exact(r):
     assert ms > 0
     assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
     assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
+    assert opts["p2p_waves"] in (0, 512, 1024, 2048, 4096)
     phi = torch.empty_like(ts)
     bbfmm.Plan(gt, go, r, **opts).execute(ts, phi)
     torch.cuda.synchronize()
@@ -250,8 +251,11 @@ def test_overlapped_schedule(kid, prm, r, path):
     ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
     ts = torch.from_numpy(sig).cuda()
     outs = {}
-    for ov in (1, 2):
-        plan = bbfmm.Plan(gt, go, r, overlap=ov, p2p_mfma=path)
+    configs = {1: dict(overlap=1), 2: dict(overlap=2)}
+    if path == 1:   # the per-lane near field with fewer workgroups than items (grid-stride)
+        configs[3] = dict(overlap=2, p2p_waves=700)
+    for ov, cfg in configs.items():
+        plan = bbfmm.Plan(gt, go, r, p2p_mfma=path, **cfg)
         plan.set_timing(True)
         phi = torch.empty_like(ts)
         for _ in range(3):
@@ -261,7 +265,7 @@ def test_overlapped_schedule(kid, prm, r, path):
         assert execs == 3 and all(v >= 0 for v in stage_ms.values()) and stage_ms["p2p"] > 0
         got = phi.cpu().numpy().astype(np.float64)
         err = ofmm.rel_l2_cols(got, ref).max()
-        print(f"kernel {kid} r {r} overlap {ov}: max column rel err {err:.2e}")
+        print(f"kernel {kid} r {r} {cfg}: max column rel err {err:.2e}")
         assert err < TOL
         outs[ov] = got
         plan.set_timing(False)
@@ -272,6 +276,8 @@ def test_overlapped_schedule(kid, prm, r, path):
             torch.cuda.synchronize()
             assert torch.equal(g, phi), (ov, rep)
     assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
+    if 3 in outs:   # the same arithmetic per target: identical to one workgroup per item
+        assert np.array_equal(outs[2], outs[3])
 
 
 def test_graph_replay_matches_eager():
