@@ -258,6 +258,11 @@ def serving_mix(n_requests: int, budget_gib: float, load: float):
     return out
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished phase (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +315,7 @@ def main() -> int:
         opts, _ = bbfmm.autotune(tree, ops, sig, phi, reps=5)
     plan = bbfmm.Plan(tree, ops, w.r, **opts)
     info = tree.info()
+    progress(f"{w.name}: tree, operators and plan ready ({opts or 'heuristic'})")
     L = info.depth - 1
 
     for _ in range(args.warmup):
@@ -330,6 +336,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stage_ms, nexec = plan.stage_times(reset=True)
+    progress(f"timed region: {K} steps, {(t1 - t0) * 1e3 / K:.3f} ms per step")
     plan.set_timing(False)
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_per_step = (t1 - t0) * 1e3 / K
@@ -404,15 +411,18 @@ def main() -> int:
     if not args.no_variants:
         out["batched_variants"] = batched_variants(max(5, min(args.steps, 20)), 2,
                                                    not args.no_autotune)
+        progress("batched variants done")
     if not args.no_serving:
         out["serving"] = serving_mix(args.serving_requests, args.serving_budget_gib,
                                      args.serving_load)
+        progress("serving mix done")
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         plan.execute(sig, phi)
         torch.cuda.synchronize()
         got = phi.cpu().numpy().astype(np.float64)[w.sample_rows]
         out["cpu_baseline"] = cpu_baseline(w, got)
+        progress("CPU oracle baseline done")
     print(json.dumps(out), flush=True)
     return 0
 
