@@ -358,6 +358,13 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.p2p_waves = nw;
                 consider(c);
             }
+        if (cur.overlap == 2)
+            for (int occ : {3, 2}) {
+                bbfmm_plan_options c = cur;
+                c.overlap = 2;
+                c.m2l_occupancy = occ;
+                consider(c);
+            }
         // make every choice explicit: what the heuristic picked for the zeros
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
         p->impl = plan_create_impl(t, o, r, &cur);

@@ -1456,6 +1456,8 @@ struct Plan {
     // field runs on the caller's stream, then L2P adds the far field
     bool overlap = false;
     int p2p_waves = 0;                  // per-lane near field: workgroups launched (0 = one per item)
+    int m2l_occupancy = 0;              // M2L workgroups per CU (0 = as many as fit)
+    size_t m2l_pad_lds = 0;             // unused dynamic LDS that enforces m2l_occupancy
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     DBuf<int32_t> pleaf;                // point -> leaf (tree order), for k_l2p
@@ -1506,7 +1508,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.p2p_mfma >= 0 && op.p2p_mfma <= 2, "p2p_mfma must be 0, 1 or 2");
     BB_REQUIRE(op.overlap >= 0 && op.overlap <= 2, "overlap must be 0, 1 or 2");
     BB_REQUIRE(op.p2p_waves >= 0, "p2p_waves must be >= 0");
-    for (int i = 0; i < 2; ++i) BB_REQUIRE(op.reserved[i] == 0, "reserved options must be 0");
+    BB_REQUIRE(op.m2l_occupancy >= 0 && op.m2l_occupancy <= 4, "m2l_occupancy must be in [0, 4]");
+    BB_REQUIRE(op.reserved[0] == 0, "reserved options must be 0");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -1639,6 +1642,20 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     // VALU work complements the MFMA-bound far field); needs a far field
     p->overlap = L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
     p->p2p_waves = op.p2p_waves;
+    p->m2l_occupancy = op.m2l_occupancy;
+    if (op.m2l_occupancy > 0 && L >= 2) {
+        // pad the M2L workgroup's LDS so that at most m2l_occupancy fit on a
+        // CU (160 KiB of LDS each), leaving registers to a concurrent kernel
+        hipFuncAttributes fa{};
+        if (o->precision == BBFMM_M2L_FP32)
+            BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l)));
+        else if (o->precision == BBFMM_M2L_BF16X3)
+            BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l_lp<BBFMM_M2L_BF16X3>)));
+        else
+            BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l_lp<BBFMM_M2L_FP16_SCALED>)));
+        const size_t per_wg = size_t(160 * 1024) / size_t(op.m2l_occupancy) - 512;
+        p->m2l_pad_lds = per_wg > fa.sharedSizeBytes ? per_wg - fa.sharedSizeBytes : 0;
+    }
     if (p->overlap) {
         const LevelData &leaf = t->lv[L];
         p->pleaf.alloc(t->n);
@@ -1661,6 +1678,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->p2p_mfma = p->p2p_mfma ? 2 : 1;
     out->overlap = p->overlap ? 2 : 1;
     out->p2p_waves = p->p2p_waves;
+    out->m2l_occupancy = p->m2l_occupancy;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -1947,9 +1965,9 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         g.nsplit = p.nsplit;
         dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
         if (o.precision == BBFMM_M2L_BF16X3)
-            k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, 0, s>>>(g);
+            k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
         else
-            k_m2l_lp<BBFMM_M2L_FP16_SCALED><<<gr, kThreads, 0, s>>>(g);
+            k_m2l_lp<BBFMM_M2L_FP16_SCALED><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
         BB_LAUNCH_CHECK();
     } else if (L >= 2) {
         M2LArgs g{};
@@ -1966,7 +1984,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         g.tpt = p.tpt;
         g.nsplit = p.nsplit;
         dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
-        k_m2l<<<gr, kThreads, 0, s>>>(g);
+        k_m2l<<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
         BB_LAUNCH_CHECK();
     }
     mark(BBFMM_STAGE_DOWN);

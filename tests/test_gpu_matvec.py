@@ -232,6 +232,7 @@ def test_autotune_options_are_valid_and_exact(r):
     assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
     assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
     assert opts["p2p_waves"] in (0, 512, 1024, 2048, 4096)
+    assert opts["m2l_occupancy"] in (0, 2, 3)
     phi = torch.empty_like(ts)
     bbfmm.Plan(gt, go, r, **opts).execute(ts, phi)
     torch.cuda.synchronize()
@@ -254,6 +255,7 @@ def test_overlapped_schedule(kid, prm, r, path):
     configs = {1: dict(overlap=1), 2: dict(overlap=2)}
     if path == 1:   # the per-lane near field with fewer workgroups than items (grid-stride)
         configs[3] = dict(overlap=2, p2p_waves=700)
+    configs[4] = dict(overlap=2, m2l_occupancy=2)   # padded M2L LDS: same arithmetic
     for ov, cfg in configs.items():
         plan = bbfmm.Plan(gt, go, r, p2p_mfma=path, **cfg)
         plan.set_timing(True)
@@ -278,6 +280,7 @@ def test_overlapped_schedule(kid, prm, r, path):
     assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
     if 3 in outs:   # the same arithmetic per target: identical to one workgroup per item
         assert np.array_equal(outs[2], outs[3])
+    assert np.array_equal(outs[2], outs[4])
 
 
 def test_graph_replay_matches_eager():
