@@ -235,7 +235,9 @@ typedef struct {
                             /* leave room for the far field when overlapped      */
     int32_t m2l_occupancy;  /* M2L workgroups per CU, 1..4 (0 = as many as fit); */
                             /* fewer leave registers to the overlapped near field */
-    int32_t reserved[1];    /* must be 0                                          */
+    int32_t m2l_layout;     /* FP32 M2L waves: 1 = 16 rank rows x 64 columns     */
+                            /* each, 2 = 32 x 32 (half the LDS reads per MFMA);  */
+                            /* 0 = 1                                             */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults).  The
@@ -290,15 +292,16 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  * per-lane kernel, the sub-lane cap 4, 8 or 16; then the overlapped
  * schedule on or off; then, overlapped with the per-lane kernel, the
  * near-field workgroup count (one per item, or 512 .. 4096); then, when
- * overlapped, the M2L workgroups per CU (as many as fit, 3 or 2).  Each candidate runs one
+ * overlapped, the M2L workgroups per CU (as many as fit, 3 or 2); then
+ * the FP32 M2L wave layout.  Each candidate runs one
  * untimed product and `reps` timed ones (HIP events on `stream`); its
  * time is the median.  Options only change launch shapes (and with them
  * the floating-point summation order), never the arithmetic precision.
  *   sigma, phi  device, N x r float32; phi is overwritten by every trial.
  *   reps        1..100.
  *   best        out: the chosen options (m2l_split, p2p_mfma,
- *               p2p_max_split, overlap, p2p_waves and m2l_occupancy
- *               explicit).
+ *               p2p_max_split, overlap, p2p_waves, m2l_occupancy and
+ *               m2l_layout explicit).
  *   best_ms     out (may be NULL): its median milliseconds per product.
  * Allocates and frees one plan workspace per candidate; synchronizes
  * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.

@@ -63,7 +63,7 @@ class PlanOptions(ctypes.Structure):
     _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
                 ("p2p_max_split", ctypes.c_int32), ("p2p_mfma", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("p2p_waves", ctypes.c_int32),
-                ("m2l_occupancy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32)]
 
 
 _lib_handle = None
@@ -215,7 +215,7 @@ class Plan:
 
     def __init__(self, tree: Tree, ops: Ops, r: int, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
-        m2l_occupancy (0 = heuristic)."""
+        m2l_occupancy, m2l_layout (0 = heuristic)."""
         h = _VP()
         opt = PlanOptions()
         for k, v in options.items():
@@ -280,7 +280,8 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
                                      ctypes.byref(best), ctypes.byref(ms)))
     return {"m2l_split": best.m2l_split, "p2p_max_split": best.p2p_max_split,
             "p2p_mfma": best.p2p_mfma, "overlap": best.overlap,
-            "p2p_waves": best.p2p_waves, "m2l_occupancy": best.m2l_occupancy}, ms.value
+            "p2p_waves": best.p2p_waves, "m2l_occupancy": best.m2l_occupancy,
+            "m2l_layout": best.m2l_layout}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,

@@ -358,6 +358,11 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.p2p_waves = nw;
                 consider(c);
             }
+        if (o->precision == BBFMM_M2L_FP32) {
+            bbfmm_plan_options c = cur;
+            c.m2l_layout = 2;
+            consider(c);
+        }
         if (cur.overlap == 2)
             for (int occ : {3, 2}) {
                 bbfmm_plan_options c = cur;

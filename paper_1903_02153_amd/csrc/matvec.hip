@@ -596,7 +596,11 @@ __device__ inline int xcd_tile(int bid, int nblocks) {
 // on how targets are grouped into tiles.  The last K chunk of a rank that
 // is not a multiple of 64 issues only its nonzero 16-deep MFMA blocks, and
 // waves whose 16 rows lie past the rank issue no MFMAs.
+template <int RW>
 __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
+    static_assert(RW == 4 || RW == 2, "row waves");
+    constexpr int RB = 4 / RW;          // 16-row blocks per wave
+    constexpr int CB = RW;              // 16-column blocks per wave
     constexpr int ldb = 64 + 4;
     __shared__ float Bs[2][kM2LCols * ldb];
     __shared__ int32_t tgt[kM2LCols], srcs[3][kM2LCols];
@@ -617,8 +621,16 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const int32_t *itab = L.itab;
     const int r = g.r, rc = g.rc;
     const int rhs0 = blockIdx.z * rc;
-    const int row0 = blockIdx.y * 64 + wave * 16;
-    const bool active = row0 < kp;
+    const int wr = wave % RW, wc = wave / RW;
+    const int rowb = blockIdx.y * 64 + wr * 16 * RB;      // first row of the wave
+    const int colb = wc * 16 * CB;                        // first column of the wave
+    bool rok[RB];
+    bool active = false;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        rok[b] = rowb + 16 * b < kp;
+        active = active || rok[b];
+    }
     const int nkc = (kp + 63) / 64;
     // visited slots of this split, compacted: index q runs over [0, jend)
     const int jbeg = 0;
@@ -675,23 +687,31 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
             *reinterpret_cast<float4 *>(&Bs[buf][(e >> 4) * ldb + 4 * bq[i]]) = breg[i];
         }
     };
-    // rows past the rank (inactive waves) read row 0 and are masked to zero
-    const float *Arow = L.C32 + int64_t(active ? row0 + (lane & 15) : 0) * kp + 4 * (lane >> 4);
-    auto load_a = [&](int j, int kc, float4 *areg) {
-        const int nkb = min(64, kp - kc * 64) / 16;
-        const float *A = Arow + int64_t(st[j]) * kp * kp + kc * 64;
+    // rows past the rank read row 0 and are masked to zero
+    int64_t arow[RB];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const bool ok = active && kb < nkb;    // wave-uniform
-            const float w = ok ? 1.f : 0.f;        // C32 is finite: 0 * v == 0
-            const float4 v = *reinterpret_cast<const float4 *>(A + (ok ? 16 * kb : 0));
-            areg[kb] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
-        }
+    for (int b = 0; b < RB; ++b)
+        arow[b] = int64_t(rok[b] ? rowb + 16 * b + (lane & 15) : 0) * kp + 4 * (lane >> 4);
+    auto load_a = [&](int j, int kc, float4 *areg) {      // areg[b * 4 + kb]
+        const int nkb = min(64, kp - kc * 64) / 16;
+        const float *A = L.C32 + int64_t(st[j]) * kp * kp + kc * 64;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bool ok = rok[b] && kb < nkb;    // wave-uniform
+                const float w = ok ? 1.f : 0.f;        // C32 is finite: 0 * v == 0
+                const float4 v = *reinterpret_cast<const float4 *>(A + arow[b] + (ok ? 16 * kb : 0));
+                areg[b * 4 + kb] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
+            }
     };
 
-    v4f acc[4];
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
-    float4 breg[4], a0[4], a1[4];
+    v4f acc[RB][CB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[b][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    float4 breg[4], a0[4 * RB], a1[4 * RB];
     int32_t itab_next = -1;
     int j = jbeg, kc = 0;
     // One step: prefetch step s+1 (sources into breg, C_t rows into anxt,
@@ -715,26 +735,34 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
         // rank (the zero-padded tail of a rank is skipped); waves whose rows
         // lie past the rank skip it entirely.  Both conditions are uniform.
         const int nkb = active ? min(64, kp - kc * 64) / 16 : 0;
-        const float *B = Bs[s & 1] + (lane & 15) * ldb + 4 * (lane >> 4);
+        const float *B = Bs[s & 1] + (colb + (lane & 15)) * ldb + 4 * (lane >> 4);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             if (kb >= nkb) break;
-            float4 b4[4];
+            float4 b4[CB];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < CB; ++cb)
                 b4[cb] = *reinterpret_cast<const float4 *>(B + cb * 16 * ldb + 16 * kb);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].x, b4[cb].x, acc[cb], 0, 0, 0);
+            for (int b = 0; b < RB; ++b)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].y, b4[cb].y, acc[cb], 0, 0, 0);
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[b * 4 + kb].x, b4[cb].x, acc[b][cb], 0, 0, 0);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].z, b4[cb].z, acc[cb], 0, 0, 0);
+            for (int b = 0; b < RB; ++b)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[kb].w, b4[cb].w, acc[cb], 0, 0, 0);
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[b * 4 + kb].y, b4[cb].y, acc[b][cb], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[b * 4 + kb].z, b4[cb].z, acc[b][cb], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[b * 4 + kb].w, b4[cb].w, acc[b][cb], 0, 0, 0);
         }
         if constexpr (MORE) {
             store_b((s + 1) & 1, breg);
@@ -764,14 +792,17 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
         }
     }
     if (!active) return;
-    for (int cb = 0; cb < 4; ++cb) {
-        const int col = cb * 16 + (lane & 15);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int col = colb + cb * 16 + (lane & 15);
         const int tl = col / rc, c = col % rc;
-        if (tl < cnt && rhs0 + c < r) {
-            float *dst = L.Fh + split * L.rows * kp +
-                         (int64_t(tgt[tl]) * r + rhs0 + c) * kp + row0 + 4 * (lane >> 4);
-            *reinterpret_cast<float4 *>(dst) = make_float4(acc[cb][0], acc[cb][1], acc[cb][2], acc[cb][3]);
-        }
+        if (tl >= cnt || rhs0 + c >= r) continue;
+        float *dst = L.Fh + split * L.rows * kp + (int64_t(tgt[tl]) * r + rhs0 + c) * kp + 4 * (lane >> 4);
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if (rok[b])
+                *reinterpret_cast<float4 *>(dst + rowb + 16 * b) =
+                    make_float4(acc[b][cb][0], acc[b][cb][1], acc[b][cb][2], acc[b][cb][3]);
     }
 }
 
@@ -1457,6 +1488,7 @@ struct Plan {
     bool overlap = false;
     int p2p_waves = 0;                  // per-lane near field: workgroups launched (0 = one per item)
     int m2l_occupancy = 0;              // M2L workgroups per CU (0 = as many as fit)
+    int m2l_layout = 1;                 // FP32 M2L waves: 1 = 16 rows x 64 columns, 2 = 32 x 32
     size_t m2l_pad_lds = 0;             // unused dynamic LDS that enforces m2l_occupancy
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -1509,7 +1541,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.overlap >= 0 && op.overlap <= 2, "overlap must be 0, 1 or 2");
     BB_REQUIRE(op.p2p_waves >= 0, "p2p_waves must be >= 0");
     BB_REQUIRE(op.m2l_occupancy >= 0 && op.m2l_occupancy <= 4, "m2l_occupancy must be in [0, 4]");
-    BB_REQUIRE(op.reserved[0] == 0, "reserved options must be 0");
+    BB_REQUIRE(op.m2l_layout >= 0 && op.m2l_layout <= 2, "m2l_layout must be 0, 1 or 2");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());
@@ -1643,12 +1675,14 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     p->overlap = L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
     p->p2p_waves = op.p2p_waves;
     p->m2l_occupancy = op.m2l_occupancy;
+    p->m2l_layout = op.m2l_layout == 2 ? 2 : 1;
     if (op.m2l_occupancy > 0 && L >= 2) {
         // pad the M2L workgroup's LDS so that at most m2l_occupancy fit on a
         // CU (160 KiB of LDS each), leaving registers to a concurrent kernel
         hipFuncAttributes fa{};
         if (o->precision == BBFMM_M2L_FP32)
-            BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l)));
+            BB_HIP(hipFuncGetAttributes(&fa, op.m2l_layout == 2 ? reinterpret_cast<const void *>(k_m2l<2>)
+                                                              : reinterpret_cast<const void *>(k_m2l<4>)));
         else if (o->precision == BBFMM_M2L_BF16X3)
             BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l_lp<BBFMM_M2L_BF16X3>)));
         else
@@ -1679,6 +1713,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->overlap = p->overlap ? 2 : 1;
     out->p2p_waves = p->p2p_waves;
     out->m2l_occupancy = p->m2l_occupancy;
+    out->m2l_layout = p->m2l_layout;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -1984,7 +2019,10 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         g.tpt = p.tpt;
         g.nsplit = p.nsplit;
         dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
-        k_m2l<<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
+        if (p.m2l_layout == 2)
+            k_m2l<2><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
+        else
+            k_m2l<4><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
         BB_LAUNCH_CHECK();
     }
     mark(BBFMM_STAGE_DOWN);

@@ -193,6 +193,30 @@ def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
     assert err < tol
 
 
+@pytest.mark.parametrize("kid,prm,n,kind,r", [(0, 1.0, 5, "uniform", 1), (1, 0.2, 6, "clustered", 3),
+                                              (2, 0.1, 4, "slab", 70)])
+def test_m2l_wave_layouts(kid, prm, n, kind, r):
+    """The FP32 M2L with waves of 16 rows x 64 columns and of 32 x 32 (rank
+    rows past a partial row group masked) against the oracle and each
+    other: the same products in the same order per output, so equal bit for
+    bit."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(20000, 110 + n, r=r, kind=kind)
+    gt, go, ot, oo = _both(pts, sig, kid, prm, n, 1e-5, fixed_depth=5)
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    ts = torch.from_numpy(sig).cuda()
+    outs = []
+    for layout in (1, 2):
+        phi = torch.empty_like(ts)
+        bbfmm.Plan(gt, go, r, m2l_layout=layout, m2l_split=2).execute(ts, phi)
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy().astype(np.float64)
+        assert ofmm.rel_l2_cols(got, ref).max() < TOL
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("r", [1, 4, 20, 40, 70])
 def test_near_field_paths_agree(r):
     """The per-lane FMA near field and the MFMA near field (kernel values as
@@ -232,7 +256,7 @@ def test_autotune_options_are_valid_and_exact(r):
     assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
     assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
     assert opts["p2p_waves"] in (0, 512, 1024, 2048, 4096)
-    assert opts["m2l_occupancy"] in (0, 2, 3)
+    assert opts["m2l_occupancy"] in (0, 2, 3) and opts["m2l_layout"] in (1, 2)
     phi = torch.empty_like(ts)
     bbfmm.Plan(gt, go, r, **opts).execute(ts, phi)
     torch.cuda.synchronize()
