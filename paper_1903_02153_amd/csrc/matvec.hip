@@ -1529,7 +1529,6 @@ struct Plan {
 
 Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                        const bbfmm_plan_options *opt) {
-    BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     bbfmm_plan_options op{};
     if (opt) op = *opt;
     BB_REQUIRE(op.m2l_split >= 0 && op.m2l_split <= 8, "m2l_split must be in [0, 8]");
@@ -1542,6 +1541,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.p2p_waves >= 0, "p2p_waves must be >= 0");
     BB_REQUIRE(op.m2l_occupancy >= 0 && op.m2l_occupancy <= 4, "m2l_occupancy must be in [0, 4]");
     BB_REQUIRE(op.m2l_layout >= 0 && op.m2l_layout <= 2, "m2l_layout must be 0, 1 or 2");
+    BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
     std::unique_ptr<Plan> p(new Plan());

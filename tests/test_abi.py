@@ -62,6 +62,31 @@ def test_invalid_arguments_rejected_without_gpu():
     lib.bbfmm_plan_free(None)
 
 
+@pytest.mark.parametrize("field,value", [("m2l_split", 9), ("m2l_min_waves", 17),
+                                         ("p2p_max_split", 3), ("p2p_mfma", 3), ("overlap", -1),
+                                         ("p2p_waves", -5), ("m2l_occupancy", 5),
+                                         ("m2l_layout", 3)])
+def test_plan_options_validated_without_gpu(field, value):
+    """Every launch-shape option is range-checked before any handle or
+    device memory is touched; the message names the option."""
+    lib = bbfmm.lib()
+    opt = bbfmm.PlanOptions()
+    setattr(opt, field, value)
+    out = ctypes.c_void_p()
+    assert lib.bbfmm_plan_create_ex(None, None, 4, ctypes.byref(opt), ctypes.byref(out)) == 1
+    assert field.encode() in lib.bbfmm_last_error()
+    assert out.value is None
+
+
+def test_autotune_rejects_invalid_arguments_without_gpu():
+    lib = bbfmm.lib()
+    best = bbfmm.PlanOptions()
+    ms = ctypes.c_double()
+    assert lib.bbfmm_plan_autotune(None, None, 1, None, None, None, 3, ctypes.byref(best),
+                                   ctypes.byref(ms)) == 1
+    assert b"NULL" in lib.bbfmm_last_error()
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(TypeError):
