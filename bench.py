@@ -236,6 +236,7 @@ def serving_mix(n_requests: int, budget_gib: float, load: float):
             time.sleep(dt)
         rids.append(submit(int(tree_ix[q]), int(rs[q])))
     stats = [srv.wait(q) for q in rids]
+    counters = srv.stats()
     srv.close()
     lat = np.array([s["t_done"] - s["t_submit"] for s in stats]) * 1e3
     queue = np.array([s["t_admit"] - s["t_submit"] for s in stats]) * 1e3
@@ -252,7 +253,8 @@ def serving_mix(n_requests: int, budget_gib: float, load: float):
            "queue_ms": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
            "throughput_points_rhs_per_s": total / span,
            "throughput_req_per_s": n_requests / span,
-           "batched_fraction": float(batched.mean())}
+           "batched_fraction": float(batched.mean()),
+           "server_counters": counters}
     del classes
     torch.cuda.empty_cache()
     return out

@@ -352,6 +352,17 @@ bbfmm_status bbfmm_server_wait(bbfmm_server *server, uint64_t request_id,
 /* Drains in-flight batches and frees the server (NULL accepted). */
 bbfmm_status bbfmm_server_destroy(bbfmm_server *server);
 
+/* Counters of a server since its creation (all out, host). */
+typedef struct {
+    int64_t requests_done;      /* completed (including rejected) requests        */
+    int64_t batches;            /* products launched                              */
+    int64_t plans_created;      /* (model, R) plans built (workspace + graph)     */
+    int64_t plans_evicted;      /* idle plans freed to make room in the budget    */
+    int64_t bytes_in_use;       /* device bytes held by cached plans now          */
+    int64_t bytes_peak;         /* largest bytes_in_use so far                    */
+} bbfmm_server_stats;
+bbfmm_status bbfmm_server_get_stats(bbfmm_server *server, bbfmm_server_stats *out);
+
 void bbfmm_tree_free(bbfmm_tree *tree);
 void bbfmm_ops_free(bbfmm_ops *ops);
 void bbfmm_plan_free(bbfmm_plan *plan);

@@ -59,6 +59,12 @@ class RequestStats(ctypes.Structure):
                 ("slot", ctypes.c_int32)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("plans_created", ctypes.c_int64), ("plans_evicted", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64)]
+
+
 class PlanOptions(ctypes.Structure):
     _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
                 ("p2p_max_split", ctypes.c_int32), ("p2p_mfma", ctypes.c_int32),
@@ -87,6 +93,7 @@ SIGNATURES = {
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
     "bbfmm_plan_set_graph": (_I32, [_VP, _I32]),
     "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+    "bbfmm_server_get_stats": (_I32, [_VP, ctypes.POINTER(ServerStats)]),
     "bbfmm_plan_autotune": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _I32, ctypes.POINTER(PlanOptions),
                                    ctypes.POINTER(ctypes.c_double)]),
     "bbfmm_server_create": (_I32, [_I64, _I32, _I32, _PVP]),
@@ -373,6 +380,11 @@ class Server:
             self._keep.pop(request_id, None)
         return {"t_submit": st.t_submit, "t_admit": st.t_admit, "t_done": st.t_done,
                 "batch_r": st.batch_r, "slot": st.slot}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().bbfmm_server_get_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
 
     def close(self):
         if self._h:

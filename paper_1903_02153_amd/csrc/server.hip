@@ -128,6 +128,7 @@ struct Server {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
     uint64_t next_id = 1, tick = 0;
     int64_t in_use = 0;
+    bbfmm_server_stats st{};
     int device = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -162,6 +163,7 @@ struct Server {
             for (Request *rq : s.batch) {
                 rq->t_done = t;
                 rq->done = true;
+                ++st.requests_done;
                 if (q != hipSuccess) {
                     rq->status = BBFMM_ERR_HIP;
                     rq->error = hipGetErrorString(q);
@@ -216,6 +218,7 @@ struct Server {
             if (victim == cache.size()) return nullptr;     // everything cached is running
             in_use -= cache[victim]->bytes;
             cache.erase(cache.begin() + victim);
+            ++st.plans_evicted;
         }
         std::unique_ptr<Entry> e(new Entry());
         e->model = mdl;
@@ -226,6 +229,8 @@ struct Server {
         e->plan = plan.release();
         e->bytes = bytes;
         in_use += bytes;
+        ++st.plans_created;
+        st.bytes_peak = std::max(st.bytes_peak, in_use);
         cache.push_back(std::move(e));
         return cache.back().get();
     }
@@ -242,6 +247,7 @@ struct Server {
                 rq->status = BBFMM_ERR_BUDGET;
                 rq->error = "request does not fit the HBM budget";
                 rq->done = true;
+                ++st.requests_done;
                 rq->t_admit = rq->t_done = now_s();
             }
             cv_done.notify_all();
@@ -268,6 +274,7 @@ struct Server {
         BB_LAUNCH_CHECK();
         for (Request *rq : batch) rq->batch_r = c0;
         BB_HIP(hipEventRecord(s.done, s.stream));
+        ++st.batches;
         e->busy = true;
         e->last_use = ++tick;
         s.entry = e;
@@ -448,6 +455,20 @@ bbfmm_status bbfmm_server_wait(bbfmm_server *sv, uint64_t request_id, bbfmm_requ
         const std::string err = rq->error;
         s.requests.erase(it);
         if (st != BBFMM_OK) fail(st, "%s", err.c_str());
+        return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    }
+}
+
+bbfmm_status bbfmm_server_get_stats(bbfmm_server *sv, bbfmm_server_stats *out) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(sv != nullptr && out != nullptr, "NULL argument");
+        Server &s = *sv->impl;
+        std::lock_guard<std::mutex> lk(s.mu);
+        *out = s.st;
+        out->bytes_in_use = s.in_use;
         return BBFMM_OK;
     } catch (const Exception &e) {
         return e.status;

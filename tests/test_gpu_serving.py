@@ -74,6 +74,9 @@ def test_mix_equals_alone_and_batches():
         print(f"model {m}: {sig_all.shape[1]} served columns, max rel err vs oracle {err:.2e}")
         assert err < 1e-5
     assert any(st["batch_r"] > sig.shape[1] for (_, sig, _, _), st in zip(reqs, stats))
+    c = srv.stats()
+    assert c["requests_done"] == len(reqs) and 0 < c["batches"] < len(reqs)
+    assert 0 < c["plans_created"] and c["bytes_peak"] <= 4 << 30
     srv.close()
 
 
