@@ -214,7 +214,14 @@ bbfmm_status bbfmm_matvec(const bbfmm_tree *tree, const bbfmm_ops *ops,
 /*
  * A reusable matvec for a fixed (tree, operators, r) that owns its
  * workspace, so repeated products allocate nothing.  plan_execute has the
- * semantics of bbfmm_matvec.  The tree and operators must outlive the plan.
+ * semantics of bbfmm_matvec but is asynchronous: it enqueues the product on
+ * `stream` and returns.  With the overlapped schedule (option `overlap`)
+ * the near field runs on a stream the plan owns, forked from and joined
+ * back into `stream` with events, so all of the product's work is still
+ * ordered after earlier work on `stream` and before later work on it.  One
+ * plan's workspace serves one product at a time: products of one plan on
+ * different streams must be ordered by the caller.  The tree and operators
+ * must outlive the plan.
  */
 bbfmm_status bbfmm_plan_create(const bbfmm_tree *tree, const bbfmm_ops *ops,
                                int64_t r, bbfmm_plan **out);
