@@ -179,6 +179,35 @@ def batched_variants(steps: int, warmup: int, tune: bool):
     return out
 
 
+def pca_section(n: int = 80_000, k: int = 100, l: int = 120):
+    """The geostatistics application: top-k eigenpairs of the exp(-r)
+    covariance of n uniform points (p = 4, 4 levels as in the paper's
+    N = 8e4 run) from two block products with l random right-hand sides."""
+    import numpy as np
+    import torch
+
+    from paper_1903_02153_amd import bbfmm, pca
+    rng = np.random.default_rng(150)
+    pts = torch.from_numpy(rng.random((n, 3)).astype(np.float32)).cuda()
+    omega = torch.from_numpy(rng.standard_normal((n, l)).astype(np.float32)).cuda()
+    tree = bbfmm.build_tree(pts, bbfmm.K_EXP, 1.0, cheb_order=4, fixed_depth=4)
+    ops = bbfmm.precompute_operators(tree, 1e-5)
+    plan = bbfmm.Plan(tree, ops, l)
+    pca.randomized_eigh(tree, ops, omega, k, plan)          # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        lam, _ = pca.randomized_eigh(tree, ops, omega, k, plan)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return {"N": n, "k": k, "l": l, "kernel": "exp(-r)", "order": 4, "depth": 4,
+            "ms_median": round(float(np.median(times)) * 1e3, 3),
+            "lambda_1": float(lam[0]), "lambda_k": float(lam[-1]),
+            "note": "two block products of l columns + CholeskyQR2 + l x l eigensolver, "
+                    "wall clock per call"}
+
+
 def serving_mix(n_requests: int, budget_gib: float, load: float):
     """The 8-tree serving mix: calibrate capacity with closed-loop bursts,
     then replay a Poisson stream at `load` x capacity and report latency
@@ -418,6 +447,9 @@ def main() -> int:
         out["serving"] = serving_mix(args.serving_requests, args.serving_budget_gib,
                                      args.serving_load)
         progress("serving mix done")
+    if not args.no_variants:
+        out["pca"] = pca_section()
+        progress("randomized eigendecomposition done")
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         plan.execute(sig, phi)
