@@ -75,6 +75,23 @@ __device__ inline void lagrange(const ChebConst &cc, float xi, float *out) {
     }
 }
 
+// The same with the order fixed at compile time (loops unrolled, the node
+// tables read with constant indices).
+template <int N>
+__device__ inline void lagrange_t(const ChebConst &cc, float xi, float *out) {
+    float d[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = xi - cc.s[k];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        float p = cc.w[m];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k != m) p *= d[k];
+        out[m] = p;
+    }
+}
+
 struct Geo {
     float lo[3];
     float h;        // half-width of a leaf
@@ -82,11 +99,23 @@ struct Geo {
 };
 
 // ----------------------------------------------------------- kernels ----
+// 1/r excludes coincident points (the kernel is singular there).  Instead of
+// a compare and a select, r^2 is formed with a bias of -2^-126 folded into
+// its first FMA: a zero distance gives a negative argument, v_rsq_f32
+// returns NaN and the IEEE maximum with 0 returns 0.  For r^2 >= 2^-100 the
+// bias is below half an ulp and r^2 is unchanged; pairs closer than about
+// 1e-19 count as coincident.
+constexpr float kInvRBias = 1.17549435e-38f;   // 2^-126
+
 template <int KID>
 __device__ inline float kernel_eval(float dx, float dy, float dz, float ia, float ia2) {
+    if constexpr (KID == BBFMM_K_INV_R) {
+        const float r2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, __fmaf_rn(dz, dz, -kInvRBias)));
+        return __builtin_fmaxf(__frsqrt_rn(r2), 0.f);
+    }
     const float r2 = dx * dx + dy * dy + dz * dz;
     if constexpr (KID == BBFMM_K_INV_R) {
-        return r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
+        return 0.f;
     } else if constexpr (KID == BBFMM_K_EXP) {
         // v_sqrt_f32 and v_exp_f32 (1 ulp); the scale is loop-invariant
         return __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * (ia * -1.44269504088896341f));
@@ -124,60 +153,88 @@ struct NodeIdx {
     static constexpr int Q = (m + 63) / 64;     // node slots per lane
 };
 
-// P2M: M[leaf][c][i] = sum_p L_i(xi_p) sigma_p[c]   (grid: leaves x r)
+// P2M: M[leaf][c][node] = sum_p Lx_i1(p) Ly_i2(p) Lz_i3(p) sigma_p[c]   (grid:
+// ceil(leaves / G) x r).  The wave holds G = 64 / n^2 leaves, one per group
+// of n^2 lanes; lane (i2, i3) of a group keeps the n sums over i1 in
+// registers and per point adds Ly Lz times the n values Lx sigma, which the
+// whole group reads from one LDS row.  The points of all G leaves are
+// requested together, so the wave waits for memory once per chunk.
 template <int N>
 __global__ void __launch_bounds__(64)
 k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-      const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int ld, int r, int mp,
-      float *M) {
-    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
-    __shared__ float lv[64][3][N];
-    __shared__ float sg[64];
+      const uint64_t *keys, int nleaf, Geo geo, ChebConst cc, const float *sig_s, int ld, int r,
+      int mp, float *M) {
+    constexpr int m = N * N * N, NP = N * N, G = 64 / NP;
+    __shared__ float wx[G][64][N], wy[G][64][N], wz[G][64][N];   // Lx sigma, Ly, Lz per point
     const int lane = threadIdx.x;
-    const int a = blockIdx.x, c = blockIdx.y;
-    const uint64_t key = keys[a];
-    float chi[3], clo[3];
-    for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
-    float acc[Q];
-    int i1[Q], i2[Q], i3[Q];
+    const int c = blockIdx.y;
+    const int a0 = blockIdx.x * G;
+    const int pq = lane % NP, g = lane / NP;
+    const int i2 = pq % N, i3 = pq / N;
+    // leaf of every group (uniform loads), and this lane's own
+    int lb[G], le[G];
+    uint64_t key[G];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = lane + 64 * q;
-        acc[q] = 0.f;
-        i1[q] = i % N;
-        i2[q] = (i / N) % N;
-        i3[q] = (i / (N * N)) % N;
+    for (int h = 0; h < G; ++h) {
+        const bool ok = a0 + h < nleaf;
+        lb[h] = ok ? pb[a0 + h] : 0;
+        le[h] = ok ? pe[a0 + h] : 0;
+        key[h] = ok ? keys[a0 + h] : 0;
     }
-    const int b = pb[a], e = pe[a];
-    for (int p0 = b; p0 < e; p0 += 64) {
-        const int np = min(64, e - p0);
-        __syncthreads();
-        if (lane < np) {
-            const float p[3] = {xs[p0 + lane], ys[p0 + lane], zs[p0 + lane]};
-            for (int d = 0; d < 3; ++d) {
-                float l[kMaxOrder];
-                lagrange(cc, local_coord(p[d], chi[d], clo[d], geo.inv_h), l);
+    int most = 0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) lv[lane][d][k] = l[k];
-            }
-            sg[lane] = sig_s[int64_t(p0 + lane) * ld + c];
+    for (int h = 0; h < G; ++h) most = max(most, le[h] - lb[h]);
+    float acc[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k] = 0.f;
+    for (int p0 = 0; p0 < most; p0 += 64) {
+        float px[G], py[G], pz[G], ps[G];
+#pragma unroll
+        for (int h = 0; h < G; ++h) {                 // all loads first
+            const int i = lb[h] + p0 + lane;
+            const bool ok = i < le[h];
+            const int q = ok ? i : lb[h];
+            px[h] = xs[q];
+            py[h] = ys[q];
+            pz[h] = zs[q];
+            ps[h] = ok ? sig_s[int64_t(q) * ld + c] : 0.f;
+        }
+        __syncthreads();                              // previous chunk consumed
+#pragma unroll
+        for (int h = 0; h < G; ++h) {
+            if (lb[h] + p0 + lane >= le[h]) continue;
+            float chi[3], clo[3], l[N];
+            for (int d = 0; d < 3; ++d)
+                center_pair(geo.lo[d], compact3(key[h] >> d), geo.h, chi[d], clo[d]);
+            lagrange_t<N>(cc, local_coord(px[h], chi[0], clo[0], geo.inv_h), l);
+#pragma unroll
+            for (int k = 0; k < N; ++k) wx[h][lane][k] = l[k] * ps[h];
+            lagrange_t<N>(cc, local_coord(py[h], chi[1], clo[1], geo.inv_h), l);
+#pragma unroll
+            for (int k = 0; k < N; ++k) wy[h][lane][k] = l[k];
+            lagrange_t<N>(cc, local_coord(pz[h], chi[2], clo[2], geo.inv_h), l);
+#pragma unroll
+            for (int k = 0; k < N; ++k) wz[h][lane][k] = l[k];
         }
         __syncthreads();
+        if (g < G) {
+            int nmine = 0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (lane + 64 * q < m) {
-                float s = acc[q];
-                for (int pp = 0; pp < np; ++pp)
-                    s += lv[pp][0][i1[q]] * lv[pp][1][i2[q]] * lv[pp][2][i3[q]] * sg[pp];
-                acc[q] = s;
+            for (int h = 0; h < G; ++h)
+                if (h == g) nmine = min(64, le[h] - lb[h] - p0);
+            for (int pp = 0; pp < nmine; ++pp) {
+                const float t = wy[g][pp][i2] * wz[g][pp][i3];
+#pragma unroll
+                for (int k = 0; k < N; ++k) acc[k] = __fmaf_rn(wx[g][pp][k], t, acc[k]);
             }
         }
     }
-    float *out = M + (int64_t(a) * r + c) * mp;
+    if (g < G && a0 + g < nleaf) {
+        float *out = M + (int64_t(a0 + g) * r + c) * mp;
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-        if (lane + 64 * q < m) out[lane + 64 * q] = acc[q];
-    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
+        for (int k = 0; k < N; ++k) out[pq * N + k] = acc[k];
+        for (int i = m + pq; i < mp; i += NP) out[i] = 0.f;
+    }
 }
 
 // P2M for blocks of right-hand sides on FP32 MFMA: M[leaf][c][node] =
@@ -329,17 +386,19 @@ __device__ inline void load_T(const ChebConst &cc, float (*Ts)[N][N]) {
     }
 }
 
-// M2M: M[P][c] = sum over children of (T (x) T (x) T) M[child][c]   (grid: parents x r)
+// M2M: M[P][c] = sum over children of (T (x) T (x) T) M[child][c]   (grid: parents x r).
+// The (at most 8) children's coefficients are all requested before the
+// first is used, so the wave waits for memory once; the translations then
+// run child by child from LDS and are summed in child order.
 template <int N>
 __global__ void __launch_bounds__(64)
 k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Mc, ChebConst cc,
       int r, int mp, float *M) {
     constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
     __shared__ float Ts[2][N][N];
-    __shared__ float A[64 * Q], B[64 * Q];
+    __shared__ float Cs[8][64 * Q], B[64 * Q];
     const int lane = threadIdx.x;
     const int P = blockIdx.x, c = blockIdx.y;
-    load_T<N>(cc, Ts);
     float acc[Q], t[Q];
     int i1[Q], i2[Q], i3[Q];
 #pragma unroll
@@ -350,17 +409,27 @@ k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *
         i2[q] = (i / N) % N;
         i3[q] = (i / (N * N)) % N;
     }
-    for (int ch = cb[P]; ch < ce[P]; ++ch) {
-        const int o = int(ckeys[ch] & 7);
-        const float *src = Mc + (int64_t(ch) * r + c) * mp;
-        __syncthreads();
+    const int c0 = cb[P], nc = min(ce[P] - c0, 8);
+    float v[8][Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (lane + 64 * q < m) A[lane + 64 * q] = src[lane + 64 * q];
-        __syncthreads();
-        mode3<N>(A, B, Ts, o, false, i1, i2, i3, t);
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = lane + 64 * q;
+            v[k][q] = (k < nc && i < m) ? Mc[(int64_t(c0 + k) * r + c) * mp + i] : 0.f;
+        }
+    load_T<N>(cc, Ts);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Cs[k][lane + 64 * q] = v[k][q];
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        const int o = int(ckeys[c0 + k] & 7);
+        mode3<N>(Cs[k], B, Ts, o, false, i1, i2, i3, t);
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] += t[q];
+        __syncthreads();       // B is rewritten by the next child's first mode product
     }
     float *out = M + (int64_t(P) * r + c) * mp;
 #pragma unroll
@@ -1066,15 +1135,31 @@ template <int KID, int RC, int S>
 __device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? RC - 1 : 1],
                                    int npad, int sub, float x, float y, float z, float ia,
                                    float ia2, float *acc) {
-    for (int u = 0; u < npad; u += 4 * S) {
+    if constexpr (RC == 1) {
+        float a0 = 0.f, a1 = 0.f;
+        for (int u = 0; u < npad; u += 8 * S) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int jj = u + v * S + sub;
-            const float4 q = sp[jj];
-            const float k = kernel_eval<KID>(x - q.x, y - q.y, z - q.z, ia, ia2);
-            acc[0] += k * q.w;
+            for (int v = 0; v < 8; v += 2) {
+                const float4 q0 = sp[u + v * S + sub];
+                const float4 q1 = sp[u + (v + 1) * S + sub];
+                const float k0 = kernel_eval<KID>(x - q0.x, y - q0.y, z - q0.z, ia, ia2);
+                const float k1 = kernel_eval<KID>(x - q1.x, y - q1.y, z - q1.z, ia, ia2);
+                a0 += k0 * q0.w;
+                a1 += k1 * q1.w;
+            }
+        }
+        acc[0] += a0 + a1;
+    } else {
+        for (int u = 0; u < npad; u += 4 * S) {
 #pragma unroll
-            for (int c = 1; c < RC; ++c) acc[c] += k * ss[jj][c - 1];
+            for (int v = 0; v < 4; ++v) {
+                const int jj = u + v * S + sub;
+                const float4 q = sp[jj];
+                const float k = kernel_eval<KID>(x - q.x, y - q.y, z - q.z, ia, ia2);
+                acc[0] += k * q.w;
+#pragma unroll
+                for (int c = 1; c < RC; ++c) acc[c] += k * ss[jj][c - 1];
+            }
         }
     }
 }
@@ -1088,6 +1173,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
     constexpr int CAP = P2PCap<RC>::value;
     __shared__ float4 sp[CAP];                        // x, y, z, sigma of the first rhs
     __shared__ float ss[CAP][RC > 1 ? RC - 1 : 1];    // remaining rhs
+    __shared__ int32_t nb_end[64], nb_src[64];        // neighbour chunk: running end, first point
     const int lane = threadIdx.x;
     // grid-stride over the work items: a launch of fewer workgroups than items
     // keeps the near field to a share of the chip (overlapped schedule)
@@ -1103,38 +1189,75 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         float acc[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = 0.f;
-        // walk the neighbour list, filling LDS passes of up to CAP records
+        // The neighbour leaves' records form one sequence (list order, points
+        // in tree order), cut into LDS passes of CAP records.  A chunk of up
+        // to 64 neighbours is described by one lane each (first point and
+        // record count, prefix-summed across the wave), so a pass is staged
+        // with independent loads: record e of the chunk belongs to the first
+        // neighbour whose running end exceeds e (binary search in LDS).
         const int q0 = nbr_off[a], q1 = nbr_off[a + 1];
-        int q = q0, off = 0;   // next neighbour and offset within it
-        while (q < q1) {
-            int n = 0;
-            __syncthreads();
-            while (q < q1 && n < CAP) {
-                const int b = nbr_idx[q];
-                const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - n);
-                for (int e = lane; e < cnt; e += 64) {
-                    const float *sg = sig_s + int64_t(sb + e) * r + rhs0;
-                    sp[n + e] = make_float4(xs[sb + e], ys[sb + e], zs[sb + e], sg[0]);
+        for (int qc = q0; qc < q1; qc += 64) {
+            int sb = 0, cnt = 0;
+            if (qc + lane < q1) {
+                const int b = nbr_idx[qc + lane];
+                sb = pb[b];
+                cnt = pe[b] - sb;
+            }
+            int inc = cnt;
 #pragma unroll
-                    for (int c = 1; c < RC; ++c) ss[n + e][c - 1] = c < nr ? sg[c] : 0.f;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int t = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += t;
+            }
+            const int total = __shfl(inc, 63, 64);
+            __syncthreads();                     // the previous chunk's table is consumed
+            nb_end[lane] = inc;
+            nb_src[lane] = sb - (inc - cnt);     // record e of this neighbour is point nb_src + e
+            for (int base = 0; base < total; base += CAP) {
+                const int n = min(CAP, total - base);
+                __syncthreads();                 // table visible, previous pass consumed
+                constexpr int KS = CAP / 64;
+                int src[KS];
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {          // all searches, then all loads
+                    const int e = base + lane + 64 * k;
+                    int j = 0;
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (nb_end[j + st - 1] <= e) j += st;
+                    src[k] = e < base + n ? nb_src[min(j, 63)] + e : -1;
                 }
-                n += cnt;
-                if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
-            }
-            // CAP is a multiple of 64 >= 4 S, so the padded count stays within LDS
-            const int npad = min(CAP, (n + 4 * S - 1) / (4 * S) * (4 * S));
-            for (int e = n + lane; e < npad; e += 64) {
-                sp[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 rec[KS];
 #pragma unroll
-                for (int c = 1; c < RC; ++c) ss[e][c - 1] = 0.f;
-            }
-            __syncthreads();
-            switch (lgS) {
-            case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-            case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-            case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-            case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-            default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                for (int k = 0; k < KS; ++k) {
+                    const int q = max(src[k], 0);
+                    rec[k] = make_float4(xs[q], ys[q], zs[q], sig_s[int64_t(q) * r + rhs0]);
+                }
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const float w = src[k] >= 0 ? 1.f : 0.f;
+                    sp[lane + 64 * k] = make_float4(rec[k].x * w, rec[k].y * w, rec[k].z * w, rec[k].w * w);
+                }
+                if constexpr (RC > 1) {
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        const float *sg = sig_s + int64_t(max(src[k], 0)) * r + rhs0;
+                        const float w = src[k] >= 0 ? 1.f : 0.f;
+#pragma unroll
+                        for (int c = 1; c < RC; ++c) ss[lane + 64 * k][c - 1] = c < nr ? sg[c] * w : 0.f;
+                    }
+                }
+                // records n .. CAP are zero; the loop below reads up to a multiple of 4 S
+                const int G = RC == 1 ? 8 * S : 4 * S;
+                const int npad = min(CAP, (n + G - 1) / G * G);
+                __syncthreads();
+                switch (lgS) {
+                case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                }
             }
         }
         if (FL != nullptr && valid) {
@@ -1938,10 +2061,10 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         BB_LAUNCH_CHECK();
     } else if (L >= 2) {
         const LevelData &leaf = t.lv[L];
-        dim3 g(leaf.C, r);
         switch (n) {
-#define BB_P2M(NN) case NN: k_p2m<NN><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, \
-            leaf.keys.p, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
+#define BB_P2M(NN) case NN: k_p2m<NN><<<dim3(unsigned(ceil_div(leaf.C, 64 / ((NN) * (NN)))), unsigned(r)), \
+            64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, leaf.keys.p, int(leaf.C), geo, \
+            o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
         BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
 #undef BB_P2M
         }
