@@ -1520,40 +1520,70 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
 // Far field added to phi, one thread per point (tree order):
 // phi[perm[i]][c] += sum_node S[i][node] F[leaf(i)][c][node], with the
 // separable Lagrange product summed x fastest.  Runs after the near field
-// has written phi (the overlapped schedule).
+// has written phi (the overlapped schedule).  The local expansions of the
+// leaves that a workgroup's points fall in are staged in LDS (one padded
+// row per leaf, so the lanes of different leaves read different banks);
+// a workgroup whose points span more leaves than fit reads them from
+// global memory instead.
+constexpr int kL2PLdsFloats = 8192;
+
+template <int N>
+__device__ inline float l2p_sum(const float *f, const float (*l)[N]) {
+    float sacc = 0.f;
+#pragma unroll
+    for (int i3 = 0; i3 < N; ++i3) {
+        float s2 = 0.f;
+#pragma unroll
+        for (int i2 = 0; i2 < N; ++i2) {
+            float s1 = 0.f;
+#pragma unroll
+            for (int i1 = 0; i1 < N; ++i1) s1 += l[0][i1] * f[(i3 * N + i2) * N + i1];
+            s2 += l[1][i2] * s1;
+        }
+        sacc += l[2][i3] * s2;
+    }
+    return sacc;
+}
+
 template <int N>
 __global__ void __launch_bounds__(kThreads)
 k_l2p(const float *xs, const float *ys, const float *zs, const int32_t *pleaf, const uint64_t *keys,
       const int32_t *perm, int64_t npts, int r, const float *FL, int mp, Geo geo, ChebConst cc,
       float *phi) {
-    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (i >= npts) return;
-    const int a = pleaf[i];
-    const uint64_t key = keys[a];
-    const float p3[3] = {xs[i], ys[i], zs[i]};
-    float l[3][kMaxOrder];
-    for (int d = 0; d < 3; ++d) {
-        float chi, clo;
-        center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
-        lagrange(cc, local_coord(p3[d], chi, clo, geo.inv_h), l[d]);
-    }
-    float *out = phi + int64_t(perm[i]) * r;
-    for (int c = 0; c < r; ++c) {
-        const float *f = FL + (int64_t(a) * r + c) * mp;
-        float sacc = 0.f;
-#pragma unroll
-        for (int i3 = 0; i3 < N; ++i3) {
-            float s2 = 0.f;
-#pragma unroll
-            for (int i2 = 0; i2 < N; ++i2) {
-                float s1 = 0.f;
-#pragma unroll
-                for (int i1 = 0; i1 < N; ++i1) s1 += l[0][i1] * f[(i3 * N + i2) * N + i1];
-                s2 += l[1][i2] * s1;
-            }
-            sacc += l[2][i3] * s2;
+    constexpr int m = N * N * N, RS = m | 1;          // LDS row stride (odd)
+    __shared__ float fs[kL2PLdsFloats];
+    const int64_t i0 = int64_t(blockIdx.x) * kThreads;
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t ilast = min(i0 + kThreads, npts) - 1;
+    const int afirst = pleaf[i0], alast = pleaf[ilast];
+    const int nl = alast - afirst + 1;
+    const bool staged = int64_t(nl) * RS <= kL2PLdsFloats;      // uniform
+    const bool active = i < npts;
+    const int a = active ? pleaf[i] : afirst;
+    float l[3][N];
+    if (active) {
+        const uint64_t key = keys[a];
+        const float p3[3] = {xs[i], ys[i], zs[i]};
+        for (int d = 0; d < 3; ++d) {
+            float chi, clo;
+            center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
+            lagrange_t<N>(cc, local_coord(p3[d], chi, clo, geo.inv_h), l[d]);
         }
-        out[c] += sacc;
+    }
+    for (int c = 0; c < r; ++c) {
+        float sacc = 0.f;
+        if (staged) {
+            __syncthreads();                  // previous column consumed
+            for (int e = threadIdx.x; e < nl * m; e += kThreads) {
+                const int la = e / m, node = e - la * m;
+                fs[la * RS + node] = FL[(int64_t(afirst + la) * r + c) * mp + node];
+            }
+            __syncthreads();
+            if (active) sacc = l2p_sum<N>(fs + (a - afirst) * RS, l);
+        } else if (active) {
+            sacc = l2p_sum<N>(FL + (int64_t(a) * r + c) * mp, l);
+        }
+        if (active) phi[int64_t(perm[i]) * r + c] += sacc;
     }
 }
 
