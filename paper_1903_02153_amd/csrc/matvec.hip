@@ -1705,8 +1705,10 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     const int mp = o->mp;
     p->rc_m2l = int(std::min<int64_t>(r, kM2LCols));
     p->tpt = kM2LCols / p->rc_m2l;
+    // right-hand sides per per-lane near-field launch column (at most 32: with
+    // 64 accumulators per lane the kernel would spill to scratch memory)
     p->rc_p2p = 1;
-    while (p->rc_p2p < r && p->rc_p2p < 64) p->rc_p2p *= 2;
+    while (p->rc_p2p < r && p->rc_p2p < 32) p->rc_p2p *= 2;
     p->p2p_mfma = op.p2p_mfma == 0 ? r >= kP2PMfmaMinR : op.p2p_mfma == 2;
     p->ncb_p2p = r <= 16 ? 1 : (r <= 32 ? 2 : 4);
     p->ld_s = p->p2p_mfma ? int(16 * p->ncb_p2p * ceil_div(r, 16 * p->ncb_p2p)) : int(r);
@@ -1948,8 +1950,7 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
     case 4: BB_P2P(4); break;
     case 8: BB_P2P(8); break;
     case 16: BB_P2P(16); break;
-    case 32: BB_P2P(32); break;
-    default: BB_P2P(64); break;
+    default: BB_P2P(32); break;
     }
 #undef BB_P2P
     BB_LAUNCH_CHECK();
