@@ -107,26 +107,38 @@ struct Geo {
 // 1e-19 count as coincident.
 constexpr float kInvRBias = 1.17549435e-38f;   // 2^-126
 
+// Kernel values from coordinate differences that are already multiplied by
+// the kernel's coordinate scale (coord_scale below), so that no per-pair
+// multiply is left: exp(-r/a) = 2^-(r log2(e) / a) and exp(-r^2/a^2) =
+// 2^-(r sqrt(log2 e) / a)^2 with the sign as a free source modifier.
 template <int KID>
-__device__ inline float kernel_eval(float dx, float dy, float dz, float ia, float ia2) {
+__device__ inline float kernel_eval(float dx, float dy, float dz) {
     if constexpr (KID == BBFMM_K_INV_R) {
         const float r2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, __fmaf_rn(dz, dz, -kInvRBias)));
         return __builtin_fmaxf(__frsqrt_rn(r2), 0.f);
-    }
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if constexpr (KID == BBFMM_K_INV_R) {
-        return 0.f;
     } else if constexpr (KID == BBFMM_K_EXP) {
-        // v_sqrt_f32 and v_exp_f32 (1 ulp); the scale is loop-invariant
-        return __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * (ia * -1.44269504088896341f));
+        // v_sqrt_f32 and v_exp_f32 (1 ulp each)
+        return __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz));
     } else if constexpr (KID == BBFMM_K_GAUSS) {
-        return __builtin_amdgcn_exp2f(r2 * (ia2 * -1.44269504088896341f));
+        return __builtin_amdgcn_exp2f(-(dx * dx + dy * dy + dz * dz));
     } else {
-        const float u[3] = {dx * ia, dy * ia, dz * ia};
+        const float u[3] = {dx, dy, dz};
         float p = 1.f;
         for (int d = 0; d < 3; ++d)
             p *= 1.f + u[d] * 0.5f - u[d] * u[d] * (1.f / 3.f) + u[d] * u[d] * u[d] * 0.2f;
         return p;
+    }
+}
+
+// Factor applied to every coordinate before kernel_eval (1/r is scale-free
+// up to a constant and is evaluated unscaled).
+inline float coord_scale(int kid, double a) {
+    const double log2e = 1.4426950408889634;
+    switch (kid) {
+    case BBFMM_K_INV_R: return 1.f;
+    case BBFMM_K_EXP: return float(log2e / a);
+    case BBFMM_K_GAUSS: return float(std::sqrt(log2e) / a);
+    default: return float(1.0 / a);
     }
 }
 
@@ -1133,8 +1145,7 @@ struct P2PCap {   // records per LDS pass: a multiple of 64, about 8-17 KB of LD
 
 template <int KID, int RC, int S>
 __device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? RC - 1 : 1],
-                                   int npad, int sub, float x, float y, float z, float ia,
-                                   float ia2, float *acc) {
+                                   int npad, int sub, float x, float y, float z, float *acc) {
     if constexpr (RC == 1) {
         float a0 = 0.f, a1 = 0.f;
         for (int u = 0; u < npad; u += 8 * S) {
@@ -1142,8 +1153,8 @@ __device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? 
             for (int v = 0; v < 8; v += 2) {
                 const float4 q0 = sp[u + v * S + sub];
                 const float4 q1 = sp[u + (v + 1) * S + sub];
-                const float k0 = kernel_eval<KID>(x - q0.x, y - q0.y, z - q0.z, ia, ia2);
-                const float k1 = kernel_eval<KID>(x - q1.x, y - q1.y, z - q1.z, ia, ia2);
+                const float k0 = kernel_eval<KID>(x - q0.x, y - q0.y, z - q0.z);
+                const float k1 = kernel_eval<KID>(x - q1.x, y - q1.y, z - q1.z);
                 a0 += k0 * q0.w;
                 a1 += k1 * q1.w;
             }
@@ -1155,7 +1166,7 @@ __device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? 
             for (int v = 0; v < 4; ++v) {
                 const int jj = u + v * S + sub;
                 const float4 q = sp[jj];
-                const float k = kernel_eval<KID>(x - q.x, y - q.y, z - q.z, ia, ia2);
+                const float k = kernel_eval<KID>(x - q.x, y - q.y, z - q.z);
                 acc[0] += k * q.w;
 #pragma unroll
                 for (int c = 1; c < RC; ++c) acc[c] += k * ss[jj][c - 1];
@@ -1168,7 +1179,7 @@ template <int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
       const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
-      const int32_t *work, int nwork, const float *sig_s, int r, float ia, float ia2,
+      const int32_t *work, int nwork, const float *sig_s, int r, float cs,
       const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
     constexpr int CAP = P2PCap<RC>::value;
     __shared__ float4 sp[CAP];                        // x, y, z, sigma of the first rhs
@@ -1186,6 +1197,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         const int i = t0 + (lane >> lgS);
         const bool valid = i < pe[a];
         const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
+        const float xc = x * cs, yc = y * cs, zc = z * cs;   // kernel coordinates
         float acc[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = 0.f;
@@ -1235,8 +1247,8 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                 }
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
-                    const float w = src[k] >= 0 ? 1.f : 0.f;
-                    sp[lane + 64 * k] = make_float4(rec[k].x * w, rec[k].y * w, rec[k].z * w, rec[k].w * w);
+                    const float w = src[k] >= 0 ? 1.f : 0.f, wc = w * cs;
+                    sp[lane + 64 * k] = make_float4(rec[k].x * wc, rec[k].y * wc, rec[k].z * wc, rec[k].w * w);
                 }
                 if constexpr (RC > 1) {
 #pragma unroll
@@ -1252,11 +1264,11 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                 const int npad = min(CAP, (n + G - 1) / G * G);
                 __syncthreads();
                 switch (lgS) {
-                case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-                case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-                case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-                case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
-                default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, x, y, z, ia, ia2, acc); break;
+                case 0: p2p_records<KID, RC, 1>(sp, ss, npad, sub, xc, yc, zc, acc); break;
+                case 1: p2p_records<KID, RC, 2>(sp, ss, npad, sub, xc, yc, zc, acc); break;
+                case 2: p2p_records<KID, RC, 4>(sp, ss, npad, sub, xc, yc, zc, acc); break;
+                case 3: p2p_records<KID, RC, 8>(sp, ss, npad, sub, xc, yc, zc, acc); break;
+                default: p2p_records<KID, RC, 16>(sp, ss, npad, sub, xc, yc, zc, acc); break;
                 }
             }
         }
@@ -1322,7 +1334,7 @@ template <int KID, int NCB, int NRB>
 __global__ void __launch_bounds__(64)
 k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
            const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
-           const int32_t *work, const float *sig_s, int ld, int r, float ia, float ia2,
+           const int32_t *work, const float *sig_s, int ld, int r, float cs,
            const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
     constexpr int CW = 16 * NCB;            // columns of this wave
     constexpr int SST = CW == 16 ? 16 : CW + 16;   // = 16 mod 32: rows k, k+1 on disjoint banks
@@ -1456,7 +1468,8 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
             const int e = lane + 64 * u;
-            sp[e] = e < cnt ? make_float4(cx[u], cy[u], cz[u], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+            sp[e] = e < cnt ? make_float4(cx[u] * cs, cy[u] * cs, cz[u] * cs, 0.f)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < SPL; ++u) {
@@ -1467,6 +1480,12 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
         }
     };
     __syncthreads();                    // Lagrange values (in ss) are consumed
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {  // kernel coordinates from here on
+        tx[rb] *= cs;
+        ty[rb] *= cs;
+        tz[rb] *= cs;
+    }
     int cnt = q < q1 ? fetch() : 0;
     while (cnt > 0) {
         publish(cnt);
@@ -1490,7 +1509,7 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
             float kv[NRB];
 #pragma unroll
             for (int rb = 0; rb < NRB; ++rb)
-                kv[rb] = kernel_eval<KID>(tx[rb] - sq.x, ty[rb] - sq.y, tz[rb] - sq.z, ia, ia2);
+                kv[rb] = kernel_eval<KID>(tx[rb] - sq.x, ty[rb] - sq.y, tz[rb] - sq.z);
 #pragma unroll
             for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
@@ -1908,7 +1927,7 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
     const bbfmm_tree &t = *p.tree;
     const LevelData &leaf = t.lv[t.leaf_level()];
     const double a = t.params.kernel_param;
-    const float ia = float(1.0 / a), ia2 = float(1.0 / (a * a));
+    const float cs = coord_scale(t.params.kernel_id, a);
     if (p.p2p_mfma) {
         for (int nrb = 1; nrb <= 4; ++nrb) {
             const int w0 = p.mfma_off[nrb - 1], nw = p.mfma_off[nrb] - w0;
@@ -1918,7 +1937,7 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
 #define BB_P2PM(NCB, NRB)                                                                     \
             k_p2p_mfma<KID, NCB, NRB><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p,        \
                 leaf.pe.p, t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p, wk, p.sig_s.p,       \
-                p.ld_s, int(p.r), ia, ia2, FL, p.ops->mp, geo, p.ops->cheb, phi)
+                p.ld_s, int(p.r), cs, FL, p.ops->mp, geo, p.ops->cheb, phi)
 #define BB_P2PM_R(NCB)                                                                        \
             switch (nrb) {                                                                    \
             case 1: BB_P2PM(NCB, 1); break;                                                   \
@@ -1942,7 +1961,7 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
 #define BB_P2P(RCV)                                                                          \
     k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
                                      t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p,         \
-                                     p.work.p, p.nwork, p.sig_s.p, int(p.r), ia, ia2, FL,     \
+                                     p.work.p, p.nwork, p.sig_s.p, int(p.r), cs, FL,         \
                                      p.ops->mp, geo, p.ops->cheb, phi)
     switch (p.rc_p2p) {
     case 1: BB_P2P(1); break;
