@@ -1133,8 +1133,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
 // T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes").
 // The sources of all neighbour leaves are copied into LDS in as few passes
 // as fit (x, y, z, sigma packed in one 16-byte record, zero-padded to a
-// multiple of 4 S records so the inner loop is uniform and unrolled; padding
-// records have sigma = 0 and a finite kernel value).  Sub-lane s takes
+// multiple of the inner loop's step -- 8 S records for one right-hand side,
+// 4 S otherwise -- so the loop is uniform and unrolled; padding records have
+// sigma = 0 and a finite kernel value).  Sub-lane s takes
 // records s, s + S, ... and the i3 planes s, s + S, ... of the L2P sum; the
 // S partial sums of a target are added by a fixed butterfly of cross-lane
 // shuffles, so results are reproducible.
@@ -1259,7 +1260,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
                         for (int c = 1; c < RC; ++c) ss[lane + 64 * k][c - 1] = c < nr ? sg[c] * w : 0.f;
                     }
                 }
-                // records n .. CAP are zero; the loop below reads up to a multiple of 4 S
+                // records n .. CAP are zero; the loop below reads up to a multiple of its step
                 const int G = RC == 1 ? 8 * S : 4 * S;
                 const int npad = min(CAP, (n + G - 1) / G * G);
                 __syncthreads();
