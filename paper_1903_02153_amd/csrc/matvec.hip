@@ -183,7 +183,7 @@ k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
     const int a0 = blockIdx.x * G;
     const int pq = lane % NP, g = lane / NP;
     const int i2 = pq % N, i3 = pq / N;
-    // leaf of every group (uniform loads), and this lane's own
+    // the leaf of every group (uniform loads)
     int lb[G], le[G];
     uint64_t key[G];
 #pragma unroll
