@@ -48,7 +48,9 @@ typedef enum {
 
 /* Kernel functions (Sections 1 and 4; all translation invariant). */
 enum {
-    BBFMM_K_INV_R = 0,      /* 1/|x-y|; K = 0 where |x-y|^2 == 0; homogeneous, degree -1 */
+    BBFMM_K_INV_R = 0,      /* 1/|x-y|; K = 0 where |x-y|^2 == 0 (on the GPU also for
+                               |x-y|^2 < 2^-126, i.e. points closer than ~1e-19);
+                               homogeneous, degree -1                              */
     BBFMM_K_EXP = 1,        /* exp(-|x-y|/a), a = kernel_param                         */
     BBFMM_K_GAUSS = 2,      /* exp(-|x-y|^2/a^2), a = kernel_param                      */
     BBFMM_K_POLY_TEST = 100 /* prod_d g((x_d-y_d)/a), g(u) = 1 + u/2 - u^2/3 + u^3/5:
