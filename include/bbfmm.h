@@ -21,9 +21,16 @@
  *     plan_execute are asynchronous.  A fault inside a kernel surfaces at
  *     the next synchronising call.
  *   - Handles (trees, operator sets, plans) own their device memory and are
- *     immutable after creation, except that a plan owns a workspace, so a
- *     plan must not be executed concurrently with itself.  Distinct plans on
- *     distinct streams may run concurrently.
+ *     immutable after creation, except that a plan owns a workspace: the
+ *     library orders the products of one plan one after another (each waits
+ *     for the previous one, whatever stream it ran on), so a plan never runs
+ *     concurrently with itself.  Distinct plans may run concurrently.
+ *   - Device memory of a handle comes from the bbfmm_allocator given when
+ *     the tree was built (operator sets and plans inherit it unless given
+ *     their own), or from hipMalloc when none was given.
+ *   - Freeing a plan waits until its last product has finished.  A tree or
+ *     an operator set must outlive the plans and servers that use it, and
+ *     is freed only once no enqueued product uses it any more.
  *   - Free functions accept NULL.
  */
 #ifndef BBFMM_H
@@ -41,7 +48,7 @@ typedef enum {
     BBFMM_ERR_INVALID_ARG = 1,   /* bad size, pointer, option or input value */
     BBFMM_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed        */
     BBFMM_ERR_HIP = 3,           /* a HIP runtime call or launch failed       */
-    BBFMM_ERR_BUDGET = 4,        /* reserved: request exceeds a memory budget */
+    BBFMM_ERR_BUDGET = 4,        /* a server request exceeds the HBM budget   */
     BBFMM_ERR_NOT_FOUND = 5,     /* unknown array / level in an export        */
     BBFMM_ERR_INTERNAL = 6       /* an internal consistency check failed      */
 } bbfmm_status;
@@ -77,6 +84,28 @@ typedef struct {
     int32_t fixed_depth;   /* > 0: use exactly this many levels (1..22)             */
 } bbfmm_tree_params;
 
+/*
+ * Device-memory hook, so that a framework's allocator (for PyTorch: its
+ * caching allocator) owns every byte of device memory the library uses.
+ *   alloc(bytes, stream, ctx)  returns device memory on the current device
+ *       usable by work enqueued on `stream` after the call, or NULL when it
+ *       cannot (the library then frees what it already holds through `free`
+ *       and returns BBFMM_ERR_OUT_OF_MEMORY).  bytes > 0.
+ *   free(ptr, stream, ctx)     returns memory from `alloc`, with the same
+ *       stream.  The library calls it once all of its work that uses ptr has
+ *       been enqueued on `stream` (temporaries of a build) or has completed
+ *       (handles), so a stream-ordered allocator may hand the memory to work
+ *       enqueued later on that stream.
+ * Both may be called from any thread that calls into the library, and from
+ * a server's scheduler thread.  The hook (its functions and ctx) must stay
+ * valid until every handle built with it is freed.
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} bbfmm_allocator;
+
 typedef struct bbfmm_tree bbfmm_tree;
 typedef struct bbfmm_ops bbfmm_ops;
 typedef struct bbfmm_plan bbfmm_plan;
@@ -108,12 +137,16 @@ typedef struct {
  * (bit b of x, y, z at bits 3b, 3b+1, 3b+2).  Also built: the leaf
  * neighbour lists N(.) and, on every level >= 2, the interaction lists I(.)
  * grouped by transfer vector.
+ *   allocator  device-memory hook of the tree and, by default, of its
+ *              operator sets and plans; NULL = hipMalloc / hipFree.  Copied.
  * Errors: INVALID_ARG for n < 1, NULL pointers, non-finite coordinates,
  * cheb_order outside 2..8, leaf_size < 1, depths outside 1..22 or an unknown
- * kernel; OUT_OF_MEMORY; HIP.
+ * kernel; OUT_OF_MEMORY (also when the allocator returns NULL; nothing is
+ * leaked); HIP.
  */
 bbfmm_status bbfmm_build_tree(const float *points, int64_t n,
-                              const bbfmm_tree_params *params, void *stream,
+                              const bbfmm_tree_params *params,
+                              const bbfmm_allocator *allocator, void *stream,
                               bbfmm_tree **out);
 
 bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *tree, bbfmm_tree_info *out);
@@ -160,11 +193,13 @@ bbfmm_status bbfmm_tree_export(const bbfmm_tree *tree, int32_t what,
  * cast U, V, C_t to the matvec precision.  For the homogeneous kernel 1/r
  * one set is built and scaled by 1/h per level.  svd_eps = 0 disables the
  * compression (U = V = identity).
+ *   allocator  NULL = the tree's.
  * Errors: INVALID_ARG (svd_eps < 0 or not finite, unknown precision),
  * OUT_OF_MEMORY, HIP.  Synchronous.
  */
 bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *tree,
                                         double svd_eps, int32_t precision,
+                                        const bbfmm_allocator *allocator,
                                         void *stream, bbfmm_ops **out);
 
 /* Rank k of level l (levels >= 2), or NOT_FOUND. */
@@ -186,7 +221,8 @@ bbfmm_status bbfmm_ops_export(const bbfmm_ops *ops, int32_t what,
 
 /*
  * Build an operator set from host FP64 arrays instead of the SVD (lets a
- * caller test the matvec with given operators).
+ * caller test the matvec with given operators).  Device memory comes from
+ * the tree's allocator.
  *   ranks  host int32[depth]: k of each level (entries of levels 0, 1 unused)
  *   U, V   host double: for each level l >= 2 in order, m x k_l row-major
  *   C      host double: for each level l >= 2 in order, 316 x k_l x k_l,
@@ -202,10 +238,16 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *tree, int32_t precision,
  * phi = K sigma for r right-hand sides (Section 2.5, multiple RHS).
  *   sigma  device, N x r float32 row-major (r fastest), original point order.
  *   phi    device, N x r float32, overwritten; must not overlap sigma.
- * Runs gather, P2M, M2M, compression, M2L, decompression, L2L, L2P and P2P
- * on the stream with a temporary workspace, and returns once the product is
- * complete (the workspace is freed).  For repeated or asynchronous products
- * use a plan.
+ * Enqueues gather, P2M, M2M, compression, M2L, decompression, L2L, L2P and
+ * P2P on the stream and returns without waiting for them (asynchronous).
+ * The workspace comes from a cache held by the operator set: one plan per
+ * (r, stream) pair, the four most recently used kept (the oldest is freed
+ * once its last product has finished), so repeated products on a stream
+ * allocate nothing; the first product of a pair allocates through the
+ * operator set's allocator and uploads its launch lists (host work, no
+ * wait for the device).  Products on different streams run concurrently;
+ * a cached workspace used again on another stream is ordered after its
+ * previous product.  The cache is freed with the operator set.
  * Errors: INVALID_ARG (r < 1 or > 4096, NULL pointers, ops not built for
  * this tree), OUT_OF_MEMORY, HIP.
  */
@@ -216,14 +258,18 @@ bbfmm_status bbfmm_matvec(const bbfmm_tree *tree, const bbfmm_ops *ops,
 /*
  * A reusable matvec for a fixed (tree, operators, r) that owns its
  * workspace, so repeated products allocate nothing.  plan_execute has the
- * semantics of bbfmm_matvec but is asynchronous: it enqueues the product on
- * `stream` and returns.  With the overlapped schedule (option `overlap`)
- * the near field runs on a stream the plan owns, forked from and joined
- * back into `stream` with events, so all of the product's work is still
- * ordered after earlier work on `stream` and before later work on it.  One
- * plan's workspace serves one product at a time: products of one plan on
- * different streams must be ordered by the caller.  The tree and operators
- * must outlive the plan.
+ * semantics of bbfmm_matvec: it enqueues the product on `stream` and
+ * returns.  With the overlapped schedule (option `overlap`) the near field
+ * runs on a side stream the plan holds, forked from and joined back into
+ * `stream` with events, so all of the product's work is still ordered after
+ * earlier work on `stream` and before later work on it.  One plan's
+ * workspace serves one product at a time: a product waits for the plan's
+ * previous product (an event) when it is enqueued on another stream.  When
+ * `stream` is being captured into a caller's graph the plan does not order
+ * or track that launch; the caller keeps the plan alive while the graph
+ * can run.  plan_free waits for the last product.  The tree and operators
+ * must outlive the plan.  bbfmm_plan_create sets up on the null stream with
+ * the operators' allocator.
  */
 bbfmm_status bbfmm_plan_create(const bbfmm_tree *tree, const bbfmm_ops *ops,
                                int64_t r, bbfmm_plan **out);
@@ -249,11 +295,15 @@ typedef struct {
                             /* 0 = 1                                             */
 } bbfmm_plan_options;
 
-/* plan_create with explicit launch shapes (NULL options = defaults).  The
- * results do not depend on the options beyond floating-point summation
- * order.  Errors: INVALID_ARG for out-of-range options. */
+/* plan_create with explicit launch shapes (NULL options = defaults), a
+ * device-memory hook (NULL = the operators') and the stream its set-up
+ * (launch-list uploads, tile masks) is enqueued on; products are ordered
+ * after the set-up.  The results do not depend on the options beyond
+ * floating-point summation order.  Errors: INVALID_ARG for out-of-range
+ * options, OUT_OF_MEMORY, HIP. */
 bbfmm_status bbfmm_plan_create_ex(const bbfmm_tree *tree, const bbfmm_ops *ops,
                                   int64_t r, const bbfmm_plan_options *options,
+                                  const bbfmm_allocator *allocator, void *stream,
                                   bbfmm_plan **out);
 bbfmm_status bbfmm_plan_execute(bbfmm_plan *plan, const float *sigma,
                                 float *phi, void *stream);
@@ -371,6 +421,20 @@ typedef struct {
     int64_t bytes_peak;         /* largest bytes_in_use so far                    */
 } bbfmm_server_stats;
 bbfmm_status bbfmm_server_get_stats(bbfmm_server *server, bbfmm_server_stats *out);
+
+/*
+ * Live resources of the library in this process (all out, host): device
+ * buffers and bytes it holds (from hooks or hipMalloc), plans, the streams
+ * and events it created and has not destroyed (side streams are kept for
+ * reuse until the process ends), and how many plans were freed while their
+ * last product was still running (plan_free then waited for it).  For
+ * checking that handles release what they hold.
+ */
+typedef struct {
+    int64_t device_buffers, device_bytes, plans, streams, events;
+    int64_t plans_freed_in_flight;
+} bbfmm_runtime_counters;
+bbfmm_status bbfmm_get_runtime_counters(bbfmm_runtime_counters *out);
 
 void bbfmm_tree_free(bbfmm_tree *tree);
 void bbfmm_ops_free(bbfmm_ops *ops);

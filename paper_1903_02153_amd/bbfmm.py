@@ -72,22 +72,92 @@ class PlanOptions(ctypes.Structure):
                 ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32)]
 
 
+class RuntimeCounters(ctypes.Structure):
+    _fields_ = [("device_buffers", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("plans", ctypes.c_int64), ("streams", ctypes.c_int64),
+                ("events", ctypes.c_int64), ("plans_freed_in_flight", ctypes.c_int64)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class AllocatorHook(ctypes.Structure):
+    """bbfmm_allocator: alloc(bytes, stream, ctx), free(ptr, stream, ctx), ctx."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """The library's device memory from torch's caching allocator, so torch
+    owns every byte.  Counts its calls; ``fail_after`` makes the allocation
+    after that many successful ones return NULL (for testing the library's
+    out-of-memory path).  Must outlive the handles built with it (they keep
+    a reference)."""
+
+    def __init__(self, fail_after: Optional[int] = None):
+        self.fail_after = fail_after
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+
+        def _alloc(nbytes, stream, _ctx):
+            try:
+                import torch
+                if self.fail_after is not None and self.allocs >= self.fail_after:
+                    return None
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+                self.allocs += 1
+                self.live[int(ptr)] = int(nbytes)
+                return ptr
+            except Exception:
+                return None
+
+        def _free(ptr, _stream, _ctx):
+            try:
+                import torch
+                torch.cuda.caching_allocator_delete(int(ptr))
+                self.frees += 1
+                self.live.pop(int(ptr), None)
+            except Exception:
+                pass
+
+        self._alloc_cb = _ALLOC_FN(_alloc)
+        self._free_cb = _FREE_FN(_free)
+        self.hook = AllocatorHook(self._alloc_cb, self._free_cb, None)
+
+
+_default_torch_alloc = None
+
+
+def torch_allocator() -> TorchAllocator:
+    """The process-wide TorchAllocator used by default."""
+    global _default_torch_alloc
+    if _default_torch_alloc is None:
+        _default_torch_alloc = TorchAllocator()
+    return _default_torch_alloc
+
+
+def _hook_arg(allocator):
+    return None if allocator is None else ctypes.byref(allocator.hook)
+
+
 _lib_handle = None
 
 # name -> (restype, argtypes); every symbol of include/bbfmm.h
 _VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _PVP = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
-    "bbfmm_build_tree": (_I32, [_VP, _I64, ctypes.POINTER(TreeParams), _VP, _PVP]),
+    "bbfmm_build_tree": (_I32, [_VP, _I64, ctypes.POINTER(TreeParams), _VP, _VP, _PVP]),
     "bbfmm_tree_info_get": (_I32, [_VP, ctypes.POINTER(TreeInfo)]),
     "bbfmm_tree_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
-    "bbfmm_precompute_operators": (_I32, [_VP, _D, _I32, _VP, _PVP]),
+    "bbfmm_precompute_operators": (_I32, [_VP, _D, _I32, _VP, _VP, _PVP]),
     "bbfmm_ops_rank": (_I32, [_VP, _I32, ctypes.POINTER(_I32)]),
     "bbfmm_ops_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
     "bbfmm_ops_import": (_I32, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _PVP]),
     "bbfmm_matvec": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "bbfmm_plan_create": (_I32, [_VP, _VP, _I64, _PVP]),
-    "bbfmm_plan_create_ex": (_I32, [_VP, _VP, _I64, _VP, _PVP]),
+    "bbfmm_plan_create_ex": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _PVP]),
+    "bbfmm_get_runtime_counters": (_I32, [ctypes.POINTER(RuntimeCounters)]),
     "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
     "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
@@ -147,10 +217,18 @@ def _device_f32(t, name: str, shape: Optional[Sequence[int]] = None):
     return t
 
 
+def runtime_counters() -> dict:
+    """Live buffers, bytes, plans, streams and events of the library."""
+    out = RuntimeCounters()
+    _check(lib().bbfmm_get_runtime_counters(ctypes.byref(out)))
+    return {name: getattr(out, name) for name, _ in RuntimeCounters._fields_}
+
+
 class Tree:
-    def __init__(self, handle: int, params: TreeParams):
+    def __init__(self, handle: int, params: TreeParams, allocator=None):
         self._h = handle
         self.params = params
+        self.allocator = allocator      # kept alive while the tree is
 
     @property
     def handle(self):
@@ -184,9 +262,10 @@ class Tree:
 
 
 class Ops:
-    def __init__(self, handle: int, tree: Tree):
+    def __init__(self, handle: int, tree: Tree, allocator=None):
         self._h = handle
         self.tree = tree
+        self.allocator = allocator
 
     @property
     def handle(self):
@@ -220,15 +299,18 @@ class Ops:
 class Plan:
     """Reusable matvec for a fixed (tree, ops, r); owns its workspace."""
 
-    def __init__(self, tree: Tree, ops: Ops, r: int, **options):
+    def __init__(self, tree: Tree, ops: Ops, r: int, allocator=None, stream=None, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
-        m2l_occupancy, m2l_layout (0 = heuristic)."""
+        m2l_occupancy, m2l_layout (0 = heuristic).  allocator: a TorchAllocator
+        (None = the operators'); stream: where the set-up is enqueued."""
         h = _VP()
         opt = PlanOptions()
         for k, v in options.items():
             setattr(opt, k, int(v))
         _check(lib().bbfmm_plan_create_ex(tree.handle, ops.handle, int(r), ctypes.byref(opt),
+                                          _hook_arg(allocator), _stream_handle(stream),
                                           ctypes.byref(h)))
+        self.allocator = allocator
         self.options = dict(options)
         self._h = h.value
         self.tree, self.ops, self.r = tree, ops, int(r)
@@ -293,24 +375,30 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
                cheb_order: int = 4, leaf_size: int = 64, max_depth: int = 22,
-               fixed_depth: int = 0, stream=None) -> Tree:
-    """Octree over the bounding cube of ``points`` ((N,3) float32 on the GPU)."""
+               fixed_depth: int = 0, stream=None, allocator="torch") -> Tree:
+    """Octree over the bounding cube of ``points`` ((N,3) float32 on the GPU).
+    allocator: "torch" (torch's caching allocator owns the library's device
+    memory; the default), a TorchAllocator, or None (hipMalloc)."""
     if points.dim() != 2 or points.shape[1] != 3:
         raise ValueError("points must have shape (N, 3)")
     _device_f32(points, "points")
+    if allocator == "torch":
+        allocator = torch_allocator()
     p = TreeParams(kernel_id, kernel_param, cheb_order, leaf_size, max_depth, fixed_depth)
     h = _VP()
     _check(lib().bbfmm_build_tree(points.data_ptr(), points.shape[0], ctypes.byref(p),
-                                  _stream_handle(stream), ctypes.byref(h)))
-    return Tree(h.value, p)
+                                  _hook_arg(allocator), _stream_handle(stream), ctypes.byref(h)))
+    return Tree(h.value, p, allocator)
 
 
 def precompute_operators(tree: Tree, svd_eps: float = 1e-5, precision: int = M2L_FP32,
-                         stream=None) -> Ops:
+                         stream=None, allocator=None) -> Ops:
+    """allocator: None = the tree's."""
     h = _VP()
     _check(lib().bbfmm_precompute_operators(tree.handle, float(svd_eps), int(precision),
-                                            _stream_handle(stream), ctypes.byref(h)))
-    return Ops(h.value, tree)
+                                            _hook_arg(allocator), _stream_handle(stream),
+                                            ctypes.byref(h)))
+    return Ops(h.value, tree, allocator)
 
 
 def ops_import(tree: Tree, ranks: Sequence[int], U: Sequence[np.ndarray],

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <vector>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -43,6 +44,94 @@ bbfmm_status guarded(F &&f) {
 
 const char *last_error() { return g_err; }
 
+// ------------------------------------------------------ device memory ----
+namespace {
+thread_local MemSource g_mem;
+Counters g_counters;
+std::mutex g_pool_mu;
+std::vector<std::pair<int, hipStream_t>> g_side_pool;   // (device, idle stream)
+}  // namespace
+
+MemSource &current_mem() { return g_mem; }
+
+MemScope::MemScope(const bbfmm_allocator *hook, hipStream_t stream) : saved(g_mem) {
+    g_mem.hook = hook ? *hook : bbfmm_allocator{};
+    g_mem.stream = stream;
+}
+MemScope::~MemScope() { g_mem = saved; }
+
+void *device_alloc(size_t bytes, const MemSource &src) {
+    void *p = nullptr;
+    if (src.hook.alloc) {
+        p = src.hook.alloc(bytes, src.stream, src.hook.ctx);
+        if (p == nullptr)
+            fail(BBFMM_ERR_OUT_OF_MEMORY, "the allocator hook returned NULL for %zu bytes", bytes);
+    } else {
+        BB_HIP(hipMalloc(&p, bytes));
+    }
+    ++g_counters.buffers;
+    g_counters.bytes += int64_t(bytes);
+    return p;
+}
+
+void device_free(void *p, size_t bytes, const MemSource &src) {
+    if (src.hook.alloc) {
+        if (src.hook.free) src.hook.free(p, src.stream, src.hook.ctx);
+    } else {
+        (void)hipFree(p);
+    }
+    --g_counters.buffers;
+    g_counters.bytes -= int64_t(bytes);
+}
+
+Counters &counters() { return g_counters; }
+
+hipEvent_t make_event(unsigned flags) {
+    hipEvent_t e = nullptr;
+    BB_HIP(hipEventCreateWithFlags(&e, flags));
+    ++g_counters.events;
+    return e;
+}
+void destroy_event(hipEvent_t e) {
+    if (!e) return;
+    (void)hipEventDestroy(e);
+    --g_counters.events;
+}
+hipStream_t make_stream() {
+    hipStream_t s = nullptr;
+    BB_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ++g_counters.streams;
+    return s;
+}
+void destroy_stream(hipStream_t s) {
+    if (!s) return;
+    (void)hipStreamDestroy(s);
+    --g_counters.streams;
+}
+
+hipStream_t acquire_side_stream() {
+    int dev = 0;
+    BB_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (size_t i = 0; i < g_side_pool.size(); ++i)
+            if (g_side_pool[i].first == dev) {
+                hipStream_t s = g_side_pool[i].second;
+                g_side_pool.erase(g_side_pool.begin() + long(i));
+                return s;
+            }
+    }
+    return make_stream();
+}
+
+void release_side_stream(hipStream_t s) {
+    if (!s) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_side_pool.emplace_back(dev, s);
+}
+
 template <class T>
 void copy_out(const T *dev, int64_t count, void *dst, int64_t capacity, int64_t *size) {
     const int64_t bytes = count * int64_t(sizeof(T));
@@ -67,11 +156,16 @@ extern "C" {
 const char *bbfmm_last_error(void) { return last_error(); }
 
 bbfmm_status bbfmm_build_tree(const float *points, int64_t n, const bbfmm_tree_params *params,
-                              void *stream, bbfmm_tree **out) {
+                              const bbfmm_allocator *allocator, void *stream, bbfmm_tree **out) {
     return guarded([&] {
         BB_REQUIRE(params != nullptr && out != nullptr, "params / out is NULL");
         *out = nullptr;
-        *out = build_tree_impl(points, n, *params, static_cast<hipStream_t>(stream));
+        BB_REQUIRE(allocator == nullptr || (allocator->alloc && allocator->free),
+                   "allocator needs both alloc and free");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        MemScope scope(allocator, s);
+        *out = build_tree_impl(points, n, *params, s);
+        if (allocator) (*out)->hook = *allocator;
     });
 }
 
@@ -128,11 +222,18 @@ bbfmm_status bbfmm_tree_export(const bbfmm_tree *t, int32_t what, int32_t level,
 }
 
 bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *t, double svd_eps, int32_t precision,
-                                        void *stream, bbfmm_ops **out) {
+                                        const bbfmm_allocator *allocator, void *stream,
+                                        bbfmm_ops **out) {
     return guarded([&] {
-        BB_REQUIRE(out != nullptr, "out is NULL");
+        BB_REQUIRE(out != nullptr && t != nullptr, "tree / out is NULL");
         *out = nullptr;
-        *out = precompute_impl(t, svd_eps, precision, static_cast<hipStream_t>(stream));
+        BB_REQUIRE(allocator == nullptr || (allocator->alloc && allocator->free),
+                   "allocator needs both alloc and free");
+        const bbfmm_allocator hook = allocator ? *allocator : t->hook;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        MemScope scope(&hook, s);
+        *out = precompute_impl(t, svd_eps, precision, s);
+        (*out)->hook = hook;
     });
 }
 
@@ -187,8 +288,10 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
                        precision == BBFMM_M2L_FP16_SCALED,
                    "unsupported M2L precision %d", precision);
         hipStream_t s = static_cast<hipStream_t>(stream);
+        MemScope scope(&t->hook, s);
         std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
         ops->tree = t;
+        ops->hook = t->hook;
         ops->n = t->params.cheb_order;
         ops->m = ops->n * ops->n * ops->n;
         ops->mp = int(ceil_div(ops->m, 16) * 16);
@@ -222,19 +325,25 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *t, int32_t precision, const int3
 }
 
 bbfmm_status bbfmm_plan_create_ex(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
-                                  const bbfmm_plan_options *opt, bbfmm_plan **out) {
+                                  const bbfmm_plan_options *opt, const bbfmm_allocator *allocator,
+                                  void *stream, bbfmm_plan **out) {
     return guarded([&] {
         BB_REQUIRE(out != nullptr, "out is NULL");
         *out = nullptr;
+        BB_REQUIRE(allocator == nullptr || (allocator->alloc && allocator->free),
+                   "allocator needs both alloc and free");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // (options, tree and operators are validated by plan_create_impl first)
+        MemScope scope(allocator ? allocator : (o ? &o->hook : nullptr), s);
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-        p->impl = plan_create_impl(t, o, r, opt);
+        p->impl = plan_create_impl(t, o, r, opt, s);
         *out = p.release();
     });
 }
 
 bbfmm_status bbfmm_plan_create(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                                bbfmm_plan **out) {
-    return bbfmm_plan_create_ex(t, o, r, nullptr, out);
+    return bbfmm_plan_create_ex(t, o, r, nullptr, nullptr, nullptr, out);
 }
 
 bbfmm_status bbfmm_plan_execute(bbfmm_plan *p, const float *sigma, float *phi, void *stream) {
@@ -284,18 +393,19 @@ bool is_device_ptr(const void *ptr) {
 // median milliseconds of `reps` products with these options (after one untimed)
 double time_options(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r, const bbfmm_plan_options &op,
                     const float *sigma, float *phi, hipStream_t s, int reps) {
+    MemScope scope(&o->hook, s);
     std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-    p->impl = plan_create_impl(t, o, r, &op);
+    p->impl = plan_create_impl(t, o, r, &op, s);
     plan_execute_impl(p->impl, sigma, phi, s);
     std::vector<hipEvent_t> ev(size_t(2 * reps), nullptr);
     struct Events {
         std::vector<hipEvent_t> &e;
         ~Events() {
             for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
+                destroy_event(x);
         }
     } guard{ev};
-    for (hipEvent_t &e : ev) BB_HIP(hipEventCreate(&e));
+    for (hipEvent_t &e : ev) e = make_event(hipEventDefault);
     for (int i = 0; i < reps; ++i) {
         BB_HIP(hipEventRecord(ev[2 * i], s));
         plan_execute_impl(p->impl, sigma, phi, s);
@@ -371,8 +481,9 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 consider(c);
             }
         // make every choice explicit: what the heuristic picked for the zeros
+        MemScope scope(&o->hook, s);
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-        p->impl = plan_create_impl(t, o, r, &cur);
+        p->impl = plan_create_impl(t, o, r, &cur, s);
         plan_resolved_options(p->impl, &cur);
         *best = cur;
         if (best_ms) *best_ms = cur_ms;
@@ -382,12 +493,24 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
 bbfmm_status bbfmm_matvec(const bbfmm_tree *t, const bbfmm_ops *o, const float *sigma, int64_t r,
                           float *phi, void *stream) {
     return guarded([&] {
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
-        p->impl = plan_create_impl(t, o, r, nullptr);
-        plan_execute_impl(p->impl, sigma, phi, s);
-        // the workspace is released only after the stream has consumed it
-        BB_HIP(hipStreamSynchronize(s));
+        BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
+        BB_REQUIRE(o->tree == t, "operators were built for another tree");
+        BB_REQUIRE(sigma != nullptr && phi != nullptr, "sigma / phi is NULL");
+        BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
+        matvec_cached(const_cast<bbfmm_ops *>(o), sigma, r, phi, static_cast<hipStream_t>(stream));
+    });
+}
+
+bbfmm_status bbfmm_get_runtime_counters(bbfmm_runtime_counters *out) {
+    return guarded([&] {
+        BB_REQUIRE(out != nullptr, "out is NULL");
+        const Counters &c = counters();
+        out->device_buffers = c.buffers.load();
+        out->device_bytes = c.bytes.load();
+        out->plans = c.plans.load();
+        out->streams = c.streams.load();
+        out->events = c.events.load();
+        out->plans_freed_in_flight = c.plans_freed_in_flight.load();
     });
 }
 

@@ -6,11 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,29 +55,67 @@ void clear_error();
         if (!(cond)) ::bbfmm::fail(BBFMM_ERR_INTERNAL, __VA_ARGS__);            \
     } while (0)
 
-// Owning device buffer (hipMalloc / hipFree).
+// ------------------------------------------------------ device memory ----
+// Where device memory comes from: the caller's allocator hook
+// (bbfmm_allocator, e.g. a framework's caching allocator) or hipMalloc /
+// hipFree.  A constructing call sets the source for its thread with a
+// MemScope; every DBuf allocated meanwhile remembers the hook and stream it
+// came from and returns its memory through the same hook.
+struct MemSource {
+    bbfmm_allocator hook{};          // hook.alloc == nullptr: hipMalloc / hipFree
+    hipStream_t stream = nullptr;
+};
+MemSource &current_mem();            // this thread's source
+struct MemScope {
+    MemSource saved;
+    MemScope(const bbfmm_allocator *hook, hipStream_t stream);
+    ~MemScope();
+    MemScope(const MemScope &) = delete;
+    MemScope &operator=(const MemScope &) = delete;
+};
+void *device_alloc(size_t bytes, const MemSource &src);
+void device_free(void *p, size_t bytes, const MemSource &src);
+
+// Live-resource counters of the library (bbfmm_get_runtime_counters).
+struct Counters {
+    std::atomic<int64_t> buffers{0}, bytes{0}, plans{0}, streams{0}, events{0};
+    std::atomic<int64_t> plans_freed_in_flight{0};
+};
+Counters &counters();
+hipEvent_t make_event(unsigned flags);   // counted hipEventCreateWithFlags
+void destroy_event(hipEvent_t e);        // NULL-safe
+hipStream_t make_stream();               // counted non-blocking stream
+void destroy_stream(hipStream_t s);      // NULL-safe
+// Non-blocking streams reused across plans (one plan holds one at a time);
+// streams are created on demand and kept until the process ends.
+hipStream_t acquire_side_stream();
+void release_side_stream(hipStream_t s);
+
+// Owning device buffer.
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    MemSource src;
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), src(o.src) { o.p = nullptr; o.n = 0; }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; src = o.src; o.p = nullptr; o.n = 0; }
         return *this;
     }
     ~DBuf() { release(); }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        BB_HIP(hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)));
+        src = current_mem();
+        p = static_cast<T *>(device_alloc(count * sizeof(T), src));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) device_free(p, n * sizeof(T), src);
         p = nullptr;
         n = 0;
     }
@@ -123,6 +163,8 @@ struct bbfmm_tree {
     bbfmm::DBuf<int32_t> nbr_off, nbr_idx;
     int64_t nbr_nnz = 0;
     bbfmm::DBuf<int32_t> tables;    // tvec[316][3], slot_t[8][189], t_slot[8][316]
+    std::vector<int32_t> leaf_pb_h, leaf_pe_h;   // host copies of the leaf point ranges
+    bbfmm_allocator hook{};         // allocator of the tree, inherited by its operators and plans
     int leaf_level() const { return depth - 1; }
     double half_width(int level) const { return double(side) / double(1ull << (level + 1)); }
 };
@@ -150,6 +192,9 @@ struct OpSet {
     DBuf<float> Cinv;                // 316: 2^-e_t
 };
 
+struct PlanCache;
+void plan_cache_destroy(PlanCache *c);
+
 struct OpsLevel {
     OpSet *set = nullptr;
     double scale = 1.0;              // factor applied after M2L (h^m for homogeneous kernels)
@@ -165,6 +210,11 @@ struct bbfmm_ops {
     bbfmm::ChebConst cheb{};
     std::vector<std::unique_ptr<bbfmm::OpSet>> sets;
     bbfmm::OpsLevel lv[bbfmm::kMaxLevels];
+    bbfmm_allocator hook{};          // allocator of the operators and of their plans
+    // workspaces of bbfmm_matvec, kept per (r, stream) (see matvec.hip)
+    std::mutex cache_mu;
+    bbfmm::PlanCache *cache = nullptr;
+    ~bbfmm_ops();
 };
 
 namespace bbfmm {
@@ -177,8 +227,12 @@ void cheb_setup(bbfmm_ops *ops, hipStream_t s);
 void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s);
 
 struct Plan;
+// A plan's device memory comes from the thread's MemScope; its set-up work
+// (launch lists, tile masks) is enqueued on `setup` and every product of
+// the plan is ordered after it.  transient: no events and no side stream
+// (for a plan that lives for one synchronous product).
 Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
-                       const bbfmm_plan_options *opt);
+                       const bbfmm_plan_options *opt, hipStream_t setup, bool transient = false);
 void plan_execute_impl(Plan *p, const float *sigma, float *phi, hipStream_t s);
 int64_t plan_workspace_bytes(const Plan *p);
 void plan_resolved_options(const Plan *p, bbfmm_plan_options *out);   // the choices in effect
@@ -186,6 +240,8 @@ void plan_destroy(Plan *p);
 void plan_set_timing(Plan *p, bool on);
 void plan_set_graph(Plan *p, bool on);
 void plan_stage_times(Plan *p, double *ms, int64_t *execs, bool reset);
+// bbfmm_matvec: a cached plan per (r, stream) of the operator set
+void matvec_cached(bbfmm_ops *o, const float *sigma, int64_t r, float *phi, hipStream_t s);
 
 // --------------------------------------------------------- primitives ----
 // exclusive prefix sum of n int32 values (in may equal out); returns total

@@ -1689,19 +1689,37 @@ struct Plan {
     hipGraphExec_t gexec = nullptr;
     const float *g_sigma = nullptr;
     float *g_phi = nullptr;
+    // ordering of the plan's products: `done` is recorded after the set-up
+    // and after every product on the stream it ran on (`last`); a product on
+    // another stream first waits for it, and the destructor waits for it
+    bool transient = false;             // one synchronous product: no events, no side stream
+    hipEvent_t done = nullptr;
+    bool issued = false;
+    hipStream_t last = nullptr;
+    std::vector<int32_t> h_tiles, h_work;   // host sources of the set-up uploads
+    hipStream_t setup = nullptr;        // where the set-up work was enqueued
+    Plan() { ++counters().plans; }
     ~Plan() {
-        if (side) (void)hipStreamSynchronize(side);
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        if (side) (void)hipStreamDestroy(side);
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        // a plan whose set-up failed (or a transient one) may still have
+        // uploads from h_tiles / h_work and mask kernels in flight
+        if (!issued) (void)hipStreamSynchronize(setup);
+        if (issued) {
+            if (hipEventQuery(done) == hipErrorNotReady) ++counters().plans_freed_in_flight;
+            (void)hipEventSynchronize(done);
+        }
+        destroy_event(fork);
+        destroy_event(join);
+        release_side_stream(side);
+        for (hipEvent_t e : events) destroy_event(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        destroy_stream(cap_stream);
+        destroy_event(done);
+        --counters().plans;
     }
 };
 
 Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
-                       const bbfmm_plan_options *opt) {
+                       const bbfmm_plan_options *opt, hipStream_t setup, bool transient) {
     bbfmm_plan_options op{};
     if (opt) op = *opt;
     BB_REQUIRE(op.m2l_split >= 0 && op.m2l_split <= 8, "m2l_split must be in [0, 8]");
@@ -1721,6 +1739,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     p->tree = t;
     p->ops = o;
     p->r = r;
+    p->transient = transient;
+    p->setup = setup;
     const int L = t->leaf_level();
     const int mp = o->mp;
     p->rc_m2l = int(std::min<int64_t>(r, kM2LCols));
@@ -1788,26 +1808,26 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         ws += p->Fh[lvl].bytes();
     }
     if (p->ntiles) {
-        p->tiles.alloc(tl.size());
-        BB_HIP(hipMemcpy(p->tiles.p, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        p->h_tiles = std::move(tl);
+        p->tiles.alloc(p->h_tiles.size());
+        BB_HIP(hipMemcpyAsync(p->tiles.p, p->h_tiles.data(), p->h_tiles.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, setup));
         p->masks.alloc(int64_t(p->ntiles) * kMaskWords);
         MaskArgs ma{};
         for (int lvl = 2; lvl <= L; ++lvl) {
             ma.itab[lvl] = t->lv[lvl].itab.p;
             ma.oct_cells[lvl] = t->lv[lvl].oct_cells.p;
         }
-        k_tile_masks<<<p->ntiles, kThreads, 0, nullptr>>>(p->tiles.p, ma, p->masks.p);
+        k_tile_masks<<<p->ntiles, kThreads, 0, setup>>>(p->tiles.p, ma, p->masks.p);
         BB_LAUNCH_CHECK();
-        BB_HIP(hipStreamSynchronize(nullptr));
         ws += p->tiles.bytes() + p->masks.bytes();
     }
     if (p->p2p_mfma) {
         // MFMA near field: one wave per (leaf, up to 64 consecutive
         // targets), grouped by the number of 16-row blocks they need
         const LevelData &leaf = t->lv[L];
-        std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
-        BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
-        BB_HIP(hipMemcpy(he.data(), leaf.pe.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_pe_h;
+        std::vector<int32_t> &w = p->h_work;
         for (int nrb = 1; nrb <= 4; ++nrb) {
             p->mfma_off[nrb - 1] = int(w.size() / 2);
             for (int a = 0; a < leaf.C; ++a)
@@ -1820,15 +1840,15 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->mfma_off[4] = int(w.size() / 2);
         p->nwork = int(w.size() / 2);
         p->work.alloc(w.size());
-        BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              setup));
     } else {
         // per-lane P2P work items (leaf, first target, log2 S): leaves of at
         // most 64 points take one wave with 64 / next_pow2(count) sub-lanes
         // per target
         const LevelData &leaf = t->lv[L];
-        std::vector<int32_t> hb(leaf.C), he(leaf.C), w;
-        BB_HIP(hipMemcpy(hb.data(), leaf.pb.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
-        BB_HIP(hipMemcpy(he.data(), leaf.pe.p, leaf.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_pe_h;
+        std::vector<int32_t> &w = p->h_work;
         for (int a = 0; a < leaf.C; ++a) {
             const int cnt = he[a] - hb[a];
             int lgT = 0;
@@ -1843,11 +1863,12 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         }
         p->nwork = int(w.size() / 3);
         p->work.alloc(w.size());
-        BB_HIP(hipMemcpy(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              setup));
     }
     // overlapped near field: by default with the per-lane near field (whose
     // VALU work complements the MFMA-bound far field); needs a far field
-    p->overlap = L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
+    p->overlap = !transient && L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
     p->p2p_waves = op.p2p_waves;
     p->m2l_occupancy = op.m2l_occupancy;
     p->m2l_layout = op.m2l_layout == 2 ? 2 : 1;
@@ -1869,14 +1890,19 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         const LevelData &leaf = t->lv[L];
         p->pleaf.alloc(t->n);
         ws += p->pleaf.bytes();
-        k_point_leaf<<<grid(leaf.C), kThreads, 0, nullptr>>>(leaf.pb.p, leaf.pe.p, leaf.C, p->pleaf.p);
+        k_point_leaf<<<grid(leaf.C), kThreads, 0, setup>>>(leaf.pb.p, leaf.pe.p, leaf.C, p->pleaf.p);
         BB_LAUNCH_CHECK();
-        BB_HIP(hipStreamSynchronize(nullptr));
-        BB_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-        BB_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
-        BB_HIP(hipEventCreateWithFlags(&p->join, hipEventDisableTiming));
+        p->side = acquire_side_stream();
+        p->fork = make_event(hipEventDisableTiming);
+        p->join = make_event(hipEventDisableTiming);
     }
     p->ws_bytes = ws;
+    if (!transient) {
+        p->done = make_event(hipEventDisableTiming);
+        BB_HIP(hipEventRecord(p->done, setup));
+        p->issued = true;
+        p->last = setup;
+    }
     return p.release();
 }
 
@@ -1981,8 +2007,8 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
 void plan_set_timing(Plan *p, bool on) {
     BB_REQUIRE(p != nullptr, "plan is NULL");
     if (on && p->events.empty()) {
-        p->events.resize(size_t(kTimingRing) * kEv);
-        for (hipEvent_t &e : p->events) BB_HIP(hipEventCreate(&e));
+        p->events.reserve(size_t(kTimingRing) * kEv);
+        for (int i = 0; i < kTimingRing * kEv; ++i) p->events.push_back(make_event(hipEventDefault));
     }
     if (!on)
         while (p->ring_pending > 0) harvest_one(*p);
@@ -2007,8 +2033,8 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
 
 void plan_set_graph(Plan *p, bool on) {
     BB_REQUIRE(p != nullptr, "plan is NULL");
-    if (on && p->cap_stream == nullptr)
-        BB_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    BB_REQUIRE(!(on && p->transient), "a transient plan has no graph");
+    if (on && p->cap_stream == nullptr) p->cap_stream = make_stream();
     if (!on && p->gexec) {
         BB_HIP(hipGraphExecDestroy(p->gexec));
         p->gexec = nullptr;
@@ -2020,32 +2046,89 @@ void plan_execute_impl(Plan *pp, const float *sigma, float *phi, hipStream_t s) 
     BB_REQUIRE(pp != nullptr, "plan is NULL");
     BB_REQUIRE(sigma != nullptr && phi != nullptr, "sigma / phi is NULL");
     Plan &p = *pp;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    BB_HIP(hipStreamIsCapturing(s, &cap));
+    const bool track = !p.transient && cap == hipStreamCaptureStatusNone;
+    // the workspace serves one product at a time: wait for the previous one
+    // when it ran on another stream
+    if (track && p.issued && p.last != s) BB_HIP(hipStreamWaitEvent(s, p.done, 0));
     if (!p.graph_on) {
         enqueue_matvec(p, sigma, phi, s, p.timing);
-        return;
-    }
-    if (p.gexec == nullptr || sigma != p.g_sigma || phi != p.g_phi) {
-        if (p.gexec) {
-            BB_HIP(hipGraphExecDestroy(p.gexec));
-            p.gexec = nullptr;
+    } else {
+        if (p.gexec == nullptr || sigma != p.g_sigma || phi != p.g_phi) {
+            if (p.gexec) {
+                BB_HIP(hipGraphExecDestroy(p.gexec));
+                p.gexec = nullptr;
+            }
+            BB_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+            hipGraph_t graph = nullptr;
+            try {
+                enqueue_matvec(p, sigma, phi, p.cap_stream, false);
+            } catch (...) {
+                (void)hipStreamEndCapture(p.cap_stream, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            BB_HIP(hipStreamEndCapture(p.cap_stream, &graph));
+            const hipError_t e = hipGraphInstantiate(&p.gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            BB_HIP(e);
+            p.g_sigma = sigma;
+            p.g_phi = phi;
         }
-        BB_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
-        hipGraph_t graph = nullptr;
-        try {
-            enqueue_matvec(p, sigma, phi, p.cap_stream, false);
-        } catch (...) {
-            (void)hipStreamEndCapture(p.cap_stream, &graph);
-            if (graph) (void)hipGraphDestroy(graph);
-            throw;
-        }
-        BB_HIP(hipStreamEndCapture(p.cap_stream, &graph));
-        const hipError_t e = hipGraphInstantiate(&p.gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        BB_HIP(e);
-        p.g_sigma = sigma;
-        p.g_phi = phi;
+        BB_HIP(hipGraphLaunch(p.gexec, s));
     }
-    BB_HIP(hipGraphLaunch(p.gexec, s));
+    if (track) {
+        BB_HIP(hipEventRecord(p.done, s));
+        p.issued = true;
+        p.last = s;
+    }
+}
+
+// ------------------------------------------------ bbfmm_matvec cache ----
+constexpr size_t kCachedPlans = 4;
+
+struct PlanCache {
+    struct Item {
+        int64_t r;
+        hipStream_t s;
+        Plan *plan;
+        uint64_t use;
+    };
+    std::vector<Item> items;
+    uint64_t tick = 0;
+};
+
+void plan_cache_destroy(PlanCache *c) {
+    if (!c) return;
+    for (PlanCache::Item &it : c->items) delete it.plan;   // waits for its last product
+    delete c;
+}
+
+void matvec_cached(bbfmm_ops *o, const float *sigma, int64_t r, float *phi, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(o->cache_mu);
+    if (o->cache == nullptr) o->cache = new PlanCache();
+    PlanCache &c = *o->cache;
+    Plan *plan = nullptr;
+    for (PlanCache::Item &it : c.items)
+        if (it.r == r && it.s == s) {
+            it.use = ++c.tick;
+            plan = it.plan;
+        }
+    if (plan == nullptr) {
+        MemScope scope(&o->hook, s);
+        std::unique_ptr<Plan> fresh(plan_create_impl(o->tree, o, r, nullptr, s));
+        if (c.items.size() >= kCachedPlans) {
+            size_t victim = 0;
+            for (size_t i = 1; i < c.items.size(); ++i)
+                if (c.items[i].use < c.items[victim].use) victim = i;
+            delete c.items[victim].plan;
+            c.items.erase(c.items.begin() + long(victim));
+        }
+        c.items.push_back(PlanCache::Item{r, s, fresh.get(), ++c.tick});
+        plan = fresh.release();
+    }
+    plan_execute_impl(plan, sigma, phi, s);
 }
 
 namespace {
@@ -2243,3 +2326,5 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
 }  // namespace
 
 }  // namespace bbfmm
+
+bbfmm_ops::~bbfmm_ops() { bbfmm::plan_cache_destroy(cache); }

@@ -180,7 +180,7 @@ struct Server {
     // An idle cached entry for (model, R), or a new one if the budget allows
     // after evicting idle entries (least recently used first).  Returns
     // nullptr when the batch must wait; sets *reject when it can never fit.
-    Entry *acquire(int mdl, int R, bool *reject) {
+    Entry *acquire(int mdl, int R, hipStream_t stream, bool *reject) {
         *reject = false;
         for (auto &e : cache)
             if (!e->busy && e->model == mdl && e->R == R) return e.get();
@@ -203,7 +203,8 @@ struct Server {
         struct PlanDel {
             void operator()(Plan *q) const { plan_destroy(q); }
         };
-        std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, &opt));
+        MemScope scope(&m.ops->hook, stream);
+        std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, &opt, stream));
         const int64_t bytes = plan_workspace_bytes(plan.get()) + 2 * m.tree->n * R * int64_t(sizeof(float));
         need[key] = bytes;
         if (bytes > budget) {
@@ -241,7 +242,7 @@ struct Server {
         Slot &s = slots[k];
         const int mdl = batch.front()->model;
         bool reject = false;
-        Entry *e = acquire(mdl, R, &reject);
+        Entry *e = acquire(mdl, R, s.stream, &reject);
         if (reject) {
             for (Request *rq : batch) {
                 rq->status = BBFMM_ERR_BUDGET;

@@ -536,6 +536,14 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
             BB_HIP(hipStreamSynchronize(s));
         }
     }
+    // host copies of the leaf point ranges, from which plans make their
+    // near-field launch lists without reading the device
+    t.leaf_pb_h.resize(size_t(leaf.C));
+    t.leaf_pe_h.resize(size_t(leaf.C));
+    BB_HIP(hipMemcpyAsync(t.leaf_pb_h.data(), leaf.pb.p, leaf.C * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    BB_HIP(hipMemcpyAsync(t.leaf_pe_h.data(), leaf.pe.p, leaf.C * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
     BB_HIP(hipStreamSynchronize(s));
     return tree.release();
 }

@@ -27,6 +27,46 @@ def gpu_matvec(tree, ops, sig):
     return phi.cpu().numpy().astype(np.float64)
 
 
+# Element-wise bar beside the per-column relative L2 bar: every element of a
+# column within ELEM_FACTOR x (the L2 bar) x the column's largest |phi|.
+ELEM_FACTOR = 10.0
+
+
+def assert_parity(got, ref, tol, label=""):
+    """Per-column relative L2 error < tol and, element by element,
+    |got - ref| <= ELEM_FACTOR * tol * max|ref| of the column.  Prints both."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if got.ndim == 1:
+        got, ref = got[:, None], ref[:, None]
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    assert np.all(np.isfinite(got)), f"{label}: non-finite output"
+    l2 = ofmm.rel_l2_cols(got, ref)
+    scale = np.abs(ref).max(axis=0)
+    scale[scale == 0] = 1.0
+    elem = np.abs(got - ref).max(axis=0) / scale
+    print(f"{label}: max column rel L2 {l2.max():.2e}, max element err / column max "
+          f"{elem.max():.2e} ({got.shape[0]} rows x {got.shape[1]} columns)")
+    assert l2.max() < tol, (label, l2)
+    assert elem.max() <= ELEM_FACTOR * tol, (label, elem)
+    return l2, elem
+
+
+def run_plan(tree, ops, sig, **options):
+    """One product with a plan of these options; the plan is held until the
+    device has finished and then freed."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    ts = sig if isinstance(sig, torch.Tensor) else \
+        torch.from_numpy(np.ascontiguousarray(sig, dtype=np.float32)).cuda()
+    phi = torch.empty_like(ts)
+    plan = bbfmm.Plan(tree, ops, ts.shape[1], **options)
+    plan.execute(ts, phi)
+    torch.cuda.synchronize()
+    plan.close()
+    return phi
+
+
 def compare_trees(gt, ot):
     """Bit-exact comparison of every tree array against the oracle."""
     info = gt.info()

@@ -37,21 +37,21 @@ def test_invalid_arguments_rejected_without_gpu():
     lib = bbfmm.lib()
     p = bbfmm.TreeParams(0, 1.0, 4, 64, 22, 0)
     out = ctypes.c_void_p()
-    assert lib.bbfmm_build_tree(None, 10, ctypes.byref(p), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(None, 10, ctypes.byref(p), None, None, ctypes.byref(out)) == 1
     assert b"NULL" in lib.bbfmm_last_error()
     fake = ctypes.c_void_p(0x1000)
-    assert lib.bbfmm_build_tree(fake, 0, ctypes.byref(p), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(fake, 0, ctypes.byref(p), None, None, ctypes.byref(out)) == 1
     bad = bbfmm.TreeParams(0, 1.0, 9, 64, 22, 0)
-    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, None, ctypes.byref(out)) == 1
     assert b"cheb_order" in lib.bbfmm_last_error()
     bad = bbfmm.TreeParams(7, 1.0, 4, 64, 22, 0)
-    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, None, ctypes.byref(out)) == 1
     bad = bbfmm.TreeParams(0, 1.0, 4, 64, 23, 0)
-    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, None, ctypes.byref(out)) == 1
     bad = bbfmm.TreeParams(1, -1.0, 4, 64, 22, 0)
-    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, None, ctypes.byref(out)) == 1
     assert out.value is None
-    assert lib.bbfmm_precompute_operators(None, 1e-5, 0, None, ctypes.byref(out)) == 1
+    assert lib.bbfmm_precompute_operators(None, 1e-5, 0, None, None, ctypes.byref(out)) == 1
     assert lib.bbfmm_plan_create(None, None, 1, ctypes.byref(out)) == 1
     assert lib.bbfmm_plan_execute(None, None, None, None) == 1
     info = bbfmm.TreeInfo()
@@ -60,6 +60,25 @@ def test_invalid_arguments_rejected_without_gpu():
     lib.bbfmm_tree_free(None)
     lib.bbfmm_ops_free(None)
     lib.bbfmm_plan_free(None)
+
+
+def test_allocator_hook_checked_and_counters_without_gpu():
+    """An allocator hook needs both functions; the runtime counters are
+    readable without a GPU and start with nothing live."""
+    lib = bbfmm.lib()
+    a = bbfmm.TorchAllocator()
+    half = bbfmm.AllocatorHook(a._alloc_cb, bbfmm._FREE_FN(), None)
+    p = bbfmm.TreeParams(0, 1.0, 4, 64, 22, 0)
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(p), ctypes.byref(half), None,
+                                ctypes.byref(out)) == 1
+    assert b"allocator" in lib.bbfmm_last_error()
+    assert out.value is None and a.allocs == 0
+    c = bbfmm.runtime_counters()
+    assert set(c) == {"device_buffers", "device_bytes", "plans", "streams", "events",
+                      "plans_freed_in_flight"}
+    assert c["device_buffers"] == 0 and c["device_bytes"] == 0 and c["plans"] == 0
 
 
 @pytest.mark.parametrize("field,value", [("m2l_split", 9), ("m2l_min_waves", 17),
@@ -73,7 +92,8 @@ def test_plan_options_validated_without_gpu(field, value):
     opt = bbfmm.PlanOptions()
     setattr(opt, field, value)
     out = ctypes.c_void_p()
-    assert lib.bbfmm_plan_create_ex(None, None, 4, ctypes.byref(opt), ctypes.byref(out)) == 1
+    assert lib.bbfmm_plan_create_ex(None, None, 4, ctypes.byref(opt), None, None,
+                                     ctypes.byref(out)) == 1
     assert field.encode() in lib.bbfmm_last_error()
     assert out.value is None
 
