@@ -21,6 +21,11 @@ direct sum.
 ``rows`` restricts the output to a subset of targets (original indices): the
 upward pass and M2L still run over every cell, while L2P and P2P are only
 evaluated for the requested targets.
+
+Separate target and source sets (eq. (1) distinguishes targets x_i from
+sources y_j): the tree is built over the union of both sets, targets first
+(``n_targets`` of them), and each stage sums over sources only (P2M and the
+near field) and evaluates at targets only (L2P and the near field).
 """
 from __future__ import annotations
 
@@ -35,12 +40,16 @@ from .tree import Tree
 
 
 def direct(points: np.ndarray, sigma: np.ndarray, kernel_id: int,
-           param: float, rows: Optional[np.ndarray] = None) -> np.ndarray:
-    """Exact phi = K sigma (eq. (2)) in FP64, for all rows or a subset."""
+           param: float, rows: Optional[np.ndarray] = None,
+           sources: Optional[np.ndarray] = None) -> np.ndarray:
+    """Exact phi = K sigma (eq. (2)) in FP64, for all rows or a subset.
+    With ``sources`` given, ``points`` are the targets and sigma belongs to
+    the sources (eq. (1) with separate sets)."""
     pts = np.asarray(points, dtype=np.float32).astype(np.float64)
+    src = pts if sources is None else np.asarray(sources, np.float32).astype(np.float64)
     sig = _as_2d(sigma)
     tgt = pts if rows is None else pts[np.asarray(rows)]
-    return direct_sum(tgt, pts, sig, kernel_id, param)
+    return direct_sum(tgt, src, sig, kernel_id, param)
 
 
 def _left(A: np.ndarray, X: np.ndarray) -> np.ndarray:
@@ -55,8 +64,11 @@ def _as_2d(sigma) -> np.ndarray:
     return s[:, None] if s.ndim == 1 else s
 
 
-def upward(tree: Tree, ops: Ops, Y: np.ndarray, S: np.ndarray) -> dict:
-    """Multipole coefficients M[level] of shape (cells, n^3, r), levels >= 2."""
+def upward(tree: Tree, ops: Ops, Y: np.ndarray, S: np.ndarray,
+           is_src: Optional[np.ndarray] = None) -> dict:
+    """Multipole coefficients M[level] of shape (cells, n^3, r), levels >= 2,
+    from the sources (``is_src``: which sorted points are sources; all by
+    default)."""
     n = ops.n
     L = tree.leaf_level
     leaf = tree.levels[L]
@@ -65,9 +77,11 @@ def upward(tree: Tree, ops: Ops, Y: np.ndarray, S: np.ndarray) -> dict:
     M = {}
     ML = np.zeros((len(leaf.keys), n ** 3, S.shape[1]))
     for a in range(len(leaf.keys)):
-        b, e = leaf.pb[a], leaf.pe[a]
-        Sa = cheb.lagrange_3d(n, (Y[b:e] - cL[a]) / hL)     # (points, n^3)
-        ML[a] = Sa.T @ S[b:e]
+        j = np.arange(leaf.pb[a], leaf.pe[a])
+        if is_src is not None:
+            j = j[is_src[j]]
+        Sa = cheb.lagrange_3d(n, (Y[j] - cL[a]) / hL)       # (sources, n^3)
+        ML[a] = Sa.T @ S[j]
     M[L] = ML
     T3 = [cheb.m2m_matrix(n, o) for o in range(8)]
     for lvl in range(L - 1, 1, -1):
@@ -117,25 +131,42 @@ def downward(tree: Tree, ops: Ops, F: dict) -> dict:
 def matvec(tree: Tree, ops: Optional[Ops], points: np.ndarray,
            sigma: np.ndarray, kernel_id: int, param: float,
            rows: Optional[np.ndarray] = None, near: bool = True,
-           far: bool = True) -> np.ndarray:
-    """phi ~ K sigma by the bbFMM; returns (len(rows) or N, r) in FP64."""
+           far: bool = True, n_targets: Optional[int] = None) -> np.ndarray:
+    """phi ~ K sigma by the bbFMM; returns (len(rows) or N, r) in FP64.
+
+    n_targets: the tree was built over [targets; sources] and the first
+    n_targets points are the targets; sigma then has one row per source
+    and the result one row per target (rows index the targets)."""
     pts = np.asarray(points, dtype=np.float32).astype(np.float64)
     sig = _as_2d(sigma)
-    N, r = sig.shape
+    N = len(pts)
+    r = sig.shape[1]
+    nt = N if n_targets is None else int(n_targets)
+    is_src = np.ones(N, bool) if n_targets is None else np.arange(N) >= nt
+    if n_targets is None:
+        assert sig.shape[0] == N
+        sig_all = sig
+    else:
+        assert sig.shape[0] == N - nt
+        sig_all = np.zeros((N, r))
+        sig_all[nt:] = sig          # the sources' weights; targets carry none
     L = tree.leaf_level
     Y = pts[tree.perm]
-    S = sig[tree.perm]
+    S = sig_all[tree.perm]
+    src_sorted = is_src[tree.perm]
     leaf = tree.levels[L]
 
     inv = np.empty(N, np.int64)
     inv[tree.perm] = np.arange(N)
-    want_pos = inv if rows is None else inv[np.asarray(rows)]
+    want = np.arange(nt) if rows is None else np.asarray(rows)
+    assert np.all(want < nt)
+    want_pos = inv[want]
     leaf_of = np.searchsorted(leaf.pb, want_pos, side="right") - 1
     out = np.zeros((len(want_pos), r))
 
     if far and L >= 2:
         n = ops.n
-        M = upward(tree, ops, Y, S)
+        M = upward(tree, ops, Y, S, src_sorted)
         F = downward(tree, ops, m2l(tree, ops, M))
         cL = tree.centers(L)
         hL = tree.half_width(L)
@@ -152,6 +183,7 @@ def matvec(tree: Tree, ops: Optional[Ops], points: np.ndarray,
             a = lo_s[s]
             nb = tree.nbr_idx[tree.nbr_off[a]:tree.nbr_off[a + 1]]
             src = np.concatenate([np.arange(leaf.pb[b], leaf.pe[b]) for b in nb])
+            src = src[src_sorted[src]]
             sel = order[s:e]
             out[sel] += direct_sum(Y[want_pos[sel]], Y[src], S[src], kernel_id,
                                    param)

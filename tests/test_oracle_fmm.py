@@ -149,3 +149,59 @@ def test_power_of_two_scale_covariance_inv_r():
     a = _bbfmm(pts, sig, 0, 1.0, 5, 4, 1e-5)
     b = _bbfmm(pts * np.float32(2.0), sig, 0, 1.0, 5, 4, 1e-5)
     assert np.allclose(b, a / 2, rtol=1e-12, atol=0)
+
+
+# Separate target and source sets (eq. (1): targets x_i, sources y_j): the
+# tree is built over [targets; sources]; P2M and the near field sum over the
+# sources only, L2P and the near field evaluate at the targets only.
+def _bbfmm_sets(tgt, src, sig, kid, prm, n, depth, eps, rows=None):
+    union = np.concatenate([tgt, src])
+    tree = T.build_tree(union, fixed_depth=depth)
+    ops = O.precompute(tree, kid, prm, n, eps)
+    return F.matvec(tree, ops, union, sig, kid, prm, rows=rows, n_targets=len(tgt))
+
+
+@pytest.mark.parametrize("n,depth,kind", [(4, 3, "uniform"), (5, 4, "clustered")])
+def test_separate_sets_polynomial_kernel_is_exact(n, depth, kind):
+    """The closed form with separate sets: eq. (3) is exact for a kernel of
+    degree < n per coordinate, so bbFMM(targets, sources) = the direct sum
+    over the sources at the targets."""
+    tgt, _ = synth.random_cloud(900, 130 + n, kind=kind)
+    src, sig = synth.random_cloud(1300, 140 + n, r=2, kind="uniform")
+    got = _bbfmm_sets(tgt, src, sig, 100, 0.7, n, depth, 0.0)
+    ex = F.direct(tgt, sig, 100, 0.7, sources=src)
+    assert got.shape == (900, 2)
+    assert F.rel_l2(got, ex) < 1e-12
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_separate_sets_two_levels_or_fewer_is_the_direct_sum(depth):
+    tgt, _ = synth.random_cloud(500, 151)
+    src, sig = synth.random_cloud(800, 152, r=3, kind="clustered")
+    got = _bbfmm_sets(tgt, src, sig, 1, 0.2, 4, depth, 1e-5)
+    assert F.rel_l2(got, F.direct(tgt, sig, 1, 0.2, sources=src)) < 1e-14
+
+
+def test_separate_sets_equal_sets_reduce_to_the_shared_set():
+    """Targets and sources given as two copies of one cloud: with 1/r
+    (K = 0 at coincident points) every term is the shared-set product's,
+    so the results agree to rounding; a dropped or doubled stage fails."""
+    pts, sig = synth.random_cloud(2000, 153, r=2, kind="clustered")
+    same = _bbfmm(pts, sig, 0, 1.0, 5, 4, 1e-5)
+    sets = _bbfmm_sets(pts, pts, sig, 0, 1.0, 5, 4, 1e-5)
+    assert F.rel_l2(sets, same) < 1e-12
+
+
+def test_separate_sets_error_and_rows():
+    """Disjoint clouds (targets clustered, sources uniform), exp(-r/a): the
+    error against the direct sum is at the level of the compression
+    tolerance, and a subset of target rows equals those rows of the full
+    result."""
+    tgt, _ = synth.random_cloud(1500, 154, kind="clustered")
+    src, sig = synth.random_cloud(2500, 155, r=2)
+    full = _bbfmm_sets(tgt, src, sig, 1, 0.3, 6, 4, 1e-7)
+    ex = F.direct(tgt, sig, 1, 0.3, sources=src)
+    assert F.rel_l2(full, ex) < 1e-5
+    rows = np.array([0, 7, 499, 1499])
+    part = _bbfmm_sets(tgt, src, sig, 1, 0.3, 6, 4, 1e-7, rows=rows)
+    assert np.allclose(part, full[rows], rtol=1e-13, atol=0)
