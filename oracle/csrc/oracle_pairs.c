@@ -13,6 +13,9 @@
  *   0   K = 1/|x-y|, with K = 0 where |x-y|^2 == 0 (singular diagonal)
  *   1   K = exp(-|x-y|/a)
  *   2   K = exp(-|x-y|^2/a^2)
+ *   3   K = (x_1 - y_1)/|x-y|^3, with K = 0 where |x-y|^2 == 0: the x-component
+ *       of a dipole field, skew-symmetric (K(y,x) = -K(x,y)) and homogeneous
+ *       of degree -2
  *   100 K = g(u_x) g(u_y) g(u_z), u = (x-y)/a, g(u) = 1 + u/2 - u^2/3 + u^3/5
  *       (a test kernel: degree 3 in each coordinate, not symmetric)
  *
@@ -31,6 +34,8 @@ static double oracle_kernel(int kid, double a, double dx, double dy, double dz)
         return exp(-sqrt(r2) / a);
     case 2:
         return exp(-r2 / (a * a));
+    case 3:
+        return r2 > 0.0 ? dx / (r2 * sqrt(r2)) : 0.0;
     case 100: {
         double u[3] = {dx / a, dy / a, dz / a};
         double p = 1.0;

@@ -13,7 +13,12 @@ with s_i the 3D Chebyshev node i of [-1,1]^3 (target cell centred at 0,
 source cell centred at 2 h t).
 
 Homogeneous kernels (Section 2.5): K(c x, c y) = c^m K(x, y); the operators
-are built once for h = 1 and scaled by h^m on each level.
+are built once for h = 1 and scaled by h^m on each level (1/r: m = -1; the
+dipole kernel (x_1 - y_1)/|x - y|^3: m = -2).
+
+Symmetry and skew-symmetry (Section 2.5): K(y, x) = +K(x, y) or -K(x, y).
+Then K_{-t} = +K_t^T or -K_t^T, and the compressed operators obey the same
+relation in the reconstructed form U C_{-t} V^T = +-(U C_t V^T)^T.
 
 SVD compression (Section 2.5, "Fast M2L translation"; details follow the
 Fong-Darve construction the paper cites).  Reading taken here:
@@ -38,8 +43,9 @@ from . import cheb
 from ._native import kernel_values
 from .tree import Tree, transfer_vectors
 
-HOMOGENEOUS_DEGREE = {0: -1}       # 1/r has degree -1
-SYMMETRIC = {0: True, 1: True, 2: True, 100: False}
+HOMOGENEOUS_DEGREE = {0: -1, 3: -2}     # 1/r: -1, dipole (x_1 - y_1)/r^3: -2
+# K(y, x) = SYMMETRY * K(x, y): +1 symmetric, -1 skew-symmetric, 0 neither
+SYMMETRY = {0: 1, 1: 1, 2: 1, 3: -1, 100: 0}
 
 
 @dataclasses.dataclass

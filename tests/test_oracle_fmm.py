@@ -38,11 +38,13 @@ def _py_kernel(kid, a, x, y):
         return math.exp(-math.sqrt(r2) / a)
     if kid == 2:
         return math.exp(-r2 / (a * a))
+    if kid == 3:
+        return 0.0 if r2 == 0 else d[0] / (r2 * math.sqrt(r2))
     g = lambda u: 1 + u / 2 - u * u / 3 + u ** 3 / 5
     return g(d[0] / a) * g(d[1] / a) * g(d[2] / a)
 
 
-@pytest.mark.parametrize("kid,prm", [(0, 1.0), (1, 0.3), (2, 0.2), (100, 0.7)])
+@pytest.mark.parametrize("kid,prm", [(0, 1.0), (1, 0.3), (2, 0.2), (3, 1.0), (100, 0.7)])
 def test_direct_sum_against_python_loops(kid, prm):
     pts, sig = synth.random_cloud(40, 9, r=2)
     pts[5] = pts[3]             # a duplicate point: K(x, x) for 1/r is 0
@@ -77,7 +79,7 @@ def test_two_levels_or_fewer_is_the_direct_sum(kid, prm, depth):
     assert F.rel_l2(got, F.direct(pts, sig, kid, prm)) < 1e-14
 
 
-@pytest.mark.parametrize("kid,prm", [(0, 1.0), (1, 1.0)])
+@pytest.mark.parametrize("kid,prm", [(0, 1.0), (1, 1.0), (3, 1.0)])
 def test_error_decays_geometrically_with_order(kid, prm):
     pts, sig = synth.random_cloud(3000, 31)
     ex = F.direct(pts, sig, kid, prm)
@@ -205,3 +207,39 @@ def test_separate_sets_error_and_rows():
     rows = np.array([0, 7, 499, 1499])
     part = _bbfmm_sets(tgt, src, sig, 1, 0.3, 6, 4, 1e-7, rows=rows)
     assert np.allclose(part, full[rows], rtol=1e-13, atol=0)
+
+
+def test_skew_symmetric_kernel_gives_skew_operator():
+    """The dipole kernel K(x, y) = (x_1 - y_1)/|x - y|^3 is skew-symmetric
+    (Section 2.5): the direct sum has u^T K u = 0 and v^T K u = -u^T K v,
+    the compressed operators obey U C_{-t} V^T = -(U C_t V^T)^T, and the
+    bbFMM operator stays skew to rounding."""
+    pts, _ = synth.random_cloud(1200, 44, kind="clustered")
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(1200), rng.standard_normal(1200)
+    Ku = F.direct(pts, u, 3, 1.0)[:, 0]
+    assert abs(u @ Ku) < 1e-12 * np.linalg.norm(u) * np.linalg.norm(Ku)
+    tree = T.build_tree(pts, fixed_depth=4)
+    ops = O.precompute(tree, 3, 1.0, 5, 1e-7)
+    assert O.SYMMETRY[3] == -1
+    tv = T.transfer_vectors()
+    for lvl in (2, 3):
+        op = ops.levels[lvl]
+        for t in (0, 57, 200):
+            neg = int(np.nonzero(np.all(tv == -tv[t], axis=1))[0][0])
+            a = op.U @ op.C[t] @ op.V.T
+            b = op.U @ op.C[neg] @ op.V.T
+            assert np.abs(a + b.T).max() < 1e-9 * np.abs(a).max()
+    Ku = F.matvec(tree, ops, pts, u, 3, 1.0)[:, 0]
+    Kv = F.matvec(tree, ops, pts, v, 3, 1.0)[:, 0]
+    assert abs(v @ Ku + u @ Kv) < 1e-9 * abs(v @ Ku)
+    assert abs(u @ Ku) < 1e-9 * np.linalg.norm(u) * np.linalg.norm(Ku)
+
+
+def test_power_of_two_scale_covariance_dipole():
+    """The dipole kernel is homogeneous of degree -2: phi(2x) = phi(x) / 4
+    (scaling by powers of two is exact in binary floating point)."""
+    pts, sig = synth.random_cloud(1500, 54)
+    a = _bbfmm(pts, sig, 3, 1.0, 5, 4, 1e-5)
+    b = _bbfmm(pts * np.float32(2.0), sig, 3, 1.0, 5, 4, 1e-5)
+    assert np.allclose(b, a / 4, rtol=1e-12, atol=0)
