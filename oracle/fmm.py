@@ -80,10 +80,10 @@ def upward(tree: Tree, ops: Ops, Y: np.ndarray, S: np.ndarray,
         j = np.arange(leaf.pb[a], leaf.pe[a])
         if is_src is not None:
             j = j[is_src[j]]
-        Sa = cheb.lagrange_3d(n, (Y[j] - cL[a]) / hL)       # (sources, n^3)
+        Sa = cheb.lagrange_3d(n, (Y[j] - cL[a]) / hL, ops.nodes)   # (sources, n^3)
         ML[a] = Sa.T @ S[j]
     M[L] = ML
-    T3 = [cheb.m2m_matrix(n, o) for o in range(8)]
+    T3 = [cheb.m2m_matrix(n, o, ops.nodes) for o in range(8)]
     for lvl in range(L - 1, 1, -1):
         child = tree.levels[lvl + 1]
         Mp = np.zeros((len(tree.levels[lvl].keys), n ** 3, S.shape[1]))
@@ -118,7 +118,7 @@ def m2l(tree: Tree, ops: Ops, M: dict) -> dict:
 def downward(tree: Tree, ops: Ops, F: dict) -> dict:
     """Adds the parents' local coefficients into every level >= 3 (L2L)."""
     n = ops.n
-    T3 = [cheb.m2m_matrix(n, o) for o in range(8)]
+    T3 = [cheb.m2m_matrix(n, o, ops.nodes) for o in range(8)]
     for lvl in range(3, tree.depth):
         child = tree.levels[lvl]
         octant = (child.keys & np.uint64(7)).astype(np.int64)
@@ -171,7 +171,7 @@ def matvec(tree: Tree, ops: Optional[Ops], points: np.ndarray,
         cL = tree.centers(L)
         hL = tree.half_width(L)
         xi = (Y[want_pos] - cL[leaf_of]) / hL
-        Sx = cheb.lagrange_3d(n, xi)                       # (targets, n^3)
+        Sx = cheb.lagrange_3d(n, xi, ops.nodes)            # (targets, n^3)
         out += np.matmul(Sx[:, None, :], F[L][leaf_of])[:, 0, :]
 
     if near:

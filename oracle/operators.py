@@ -65,11 +65,13 @@ class Ops:
     kernel_id: int
     kernel_param: float
     levels: Dict[int, LevelOps]
+    nodes: str = "cheb"          # interpolation nodes: "cheb" or "uniform"
 
 
-def sample_m2l(kernel_id: int, param: float, n: int, h: float) -> np.ndarray:
+def sample_m2l(kernel_id: int, param: float, n: int, h: float,
+               nodes: str = "cheb") -> np.ndarray:
     """All 316 K_t at half-width h: array (316, n^3, n^3)."""
-    g = cheb.grid_nodes(n)
+    g = cheb.grid_nodes(n, nodes)
     T = transfer_vectors().astype(np.float64)
     tgt = h * g                                        # (m, 3)
     src = h * (2.0 * T[:, None, :] + g[None, :, :])    # (316, m, 3)
@@ -96,17 +98,23 @@ def compress(K: np.ndarray, eps: float) -> LevelOps:
 
 
 def precompute(tree: Tree, kernel_id: int, param: float, n: int,
-               eps: float) -> Ops:
+               eps: float, nodes: str = "cheb") -> Ops:
+    """Operators of every level >= 2.  With equally spaced nodes ("uniform",
+    Section 2.5 "Fast M2L translation") the operators stay uncompressed
+    (eps is ignored): K_t is the block-Toeplitz matrix a fast method applies
+    with the FFT, and the oracle applies it as the dense product."""
     levels: Dict[int, LevelOps] = {}
+    if nodes == "uniform":
+        eps = 0.0
     deg = HOMOGENEOUS_DEGREE.get(kernel_id)
     if deg is not None:
-        base = compress(sample_m2l(kernel_id, param, n, 1.0), eps)
+        base = compress(sample_m2l(kernel_id, param, n, 1.0, nodes), eps)
         for lvl in range(2, tree.depth):
             s = tree.half_width(lvl) ** deg
             levels[lvl] = LevelOps(base.k, base.U, base.V, base.C * s,
                                    base.sv_fat, base.sv_thin)
     else:
         for lvl in range(2, tree.depth):
-            K = sample_m2l(kernel_id, param, n, tree.half_width(lvl))
+            K = sample_m2l(kernel_id, param, n, tree.half_width(lvl), nodes)
             levels[lvl] = compress(K, eps)
-    return Ops(n, eps, kernel_id, param, levels)
+    return Ops(n, eps, kernel_id, param, levels, nodes)

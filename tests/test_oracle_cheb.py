@@ -98,3 +98,39 @@ def test_m2m_translation_consistency(n, octant):
     l2p_parent = cheb.lagrange_3d(n, pts) @ F
     l2p_child = cheb.lagrange_3d(n, (pts - shift) / 0.5) @ (cheb.m2m_matrix(n, octant).T @ F)
     assert np.allclose(l2p_child, l2p_parent, atol=1e-11)
+
+
+# Equally spaced nodes (Section 2.2: (k-1)/(p-1), k = 1..p, on the cell's
+# [-1, 1] frame): the same Lagrange construction on another node set.
+@pytest.mark.parametrize("n", range(2, 9))
+def test_uniform_nodes_delta_unity_and_exactness(n):
+    s = cheb.nodes(n, "uniform")
+    assert np.allclose(s, np.linspace(-1.0, 1.0, n), atol=1e-15)
+    assert np.allclose(cheb.lagrange_1d(n, s, "uniform"), np.eye(n), atol=1e-12)
+    rng = np.random.default_rng(60 + n)
+    x = rng.uniform(-1, 1, 200)
+    assert np.allclose(cheb.lagrange_1d(n, x, "uniform").sum(axis=1), 1.0, atol=1e-11)
+    c = rng.standard_normal(n)              # degree n-1 is reproduced exactly
+    interp = cheb.lagrange_1d(n, x, "uniform") @ nppoly.polyval(s, c)
+    assert np.allclose(interp, nppoly.polyval(x, c), atol=1e-10)
+    # and degree n is not
+    assert np.max(np.abs(cheb.lagrange_1d(n, x, "uniform") @ s ** n - x ** n)) > 1e-4
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+@pytest.mark.parametrize("octant", [0, 5, 7])
+def test_uniform_nodes_translation_consistency(n, octant):
+    """M2M / L2L identities hold for the uniform basis too (exactness below
+    degree n does not depend on the nodes)."""
+    rng = np.random.default_rng(octant + 70 * n)
+    shift = np.array([(octant >> d) & 1 for d in range(3)]) - 0.5
+    pts = shift + rng.uniform(-0.5, 0.5, (25, 3))
+    sig = rng.standard_normal(25)
+    m_parent = cheb.lagrange_3d(n, pts, "uniform").T @ sig
+    m_child = cheb.lagrange_3d(n, (pts - shift) / 0.5, "uniform").T @ sig
+    T = cheb.m2m_matrix(n, octant, "uniform")
+    assert np.allclose(T @ m_child, m_parent, atol=1e-10)
+    F = rng.standard_normal(n ** 3)
+    l2p_parent = cheb.lagrange_3d(n, pts, "uniform") @ F
+    l2p_child = cheb.lagrange_3d(n, (pts - shift) / 0.5, "uniform") @ (T.T @ F)
+    assert np.allclose(l2p_child, l2p_parent, atol=1e-10)

@@ -243,3 +243,30 @@ def test_power_of_two_scale_covariance_dipole():
     a = _bbfmm(pts, sig, 3, 1.0, 5, 4, 1e-5)
     b = _bbfmm(pts * np.float32(2.0), sig, 3, 1.0, 5, 4, 1e-5)
     assert np.allclose(b, a / 4, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n,depth", [(4, 3), (5, 4)])
+def test_uniform_nodes_polynomial_kernel_is_exact(n, depth):
+    """The closed form holds on equally spaced nodes too: the interpolant of
+    a kernel of degree < n per coordinate is exact (uncompressed
+    block-Toeplitz M2L)."""
+    pts, sig = synth.random_cloud(1500, 160 + n, r=2, kind="clustered")
+    tree = T.build_tree(pts, fixed_depth=depth)
+    ops = O.precompute(tree, 100, 0.7, n, 1e-5, nodes="uniform")
+    assert ops.levels[2].k == n ** 3
+    got = F.matvec(tree, ops, pts, sig, 100, 0.7)
+    assert F.rel_l2(got, F.direct(pts, sig, 100, 0.7)) < 1e-12
+
+
+def test_uniform_nodes_error_decreases_at_low_order():
+    """Equally spaced nodes converge at low order for a smooth kernel (the
+    paper notes Runge's phenomenon at high degree): n = 2..5."""
+    pts, sig = synth.random_cloud(3000, 165)
+    ex = F.direct(pts, sig, 1, 1.0)
+    tree = T.build_tree(pts, fixed_depth=4)
+    errs = []
+    for n in range(2, 6):
+        ops = O.precompute(tree, 1, 1.0, n, 0.0, nodes="uniform")
+        errs.append(F.rel_l2(F.matvec(tree, ops, pts, sig, 1, 1.0), ex))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-4, errs

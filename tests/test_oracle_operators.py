@@ -101,3 +101,27 @@ def test_homogeneous_scaling_matches_direct_sampling():
             a = op.U @ op.C[ti] @ op.V.T
             b = direct.U @ direct.C[ti] @ direct.V.T
             assert np.allclose(a, b, rtol=0, atol=1e-9 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("n", [2, 4, 5])
+def test_uniform_node_operator_is_block_toeplitz(n):
+    """With equally spaced nodes K_t[i, j] depends only on the per-axis
+    index differences i_d - j_d (Section 2.5, fast M2L translation): a
+    p^3 x p^3 operator with only (2p - 1)^3 distinct entries."""
+    K = O.sample_m2l(1, 0.7, n, 0.3, nodes="uniform")
+    idx = np.arange(n ** 3)
+    i3 = np.stack([idx % n, (idx // n) % n, idx // (n * n)], axis=1)
+    diff = i3[:, None, :] - i3[None, :, :] + (n - 1)           # in [0, 2n-2]
+    code = diff[..., 0] + (2 * n - 1) * (diff[..., 1] + (2 * n - 1) * diff[..., 2])
+    for t in (0, 150, 315):
+        vals = {}
+        for c, v in zip(code.ravel(), K[t].ravel()):
+            vals.setdefault(int(c), []).append(v)
+        assert len(vals) == (2 * n - 1) ** 3
+        assert max(np.ptp(v) for v in vals.values()) <= 1e-15 * np.abs(K[t]).max()
+    # Chebyshev nodes have no such structure (from n = 3 on; two nodes are
+    # symmetric about 0 and so equally spaced)
+    if n > 2:
+        Kc = O.sample_m2l(1, 0.7, n, 0.3)[150].ravel()
+        spread = max(np.ptp(Kc[code.ravel() == c]) for c in np.unique(code))
+        assert spread > 1e-6 * np.abs(Kc).max()
