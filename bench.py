@@ -63,12 +63,32 @@ def flops_per_pair_p2p(kernel_id: int, r: int) -> int:
     return base + 2 * r
 
 
-def cpu_baseline(w, gpu_phi_rows):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_threads() -> int:
+    """Threads the oracle's BLAS and OpenMP pools use right now."""
+    from threadpoolctl import threadpool_info
+    return max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+
+
+def cpu_baseline(w, gpu_phi_rows, single_rows: int = 512):
     """The oracle as it stands on this host: full upward pass and M2L, L2P
-    and P2P on the sampled targets; P2P time scaled to all N targets.  For
-    a block of right-hand sides the oracle runs the first column only (the
-    columns are independent) and the rate is per column."""
+    and P2P on the sampled targets; P2P time scaled to all N targets.  Run
+    on all host threads (the value) and again on one thread (on the first
+    `single_rows` sampled targets).  For a block of right-hand sides the
+    oracle runs the first column only (the columns are independent) and the
+    rate is per column."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import fmm as ofmm, operators as oops, tree as otree
     rows = w.sample_rows if w.r == 1 else w.sample_rows[::4]
     sig = w.sigma[:, :1]
@@ -77,27 +97,119 @@ def cpu_baseline(w, gpu_phi_rows):
                           fixed_depth=w.fixed_depth)
     ops = oops.precompute(tr, w.kernel_id, w.kernel_param, w.order, w.eps)
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ref = ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rows)
-    t_sample = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rows, far=False)
-    t_near = time.perf_counter() - t0
-    est = t_sample + t_near * (w.n / len(rows) - 1.0)
+
+    def timed(rws):
+        t0 = time.perf_counter()
+        ref = ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rws)
+        t_sample = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ofmm.matvec(tr, ops, w.points, sig, w.kernel_id, w.kernel_param, rows=rws, far=False)
+        t_near = time.perf_counter() - t0
+        return ref, t_sample, t_near, t_sample + t_near * (w.n / len(rws) - 1.0)
+
+    threads = _oracle_threads()
+    ref, t_sample, t_near, est = timed(rows)
+    with threadpool_limits(limits=1):
+        one_threads = _oracle_threads()
+        _, t1_sample, t1_near, est1 = timed(rows[:single_rows])
     exact = ofmm.direct(w.points, sig, w.kernel_id, w.kernel_param, rows=rows)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     got = gpu_phi_rows[:len(rows)] if w.r == 1 else gpu_phi_rows[::4][:, :1]
     return {
-        "value": w.n / est, "unit": "points*RHS/s", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 oracle bbFMM on the same workload (first right-hand side): upward "
-                   f"pass and M2L over all cells plus L2P+P2P on {len(rows)} sampled targets "
-                   f"took {t_sample:.2f} s; its P2P part ({t_near:.2f} s) scaled by "
-                   f"N/{len(rows)} gives {est:.1f} s per matvec (tree + operator setup "
-                   f"{t_setup:.1f} s excluded)"),
+        "value": w.n / est, "unit": "points*RHS/s", "cores": threads, "kind": "oracle",
+        "cpu_model": _cpu_model(), "host_logical_cpus": os.cpu_count(),
+        "sample": (f"FP64 oracle bbFMM on the same workload (first right-hand side), "
+                   f"{threads} threads: upward pass and M2L over all cells plus L2P+P2P on "
+                   f"{len(rows)} sampled targets took {t_sample:.2f} s; its P2P part "
+                   f"({t_near:.2f} s) scaled by N/{len(rows)} gives {est:.1f} s per matvec "
+                   f"(tree + operator setup {t_setup:.1f} s excluded)"),
+        "single_thread": {
+            "value": w.n / est1, "unit": "points*RHS/s", "cores": one_threads,
+            "sample": (f"same, one thread, L2P+P2P on {min(single_rows, len(rows))} sampled "
+                       f"targets: {t1_sample:.2f} s, P2P part {t1_near:.2f} s, {est1:.1f} s "
+                       f"per matvec")},
         "rel_err_gpu_vs_oracle": ofmm.rel_l2(got, ref),
         "rel_err_gpu_vs_direct": ofmm.rel_l2(got, exact),
         "rel_err_oracle_vs_direct": ofmm.rel_l2(ref, exact),
     }
+
+
+def fft_m2l_section(w, sig, steps: int = 20):
+    """The second M2L variant (Section 2.5): equally spaced nodes with the
+    block-Toeplitz M2L applied by the FFT, on the same workload and order as
+    the headline, beside the Chebyshev/SVD form; error against the direct
+    sum on the workload's sampled rows for both."""
+    import numpy as np
+    import torch
+
+    from oracle import fmm as ofmm
+    from paper_1903_02153_amd import bbfmm
+    pts = torch.from_numpy(w.points).cuda()
+    tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
+                            leaf_size=w.leaf_size, max_depth=w.max_depth,
+                            fixed_depth=w.fixed_depth)
+    exact = ofmm.direct(w.points, w.sigma, w.kernel_id, w.kernel_param, rows=w.sample_rows)
+    out = {"workload": w.name, "order": w.order}
+    for tag, prec in (("svd_fp32", bbfmm.M2L_FP32), ("fft_uniform", bbfmm.M2L_FFT)):
+        ops = bbfmm.precompute_operators(tree, w.eps, prec)
+        plan = bbfmm.Plan(tree, ops, w.r)
+        phi = torch.empty_like(sig)
+        lat = time_plan(plan, sig, phi, steps, 3)
+        plan.set_timing(True)
+        plan.stage_times(reset=True)
+        for _ in range(5):
+            plan.execute(sig, phi)
+        torch.cuda.synchronize()
+        st, ne = plan.stage_times(reset=True)
+        got = phi.cpu().numpy().astype(np.float64)[w.sample_rows]
+        med = float(np.median(lat))
+        out[tag] = {"ms_median": round(med, 4), "points_rhs_per_s": w.n * w.r / (med * 1e-3),
+                    "m2l_ms": round(st["m2l"] / ne, 4),
+                    "up_ms": round((st["p2m"] + st["m2m"]) / ne, 4),
+                    "down_ms": round(st["down"] / ne, 4),
+                    "rel_err_vs_direct": ofmm.rel_l2(got, exact)}
+        plan.close()
+        ops.close()
+    return out
+
+
+def order_study(orders=range(2, 9)):
+    """Error against the direct sum per Chebyshev order (the error-versus-
+    order study of the paper's accuracy section) on the small uniform
+    workload (4096 points, 1/r, 3 levels): the GPU FP32 matvec and the FP64
+    oracle bbFMM at each order, with SVD tolerance 1e-5 and without
+    compression."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import fmm as ofmm, operators as oops, tree as otree
+    from paper_1903_02153_amd import bbfmm
+    w = synth.cfg_small()
+    exact = ofmm.direct(w.points, w.sigma, w.kernel_id, w.kernel_param)
+    ot = otree.build_tree(w.points, fixed_depth=w.fixed_depth)
+    pts = torch.from_numpy(w.points).cuda()
+    sig = torch.from_numpy(np.ascontiguousarray(w.sigma, dtype=np.float32)).cuda()
+    if sig.dim() == 1:
+        sig = sig[:, None].contiguous()
+    out = []
+    for n in orders:
+        tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=n,
+                                fixed_depth=w.fixed_depth)
+        for eps in (1e-5, 0.0):
+            ops = bbfmm.precompute_operators(tree, eps)
+            got = bbfmm.matvec(tree, ops, sig)
+            torch.cuda.synchronize()
+            g = got.cpu().numpy().astype(np.float64)
+            oo = oops.precompute(ot, w.kernel_id, w.kernel_param, n, eps)
+            ref = ofmm.matvec(ot, oo, w.points, w.sigma, w.kernel_id, w.kernel_param)
+            out.append({"n": n, "svd_eps": eps,
+                        "gpu_vs_direct": ofmm.rel_l2(g, exact),
+                        "gpu_vs_oracle": ofmm.rel_l2(g, ref),
+                        "oracle_vs_direct": ofmm.rel_l2(ref, exact)})
+            ops.close()
+        tree.close()
+    return {"workload": w.name, "N": w.n, "kernel": "1/r", "depth": w.fixed_depth,
+            "rows": "all", "per_order": out}
 
 
 def time_plan(plan, sig, phi, steps: int, warmup: int):
@@ -308,9 +420,14 @@ def main() -> int:
                     help="M2L precision (default: fp32 for uniform-1M, else the workload's own)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in launch-shape heuristic instead of bbfmm_plan_autotune")
+    ap.add_argument("--plan-options", default=None,
+                    help="JSON object of plan options to use instead of autotuning (for profiling "
+                         "runs that repeat a configuration)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the batched mixed-precision comparison (clustered-2M, slab-1M)")
     ap.add_argument("--no-serving", action="store_true", help="skip the 8-tree serving mix")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the error-per-order study and the FFT M2L comparison")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-load", type=float, default=0.7)
@@ -342,7 +459,9 @@ def main() -> int:
                             fixed_depth=w.fixed_depth)
     ops = bbfmm.precompute_operators(tree, w.eps, prec)
     opts = {}
-    if not args.no_autotune:     # launch shapes only; outside the timed region
+    if args.plan_options:
+        opts = {k: int(v) for k, v in json.loads(args.plan_options).items()}
+    elif not args.no_autotune:     # launch shapes only; outside the timed region
         opts, _ = bbfmm.autotune(tree, ops, sig, phi, reps=5)
     plan = bbfmm.Plan(tree, ops, w.r, **opts)
     info = tree.info()
@@ -450,6 +569,11 @@ def main() -> int:
     if not args.no_variants:
         out["pca"] = pca_section()
         progress("randomized eigendecomposition done")
+    if args.workload == "uniform-1M" and not args.no_extras:
+        out["order_study"] = order_study()
+        progress("error per order done")
+        out["m2l_fft"] = fft_m2l_section(w, sig)
+        progress("FFT M2L variant done")
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         plan.execute(sig, phi)

@@ -60,6 +60,9 @@ enum {
                                homogeneous, degree -1                              */
     BBFMM_K_EXP = 1,        /* exp(-|x-y|/a), a = kernel_param                         */
     BBFMM_K_GAUSS = 2,      /* exp(-|x-y|^2/a^2), a = kernel_param                      */
+    BBFMM_K_DIPOLE_X = 3,   /* (x_1-y_1)/|x-y|^3 (x target, y source); K = 0 where
+                               |x-y|^2 == 0 (as for 1/r); skew-symmetric,
+                               homogeneous of degree -2 (Section 2.5)            */
     BBFMM_K_POLY_TEST = 100 /* prod_d g((x_d-y_d)/a), g(u) = 1 + u/2 - u^2/3 + u^3/5:
                                degree 3 per coordinate, for exactness tests only     */
 };
@@ -70,8 +73,12 @@ enum {
     BBFMM_M2L_FP32 = 0,         /* FP32 operands, FP32 MFMA                          */
     BBFMM_M2L_BF16X3 = 1,       /* operands split x = hi + lo in bf16; products
                                    hi*hi + hi*lo + lo*hi on bf16 MFMA, FP32 accumulate */
-    BBFMM_M2L_FP16_SCALED = 2   /* fp16 operands with a power-of-two scale per operator
+    BBFMM_M2L_FP16_SCALED = 2,  /* fp16 operands with a power-of-two scale per operator
                                    and per (cell, RHS, 64 ranks) block; FP32 accumulate */
+    BBFMM_M2L_FFT = 3           /* equally spaced interpolation nodes (Section 2.2) and
+                                   the uncompressed block-Toeplitz M2L applied with the
+                                   FFT (Section 2.5): transforms of size (2n)^3 per
+                                   cell, FP32 complex; svd_eps is ignored             */
 };
 
 typedef struct {
@@ -122,7 +129,11 @@ typedef struct {
     int32_t max_leaf_points;
     int32_t cells[22];         /* occupied cells per level                         */
     int64_t pairs[22];         /* M2L pairs per level (0 on levels 0 and 1)        */
-    int64_t near_pairs;        /* point pairs evaluated by P2P                     */
+    int64_t near_pairs;        /* point pairs of neighbouring leaves (over all
+                                  points, also with separate sets)                */
+    int64_t n_targets;         /* rows of phi: N, or the targets of a tree over
+                                  separate sets                                   */
+    int64_t n_sources;         /* rows of sigma: N, or the sources                 */
 } bbfmm_tree_info;
 
 /*
@@ -148,6 +159,23 @@ bbfmm_status bbfmm_build_tree(const float *points, int64_t n,
                               const bbfmm_tree_params *params,
                               const bbfmm_allocator *allocator, void *stream,
                               bbfmm_tree **out);
+
+/*
+ * The same for separate target and source sets (eq. (1): phi(x_i) = sum_j
+ * K(x_i, y_j) sigma_j with targets x and sources y): one octree over the
+ * bounding cube of both sets, whose points are [targets; sources].  A
+ * product on such a tree takes sigma with one row per source and writes phi
+ * with one row per target: P2M and the near field sum over the sources of
+ * a leaf, L2P and the near field evaluate at its targets.
+ *   targets  device, n_targets x 3 float32;  sources  device, n_sources x 3.
+ *   n_targets, n_sources >= 1, n_targets + n_sources < 2^31.
+ * The depth rule counts the points of both sets.  Errors as bbfmm_build_tree.
+ */
+bbfmm_status bbfmm_build_tree_sets(const float *targets, int64_t n_targets,
+                                   const float *sources, int64_t n_sources,
+                                   const bbfmm_tree_params *params,
+                                   const bbfmm_allocator *allocator, void *stream,
+                                   bbfmm_tree **out);
 
 bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *tree, bbfmm_tree_info *out);
 
@@ -236,8 +264,10 @@ bbfmm_status bbfmm_ops_import(const bbfmm_tree *tree, int32_t precision,
 
 /*
  * phi = K sigma for r right-hand sides (Section 2.5, multiple RHS).
- *   sigma  device, N x r float32 row-major (r fastest), original point order.
- *   phi    device, N x r float32, overwritten; must not overlap sigma.
+ *   sigma  device, N x r float32 row-major (r fastest), original point order
+ *          (n_sources x r for a tree over separate sets).
+ *   phi    device, N x r float32, overwritten; must not overlap sigma
+ *          (n_targets x r for a tree over separate sets).
  * Enqueues gather, P2M, M2M, compression, M2L, decompression, L2L, L2P and
  * P2P on the stream and returns without waiting for them (asynchronous).
  * The workspace comes from a cache held by the operator set: one plan per
@@ -293,6 +323,16 @@ typedef struct {
     int32_t m2l_layout;     /* FP32 M2L waves: 1 = 16 rank rows x 64 columns     */
                             /* each, 2 = 32 x 32 (half the LDS reads per MFMA);  */
                             /* 0 = 1                                             */
+    int32_t m2l_schedule;   /* 1: one M2L launch for all levels after the upward */
+                            /* pass; 2: each level's M2L starts as soon as its   */
+                            /* compressed multipoles exist (the upward chain     */
+                            /* runs on a second stream, Section 2.4); 0 = 2 with */
+                            /* at least two M2L levels                           */
+    int32_t m2l_block;      /* 16-bit M2L: 1 = tiles of 64 (target, column)      */
+                            /* pairs of one octant; 2 = the children of a parent */
+                            /* cell as one block, each source of their halo      */
+                            /* staged once for all of them (no slot split);      */
+                            /* 0 = 2 from r = 16 on                              */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a
@@ -352,15 +392,18 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  * schedule on or off; then, overlapped with the per-lane kernel, the
  * near-field workgroup count (one per item, or 512 .. 4096); then, when
  * overlapped, the M2L workgroups per CU (as many as fit, 3 or 2); then
- * the FP32 M2L wave layout.  Each candidate runs one
+ * the FP32 M2L wave layout; then the M2L schedule (one launch, or per
+ * level as the upward pass finishes each level); then, for a 16-bit M2L,
+ * the target grouping (64-column tiles or parent blocks).  Each candidate runs one
  * untimed product and `reps` timed ones (HIP events on `stream`); its
  * time is the median.  Options only change launch shapes (and with them
  * the floating-point summation order), never the arithmetic precision.
- *   sigma, phi  device, N x r float32; phi is overwritten by every trial.
+ *   sigma, phi  device, float32 (n_sources x r, n_targets x r; N x r for one
+ *               set); phi is overwritten by every trial.
  *   reps        1..100.
  *   best        out: the chosen options (m2l_split, p2p_mfma,
- *               p2p_max_split, overlap, p2p_waves, m2l_occupancy and
- *               m2l_layout explicit).
+ *               p2p_max_split, overlap, p2p_waves, m2l_occupancy,
+ *               m2l_layout, m2l_schedule and m2l_block explicit).
  *   best_ms     out (may be NULL): its median milliseconds per product.
  * Allocates and frees one plan workspace per candidate; synchronizes
  * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
@@ -380,7 +423,8 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *tree, const bbfmm_ops *ops, i
  * replayed as a HIP graph) stays within hbm_budget_bytes; idle plans are
  * evicted least recently used first to make room.  A request larger than
  * the budget on its own fails with BBFMM_ERR_BUDGET (reported by wait).
- *   sigma, phi  device, N x r float32 (the model's N); must stay valid and
+ *   sigma, phi  device, float32, n_sources x r and n_targets x r of the
+ *               model's tree (N x r for one set); must stay valid and
  *               untouched until wait returns.
  * Batch invariance: every server plan uses m2l_split = 2 and p2p_mfma = 2,
  * and with these fixed the arithmetic of one column does not depend on the

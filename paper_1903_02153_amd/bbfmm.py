@@ -19,8 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
-K_INV_R, K_EXP, K_GAUSS, K_POLY_TEST = 0, 1, 2, 100
-M2L_FP32, M2L_BF16X3, M2L_FP16_SCALED = 0, 1, 2
+K_INV_R, K_EXP, K_GAUSS, K_DIPOLE_X, K_POLY_TEST = 0, 1, 2, 3, 100
+M2L_FP32, M2L_BF16X3, M2L_FP16_SCALED, M2L_FFT = 0, 1, 2, 3
 
 TA = dict(perm=0, keys=1, pb=2, pe=3, parent=4, cb=5, ce=6, nbr_off=7, nbr_idx=8,
           pair_t=9, pair_tgt=10, pair_src=11, pair_goff=12)
@@ -50,7 +50,8 @@ class TreeInfo(ctypes.Structure):
                 ("kernel_param", ctypes.c_double), ("lo", ctypes.c_float * 3),
                 ("side", ctypes.c_float), ("scale", ctypes.c_float),
                 ("max_leaf_points", ctypes.c_int32), ("cells", ctypes.c_int32 * 22),
-                ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64)]
+                ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64),
+                ("n_targets", ctypes.c_int64), ("n_sources", ctypes.c_int64)]
 
 
 class RequestStats(ctypes.Structure):
@@ -69,7 +70,8 @@ class PlanOptions(ctypes.Structure):
     _fields_ = [("m2l_split", ctypes.c_int32), ("m2l_min_waves", ctypes.c_int32),
                 ("p2p_max_split", ctypes.c_int32), ("p2p_mfma", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("p2p_waves", ctypes.c_int32),
-                ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32)]
+                ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32),
+                ("m2l_schedule", ctypes.c_int32), ("m2l_block", ctypes.c_int32)]
 
 
 class RuntimeCounters(ctypes.Structure):
@@ -148,6 +150,8 @@ _VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_
 _PVP = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "bbfmm_build_tree": (_I32, [_VP, _I64, ctypes.POINTER(TreeParams), _VP, _VP, _PVP]),
+    "bbfmm_build_tree_sets": (_I32, [_VP, _I64, _VP, _I64, ctypes.POINTER(TreeParams), _VP, _VP,
+                                     _PVP]),
     "bbfmm_tree_info_get": (_I32, [_VP, ctypes.POINTER(TreeInfo)]),
     "bbfmm_tree_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
     "bbfmm_precompute_operators": (_I32, [_VP, _D, _I32, _VP, _VP, _PVP]),
@@ -301,7 +305,7 @@ class Plan:
 
     def __init__(self, tree: Tree, ops: Ops, r: int, allocator=None, stream=None, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
-        m2l_occupancy, m2l_layout (0 = heuristic).  allocator: a TorchAllocator
+        m2l_occupancy, m2l_layout, m2l_schedule, m2l_block (0 = heuristic).  allocator: a TorchAllocator
         (None = the operators'); stream: where the set-up is enqueued."""
         h = _VP()
         opt = PlanOptions()
@@ -314,7 +318,8 @@ class Plan:
         self.options = dict(options)
         self._h = h.value
         self.tree, self.ops, self.r = tree, ops, int(r)
-        self.n = tree.info().n_points
+        info = tree.info()
+        self.n_in, self.n_out = info.n_sources, info.n_targets
 
     def workspace_bytes(self) -> int:
         b = _I64(0)
@@ -336,8 +341,8 @@ class Plan:
         return dict(zip(STAGES, list(ms))), n.value
 
     def execute(self, sigma, phi, stream=None):
-        _device_f32(sigma, "sigma", (self.n, self.r))
-        _device_f32(phi, "phi", (self.n, self.r))
+        _device_f32(sigma, "sigma", (self.n_in, self.r))
+        _device_f32(phi, "phi", (self.n_out, self.r))
         _check(lib().bbfmm_plan_execute(self._h, sigma.data_ptr(), phi.data_ptr(),
                                         _stream_handle(stream)))
         return phi
@@ -358,10 +363,11 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
     """Fastest launch-shape options for (tree, ops, r = sigma.shape[1]) on this
     data (bbfmm_plan_autotune); returns (options dict for Plan, median ms)."""
     import torch
-    _device_f32(sigma, "sigma")
+    info = tree.info()
+    _device_f32(sigma, "sigma", (info.n_sources, sigma.shape[1]))
     if phi is None:
-        phi = torch.empty_like(sigma)
-    _device_f32(phi, "phi", tuple(sigma.shape))
+        phi = torch.empty((info.n_targets, sigma.shape[1]), dtype=sigma.dtype, device=sigma.device)
+    _device_f32(phi, "phi", (info.n_targets, sigma.shape[1]))
     best = PlanOptions()
     ms = ctypes.c_double(0.0)
     _check(lib().bbfmm_plan_autotune(tree.handle, ops.handle, sigma.shape[1], sigma.data_ptr(),
@@ -370,24 +376,36 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
     return {"m2l_split": best.m2l_split, "p2p_max_split": best.p2p_max_split,
             "p2p_mfma": best.p2p_mfma, "overlap": best.overlap,
             "p2p_waves": best.p2p_waves, "m2l_occupancy": best.m2l_occupancy,
-            "m2l_layout": best.m2l_layout}, ms.value
+            "m2l_layout": best.m2l_layout, "m2l_schedule": best.m2l_schedule,
+            "m2l_block": best.m2l_block}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
                cheb_order: int = 4, leaf_size: int = 64, max_depth: int = 22,
-               fixed_depth: int = 0, stream=None, allocator="torch") -> Tree:
+               fixed_depth: int = 0, stream=None, allocator="torch", sources=None) -> Tree:
     """Octree over the bounding cube of ``points`` ((N,3) float32 on the GPU).
+    sources: a second (M,3) set; then ``points`` are the targets, products
+    take sigma of M rows and give phi of N rows (bbfmm_build_tree_sets).
     allocator: "torch" (torch's caching allocator owns the library's device
     memory; the default), a TorchAllocator, or None (hipMalloc)."""
-    if points.dim() != 2 or points.shape[1] != 3:
-        raise ValueError("points must have shape (N, 3)")
+    for name, pts in (("points", points), ("sources", sources)):
+        if pts is not None and (pts.dim() != 2 or pts.shape[1] != 3):
+            raise ValueError(f"{name} must have shape (N, 3)")
     _device_f32(points, "points")
     if allocator == "torch":
         allocator = torch_allocator()
     p = TreeParams(kernel_id, kernel_param, cheb_order, leaf_size, max_depth, fixed_depth)
     h = _VP()
-    _check(lib().bbfmm_build_tree(points.data_ptr(), points.shape[0], ctypes.byref(p),
-                                  _hook_arg(allocator), _stream_handle(stream), ctypes.byref(h)))
+    if sources is None:
+        _check(lib().bbfmm_build_tree(points.data_ptr(), points.shape[0], ctypes.byref(p),
+                                      _hook_arg(allocator), _stream_handle(stream),
+                                      ctypes.byref(h)))
+    else:
+        _device_f32(sources, "sources")
+        _check(lib().bbfmm_build_tree_sets(points.data_ptr(), points.shape[0],
+                                           sources.data_ptr(), sources.shape[0], ctypes.byref(p),
+                                           _hook_arg(allocator), _stream_handle(stream),
+                                           ctypes.byref(h)))
     return Tree(h.value, p, allocator)
 
 
@@ -425,10 +443,11 @@ def matvec(tree: Tree, ops: Ops, sigma, phi=None, stream=None):
     import torch
     squeeze = sigma.dim() == 1
     s2 = sigma.reshape(-1, 1) if squeeze else sigma
-    _device_f32(s2, "sigma")
+    info = tree.info()
+    _device_f32(s2, "sigma", (info.n_sources, s2.shape[1]))
     if phi is None:
-        phi = torch.empty_like(s2)
-    _device_f32(phi, "phi", tuple(s2.shape))
+        phi = torch.empty((info.n_targets, s2.shape[1]), dtype=s2.dtype, device=s2.device)
+    _device_f32(phi, "phi", (info.n_targets, s2.shape[1]))
     _check(lib().bbfmm_matvec(tree.handle, ops.handle, s2.data_ptr(), s2.shape[1],
                               phi.data_ptr(), _stream_handle(stream)))
     return phi.reshape(-1) if squeeze else phi

@@ -169,6 +169,22 @@ bbfmm_status bbfmm_build_tree(const float *points, int64_t n, const bbfmm_tree_p
     });
 }
 
+bbfmm_status bbfmm_build_tree_sets(const float *targets, int64_t n_targets, const float *sources,
+                                   int64_t n_sources, const bbfmm_tree_params *params,
+                                   const bbfmm_allocator *allocator, void *stream,
+                                   bbfmm_tree **out) {
+    return guarded([&] {
+        BB_REQUIRE(params != nullptr && out != nullptr, "params / out is NULL");
+        *out = nullptr;
+        BB_REQUIRE(allocator == nullptr || (allocator->alloc && allocator->free),
+                   "allocator needs both alloc and free");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        MemScope scope(allocator, s);
+        *out = build_tree_sets_impl(targets, n_targets, sources, n_sources, *params, s);
+        if (allocator) (*out)->hook = *allocator;
+    });
+}
+
 bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *t, bbfmm_tree_info *out) {
     return guarded([&] {
         BB_REQUIRE(t != nullptr && out != nullptr, "tree / out is NULL");
@@ -187,6 +203,8 @@ bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *t, bbfmm_tree_info *out) {
             out->pairs[l] = t->lv[l].npairs;
         }
         out->near_pairs = t->near_pairs;
+        out->n_targets = t->n_out();
+        out->n_sources = t->n_in();
     });
 }
 
@@ -254,6 +272,8 @@ bbfmm_status bbfmm_ops_export(const bbfmm_ops *o, int32_t what, int32_t level, v
             fail(BBFMM_ERR_NOT_FOUND, "level %d has no M2L operators", level);
         const OpSet &set = *o->lv[level].set;
         const int64_t m = o->m, k = set.k;
+        if (o->precision == BBFMM_M2L_FFT)
+            fail(BBFMM_ERR_NOT_FOUND, "the FFT M2L keeps operator spectra, not U, V, C");
         switch (what) {
         case BBFMM_OA_U: copy_out(set.U64.p, m * k, dst, capacity, size); break;
         case BBFMM_OA_V: copy_out(set.V64.p, m * k, dst, capacity, size); break;
@@ -478,6 +498,17 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 bbfmm_plan_options c = cur;
                 c.overlap = 2;
                 c.m2l_occupancy = occ;
+                consider(c);
+            }
+        for (int sch = 1; sch <= 2; ++sch) {
+            bbfmm_plan_options c = cur;
+            c.m2l_schedule = sch;
+            consider(c);
+        }
+        if (o->precision == BBFMM_M2L_BF16X3 || o->precision == BBFMM_M2L_FP16_SCALED)
+            for (int blk = 1; blk <= 2; ++blk) {
+                bbfmm_plan_options c = cur;
+                c.m2l_block = blk;
                 consider(c);
             }
         // make every choice explicit: what the heuristic picked for the zeros

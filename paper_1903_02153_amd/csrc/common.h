@@ -164,8 +164,19 @@ struct bbfmm_tree {
     int64_t nbr_nnz = 0;
     bbfmm::DBuf<int32_t> tables;    // tvec[316][3], slot_t[8][189], t_slot[8][316]
     std::vector<int32_t> leaf_pb_h, leaf_pe_h;   // host copies of the leaf point ranges
+    // Separate target and source sets: the points are [targets; sources]
+    // (n_targets of them targets; 0 = one set, every point both).  Within a
+    // leaf the targets come first (stable sort): targets [pb, te), sources
+    // [sb, pe) with te == sb.
+    int64_t n_targets = 0;
+    bbfmm::DBuf<int32_t> leaf_sb, leaf_te;      // per leaf, only with separate sets
+    std::vector<int32_t> leaf_te_h;             // host copy of the target ends (pe for one set)
     bbfmm_allocator hook{};         // allocator of the tree, inherited by its operators and plans
     int leaf_level() const { return depth - 1; }
+    const int32_t *src_begin() const { return n_targets ? leaf_sb.p : lv[depth - 1].pb.p; }
+    const int32_t *tgt_end() const { return n_targets ? leaf_te.p : lv[depth - 1].pe.p; }
+    int64_t n_out() const { return n_targets ? n_targets : n; }          // rows of phi
+    int64_t n_in() const { return n - n_targets; }                       // rows of sigma
     double half_width(int level) const { return double(side) / double(1ull << (level + 1)); }
 };
 
@@ -190,6 +201,7 @@ struct OpSet {
     DBuf<uint16_t> Chi, Clo;         // 316 x kp x kp bf16 halves, split-BF16 M2L
     DBuf<uint16_t> C16;              // 316 x kp x kp fp16 scaled by 2^e_t, FP16 M2L
     DBuf<float> Cinv;                // 316: 2^-e_t
+    DBuf<float2> Ghat;               // FFT M2L: 316 x Q operator spectra (fft_m2l.hip)
 };
 
 struct PlanCache;
@@ -207,6 +219,7 @@ struct bbfmm_ops {
     int n = 0, m = 0, mp = 0;        // order, n^3, n^3 padded to a multiple of 16
     int precision = 0;
     double eps = 0.0;
+    int nodes = 0;                   // interpolation nodes: 0 Chebyshev, 1 equally spaced
     bbfmm::ChebConst cheb{};
     std::vector<std::unique_ptr<bbfmm::OpSet>> sets;
     bbfmm::OpsLevel lv[bbfmm::kMaxLevels];
@@ -222,8 +235,24 @@ namespace bbfmm {
 // --------------------------------------------------------------- entry ----
 bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params &p,
                             hipStream_t s);
+// a tree over [targets; sources] (both device N x 3)
+bbfmm_tree *build_tree_sets_impl(const float *targets, int64_t nt, const float *sources,
+                                 int64_t ns, const bbfmm_tree_params &p, hipStream_t s);
 bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s);
-void cheb_setup(bbfmm_ops *ops, hipStream_t s);
+void cheb_setup(bbfmm_ops *ops, hipStream_t s);   // nodes of ops->nodes
+
+// FFT M2L on equally spaced nodes (fft_m2l.hip): transform size P = 2n per
+// axis, Q = (P/2 + 1) P^2 complex values per (cell, column)
+int fft_size(int n);
+int fft_freqs(int n);
+void fft_operator_spectra(int kid, double a, int n, double h, const int32_t *tvec,
+                          DBuf<float2> &Ghat, hipStream_t s);
+void fft_forward(int n, const float *M, int mp, int64_t rows, float2 *Mhat, hipStream_t s);
+void fft_inverse(int n, const float2 *Fhat, int64_t rows, float scale, bool accumulate, int mp,
+                 float *F, hipStream_t s);
+void fft_m2l(int n, const float2 *Mhat, const float2 *Ghat, const int32_t *itab,
+             const uint64_t *keys, const int32_t *slot_t, int64_t cells, int r, float2 *Fhat,
+             hipStream_t s);
 void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s);
 
 struct Plan;

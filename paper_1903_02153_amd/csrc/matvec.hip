@@ -121,6 +121,11 @@ __device__ inline float kernel_eval(float dx, float dy, float dz) {
         return __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz));
     } else if constexpr (KID == BBFMM_K_GAUSS) {
         return __builtin_amdgcn_exp2f(-(dx * dx + dy * dy + dz * dz));
+    } else if constexpr (KID == BBFMM_K_DIPOLE_X) {
+        // dx / r^3 with the same coincidence guard as 1/r (0 * 0 = 0)
+        const float r2 = __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, __fmaf_rn(dz, dz, -kInvRBias)));
+        const float ir = __builtin_fmaxf(__frsqrt_rn(r2), 0.f);
+        return dx * (ir * ir * ir);
     } else {
         const float u[3] = {dx, dy, dz};
         float p = 1.f;
@@ -136,6 +141,7 @@ inline float coord_scale(int kid, double a) {
     const double log2e = 1.4426950408889634;
     switch (kid) {
     case BBFMM_K_INV_R: return 1.f;
+    case BBFMM_K_DIPOLE_X: return 1.f;
     case BBFMM_K_EXP: return float(log2e / a);
     case BBFMM_K_GAUSS: return float(std::sqrt(log2e) / a);
     default: return float(1.0 / a);
@@ -143,14 +149,18 @@ inline float coord_scale(int kid, double a) {
 }
 
 // ------------------------------------------------------------ gather ----
-// sig_s[i][c] = sigma[perm[i]][c] for c < r, 0 for r <= c < ld
+// sig_s[i][c] = sigma[perm[i] - base][c] for c < r, 0 for r <= c < ld and
+// for points that are not sources (perm[i] < base: the targets of a tree
+// over separate target and source sets, which come first)
 __global__ void __launch_bounds__(kThreads)
-k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, int ld, float *sig_s) {
+k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, int ld, int base,
+               float *sig_s) {
     const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (g >= n * ld) return;
     const int64_t i = g / ld;
     const int c = int(g % ld);
-    sig_s[g] = c < r ? sigma[int64_t(perm[i]) * r + c] : 0.f;
+    const int u = perm[i] - base;
+    sig_s[g] = (c < r && u >= 0) ? sigma[int64_t(u) * r + c] : 0.f;
 }
 
 // ----------------------------------------------------- up / down ----
@@ -651,6 +661,7 @@ struct M2LArgs {
     const int32_t *tables;      // slot_t[8][189] at offset 3 * 316
     int r, rc, tpt;
     int nsplit;                 // the 189 slots are split over this many workgroups
+    int tile0;                  // first tile of this launch
 };
 
 // Block index -> tile so that each XCD (blocks are dealt round-robin over
@@ -692,7 +703,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     __shared__ int16_t st[kSlots];
     const int vb = xcd_tile(blockIdx.x, gridDim.x);
     const int split = vb % g.nsplit;
-    const int tix = vb / g.nsplit;
+    const int tix = g.tile0 + vb / g.nsplit;
     const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevel &L = g.lv[tile.x];
     const int o = tile.y, start = tile.z, cnt = tile.w;
@@ -915,6 +926,7 @@ struct M2LArgsLP {
     const int32_t *tables;
     int r, rc, tpt;
     int nsplit;
+    int tile0;
 };
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -935,7 +947,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int vb = xcd_tile(blockIdx.x, gridDim.x);
     const int split = vb % g.nsplit;
-    const int tix = vb / g.nsplit;
+    const int tix = g.tile0 + vb / g.nsplit;
     const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevelLP &L = g.lv[tile.x];
     const int o = tile.y, start = tile.z, cnt = tile.w;
@@ -1128,6 +1140,258 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     }
 }
 
+// ------------------------------ M2L, 16-bit operands, parent blocks ----
+// For blocks of right-hand sides the tile kernel above gathers every source
+// block once per (target, slot) pair.  Here a workgroup takes the (up to
+// eight) children of one parent cell as its targets.  Their interaction
+// lists all lie among the 6 x 6 x 6 children of the parent's neighbours
+// (the halo; position h = k(b) - 2 k(parent) + 2 per axis), and a halo cell
+// b interacts with every child a it is not adjacent to, with transfer
+// vector t = h - 2 - o(a) (o(a): the child's offset, the octant bits).  So
+// each occupied halo cell's compressed multipoles are staged in LDS once per
+// 64-rank chunk and serve all children that see them (about seven on a full
+// grid), while the operator rows C_t come from L2 (316 operators per
+// level).  Wave w owns children 2w and 2w+1: RB 16-row blocks of the rank
+// times CB 16-column blocks of right-hand sides for each.  The sum over the
+// halo is complete inside the workgroup (one partial result).  Staging of
+// the next halo chunk is issued before the MFMAs of the current one, as in
+// the tile kernel.
+struct M2LBlockArgs {
+    const uint16_t *Mh, *Ml;   // level operands [C][r][kp] (bf16 hi / lo, or fp16 in Mh)
+    const float *Msinv;        // fp16: inverse block scales [C][r][nchunk]
+    float *Fh;                 // [C][r][kp]
+    const uint16_t *Ch, *Cl;   // operators [316][kp][kp]
+    const float *Cinv;         // fp16: operator inverse scales [316]
+    const int32_t *itab;       // [C][189]
+    const uint64_t *keys;      // level keys (child octant = key & 7)
+    const int32_t *pcb, *pce;  // children of each parent (level above)
+    const int32_t *t_slot;     // [8][316]: slot of transfer vector t for an octant, -1
+    int kp, r;
+};
+
+// compact index of t in {-3..3}^3 minus {-1..1}^3 (ascending (tx+3) + 7(ty+3) + 49(tz+3))
+__device__ inline int t_compact(int tx, int ty, int tz) {
+    const int code = (tx + 3) + 7 * (ty + 3) + 49 * (tz + 3);
+    int inner = 0;                            // codes of {-1..1}^3 below this one
+    for (int z = 2; z <= 4; ++z)
+        for (int y = 2; y <= 4; ++y)
+            for (int x = 2; x <= 4; ++x) inner += (x + 7 * y + 49 * z) < code;
+    return code - inner;
+}
+
+template <int PREC, int RB, int CB>
+__global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
+    constexpr bool X3 = PREC == BBFMM_M2L_BF16X3;
+    constexpr int COLS = 16 * CB;
+    constexpr int ldb = 64 + 8;                 // 144-byte column rows: conflict-free reads
+    constexpr int PPC = X3 ? 16 : 8;            // 16-byte pieces per column (hi + lo for X3)
+    constexpr int NB = (COLS * PPC + kThreads - 1) / kThreads;
+    constexpr int NH = 216;                     // halo positions
+    __shared__ uint4 Bstore[2][X3 ? 2 : 1][COLS * ldb / 8];
+    __shared__ float Bsc[2][COLS];
+    __shared__ int32_t hb[NH];                  // compacted: source cell
+    __shared__ uint8_t hmask[NH];               // children that interact with it
+    __shared__ int16_t htix[NH][8];             // their transfer-vector indices
+    __shared__ int wcount[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int P = xcd_tile(blockIdx.x, gridDim.x);
+    const int c0 = g.pcb[P], nchild = g.pce[P] - c0;
+    const int kp = g.kp, r = g.r;
+    const int row0 = blockIdx.y * 16 * RB;
+    const int rhs0 = blockIdx.z * COLS;
+    const int nkc = (kp + 63) / 64;
+    int oct[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) oct[i] = i < nchild ? int(g.keys[c0 + i] & 7u) : 0;
+
+    // ---- the halo: occupied positions that some child interacts with
+    int my_b = -1;
+    unsigned my_m = 0;
+    int16_t my_t[8];
+    const int hx = tid % 6, hy = (tid / 6) % 6, hz = tid / 36;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {             // unrolled: the arrays stay in registers
+        my_t[i] = -1;
+        if (tid >= NH || i >= nchild) continue;
+        const int o = oct[i];
+        const int tx = hx - 2 - (o & 1), ty = hy - 2 - ((o >> 1) & 1), tz = hz - 2 - (o >> 2);
+        if (max(abs(tx), max(abs(ty), abs(tz))) < 2) continue;         // adjacent: near field
+        const int ti = t_compact(tx, ty, tz);
+        const int slot = g.t_slot[o * kNumT + ti];
+        const int src = slot >= 0 ? g.itab[int64_t(c0 + i) * kSlots + slot] : -1;
+        if (src < 0) continue;
+        my_b = src;                           // the same cell for every child that sees it
+        my_m |= 1u << i;
+        my_t[i] = int16_t(ti);
+    }
+    const bool have = my_m != 0u;
+    const uint64_t bal = __ballot(have);
+    const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wave; ++w) off += wcount[w];
+    const int nh = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (have) {
+        const int q = off + before;
+        hb[q] = my_b;
+        hmask[q] = uint8_t(my_m);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) htix[q][i] = my_t[i];
+    }
+    __syncthreads();
+    if (row0 >= kp) return;                     // uniform: a row group past the rank
+
+    // staged piece e = tid + 256 i: column e / PPC, 16-byte piece e % PPC
+    int bpart[NB], bsub[NB], bcol[NB];
+    int64_t boff[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int e = tid + i * kThreads;
+        const int col = e / PPC, q = e % PPC;
+        bcol[i] = col;
+        bpart[i] = q >> 3;
+        bsub[i] = q & 7;
+        boff[i] = (e < COLS * PPC && rhs0 + col < r) ? int64_t(rhs0 + col) * kp + 8 * bsub[i] : -1;
+    }
+    const int scol = tid % COLS;
+    auto load_b = [&](int s, uint4 *breg, float &bscale) {
+        const int h = s / nkc, kc = s - (s / nkc) * nkc;
+        const int b = hb[h];
+        const int lim = min(64, kp - kc * 64) / 8;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const bool ok = boff[i] >= 0 && bsub[i] < lim;
+            const uint16_t *base = bpart[i] ? g.Ml : g.Mh;
+            const uint4 v = *reinterpret_cast<const uint4 *>(
+                base + (ok ? int64_t(b) * r * kp + boff[i] + kc * 64 : 0));
+            const uint32_t w = ok ? 0xffffffffu : 0u;
+            breg[i] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+        }
+        if constexpr (!X3) {
+            const bool ok = rhs0 + scol < r;
+            const float v = g.Msinv[ok ? (int64_t(b) * r + rhs0 + scol) * nkc + kc : 0];
+            bscale = ok ? v : 0.f;
+        }
+    };
+    auto store_b = [&](int buf, const uint4 *breg, float bscale) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (bcol[i] < COLS) Bstore[buf][bpart[i]][(bcol[i] * ldb + 8 * bsub[i]) / 8] = breg[i];
+        if constexpr (!X3) if (tid < COLS) Bsc[buf][scol] = bscale;
+    };
+
+    v4f acc[2][RB][CB];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[u][rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = nh * nkc;
+    uint4 breg[NB];
+    float bscale = 0.f;
+    if (nsteps > 0) {
+        load_b(0, breg, bscale);
+        store_b(0, breg, bscale);
+    }
+    __syncthreads();
+    const int bbase = ((lane & 15) * ldb + 8 * (lane >> 4)) / 8;
+    for (int s = 0; s < nsteps; ++s) {
+        const bool more = s + 1 < nsteps;
+        if (more) load_b(s + 1, breg, bscale);
+        const int h = s / nkc, kc = s - (s / nkc) * nkc;
+        const int nks = min(64, kp - kc * 64) / 32;           // 32-deep blocks with rank
+        const unsigned hm = hmask[h];
+        const uint4 *Bh = Bstore[s & 1][0];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = 2 * wave + u;
+            if (!((hm >> i) & 1u)) continue;                    // wave-uniform
+            const int ti = htix[h][i];
+            const int64_t cbase = int64_t(ti) * kp * kp + kc * 64 + 8 * (lane >> 4);
+            v4f part[RB][CB];
+            if constexpr (!X3) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) part[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                if (ks >= nks) break;
+                uint4 ah[RB], al[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const int row = row0 + rb * 16 + (lane & 15);
+                    const bool ok = row < kp;
+                    const int64_t o = ok ? cbase + int64_t(row) * kp + 32 * ks : 0;
+                    const uint32_t w = ok ? 0xffffffffu : 0u;
+                    uint4 v = *reinterpret_cast<const uint4 *>(g.Ch + o);
+                    ah[rb] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+                    if constexpr (X3) {
+                        v = *reinterpret_cast<const uint4 *>(g.Cl + o);
+                        al[rb] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+                    }
+                }
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const uint4 braw = Bh[bbase + (cb * 16 * ldb + 32 * ks) / 8];
+                    if constexpr (X3) {
+                        const v8bf bh = __builtin_bit_cast(v8bf, braw);
+                        const v8bf bl = __builtin_bit_cast(
+                            v8bf, Bstore[s & 1][1][bbase + (cb * 16 * ldb + 32 * ks) / 8]);
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) {
+                            const v8bf a_h = __builtin_bit_cast(v8bf, ah[rb]);
+                            const v8bf a_l = __builtin_bit_cast(v8bf, al[rb]);
+                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[u][rb][cb], 0, 0, 0);
+                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[u][rb][cb], 0, 0, 0);
+                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[u][rb][cb], 0, 0, 0);
+                        }
+                    } else {
+                        const v8h b16 = __builtin_bit_cast(v8h, braw);
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb)
+                            part[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(v8h, ah[rb]), b16, part[rb][cb], 0, 0, 0);
+                    }
+                }
+            }
+            if constexpr (!X3) {
+                const float cinv = g.Cinv[ti];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const float f = Bsc[s & 1][cb * 16 + (lane & 15)] * cinv;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) acc[u][rb][cb] += part[rb][cb] * f;
+                }
+            }
+        }
+        if (more) store_b((s + 1) & 1, breg, bscale);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 2 * wave + u;
+        if (i >= nchild) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int c = rhs0 + cb * 16 + (lane & 15);
+            if (c >= r) continue;
+            float *dst = g.Fh + (int64_t(c0 + i) * r + c) * kp + 4 * (lane >> 4);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int row = row0 + rb * 16;
+                if (row < kp)
+                    *reinterpret_cast<float4 *>(dst + row) =
+                        make_float4(acc[u][rb][cb][0], acc[u][rb][cb][1], acc[u][rb][cb][2], acc[u][rb][cb][3]);
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------- L2P + P2P ----
 // One wave per work item (leaf a, first target t0, log2 S): the wave holds
 // T = 64 / S targets, each spread over S consecutive lanes ("sub-lanes").
@@ -1178,9 +1442,9 @@ __device__ inline void p2p_records(const float4 *sp, const float (*ss)[RC > 1 ? 
 
 template <int KID, int RC>
 __global__ void __launch_bounds__(64)
-k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-      const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
-      const int32_t *work, int nwork, const float *sig_s, int r, float cs,
+k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf, const int32_t *pe,
+      const int32_t *te, const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys,
+      const int32_t *perm, const int32_t *work, int nwork, const float *sig_s, int r, float cs,
       const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
     constexpr int CAP = P2PCap<RC>::value;
     __shared__ float4 sp[CAP];                        // x, y, z, sigma of the first rhs
@@ -1196,7 +1460,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         const int rhs0 = blockIdx.y * RC;
         const int nr = min(RC, r - rhs0);
         const int i = t0 + (lane >> lgS);
-        const bool valid = i < pe[a];
+        const bool valid = i < te[a];
         const float x = valid ? xs[i] : 0.f, y = valid ? ys[i] : 0.f, z = valid ? zs[i] : 0.f;
         const float xc = x * cs, yc = y * cs, zc = z * cs;   // kernel coordinates
         float acc[RC];
@@ -1213,7 +1477,7 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
             int sb = 0, cnt = 0;
             if (qc + lane < q1) {
                 const int b = nbr_idx[qc + lane];
-                sb = pb[b];
+                sb = sb_leaf[b];
                 cnt = pe[b] - sb;
             }
             int inc = cnt;
@@ -1333,9 +1597,9 @@ struct P2PMfmaCap {   // source records per LDS pass (coordinates + NCB x 16 sig
 
 template <int KID, int NCB, int NRB>
 __global__ void __launch_bounds__(64)
-k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-           const int32_t *nbr_off, const int32_t *nbr_idx, const uint64_t *keys, const int32_t *perm,
-           const int32_t *work, const float *sig_s, int ld, int r, float cs,
+k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf,
+           const int32_t *pe, const int32_t *te, const int32_t *nbr_off, const int32_t *nbr_idx,
+           const uint64_t *keys, const int32_t *perm, const int32_t *work, const float *sig_s, int ld, int r, float cs,
            const float *FL, int mp, Geo geo, ChebConst cc, float *phi) {
     constexpr int CW = 16 * NCB;            // columns of this wave
     constexpr int SST = CW == 16 ? 16 : CW + 16;   // = 16 mod 32: rows k, k+1 on disjoint banks
@@ -1353,7 +1617,7 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
     float (*Ls)[16][3 * kMaxOrder] = reinterpret_cast<float (*)[16][3 * kMaxOrder]>(ss);
     const int lane = threadIdx.x, row = lane & 15, kq = lane >> 4;
     const int a = work[2 * blockIdx.x], t0 = work[2 * blockIdx.x + 1];
-    const int tend = pe[a];
+    const int tend = te[a];
     const int col0 = blockIdx.y * CW;
     float tx[NRB], ty[NRB], tz[NRB];
 #pragma unroll
@@ -1442,7 +1706,7 @@ k_p2p_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
         int cnt_all = 0;
         while (q < q1 && cnt_all < CAP) {
             const int b = nbr_idx[q];
-            const int sb = pb[b] + off, cnt = min(pe[b] - sb, CAP - cnt_all);
+            const int sb = sb_leaf[b] + off, cnt = min(pe[b] - sb, CAP - cnt_all);
             for (int e = lane; e < cnt; e += 64) sidx[cnt_all + e] = sb + e;
             cnt_all += cnt;
             if (sb + cnt == pe[b]) { ++q; off = 0; } else { off += cnt; }
@@ -1568,8 +1832,8 @@ __device__ inline float l2p_sum(const float *f, const float (*l)[N]) {
 template <int N>
 __global__ void __launch_bounds__(kThreads)
 k_l2p(const float *xs, const float *ys, const float *zs, const int32_t *pleaf, const uint64_t *keys,
-      const int32_t *perm, int64_t npts, int r, const float *FL, int mp, Geo geo, ChebConst cc,
-      float *phi) {
+      const int32_t *perm, int64_t npts, int64_t n_out, int r, const float *FL, int mp, Geo geo,
+      ChebConst cc, float *phi) {
     constexpr int m = N * N * N, RS = m | 1;          // LDS row stride (odd)
     __shared__ float fs[kL2PLdsFloats];
     const int64_t i0 = int64_t(blockIdx.x) * kThreads;
@@ -1603,7 +1867,7 @@ k_l2p(const float *xs, const float *ys, const float *zs, const int32_t *pleaf, c
         } else if (active) {
             sacc = l2p_sum<N>(FL + (int64_t(a) * r + c) * mp, l);
         }
-        if (active) phi[int64_t(perm[i]) * r + c] += sacc;
+        if (active && perm[i] < n_out) phi[int64_t(perm[i]) * r + c] += sacc;   // targets only
     }
 }
 
@@ -1671,9 +1935,16 @@ struct Plan {
     DBuf<float> M[kMaxLevels], Mh[kMaxLevels], Fh[kMaxLevels], F[kMaxLevels];
     DBuf<uint16_t> Mh16[kMaxLevels], Ml16[kMaxLevels];   // 16-bit M2L operand formats
     DBuf<float> Msinv[kMaxLevels];                       // fp16 block scales
+    DBuf<float2> Mc[kMaxLevels], Fc[kMaxLevels];         // FFT M2L: spectra of M and F
     DBuf<int32_t> tiles;                // all M2L tiles of all levels
     DBuf<uint32_t> masks;               // per tile: slots in which some target has a source
     int ntiles = 0, max_kp = 0;
+    int tile_off[kMaxLevels + 1] = {0};  // first tile of each level (levels >= 2)
+    // per-level M2L schedule: the upward chain on `up`, one event per level
+    bool m2l_early = false;
+    bool m2l_block = false;             // 16-bit M2L by parent blocks (k_m2l_blk), no slot split
+    hipStream_t up = nullptr;
+    hipEvent_t lev_ev[kMaxLevels] = {};
     DBuf<int32_t> work;
     int nwork = 0;
     int64_t ws_bytes = 0;
@@ -1710,6 +1981,8 @@ struct Plan {
         destroy_event(fork);
         destroy_event(join);
         release_side_stream(side);
+        for (hipEvent_t e : lev_ev) destroy_event(e);
+        release_side_stream(up);
         for (hipEvent_t e : events) destroy_event(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         destroy_stream(cap_stream);
@@ -1732,6 +2005,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.p2p_waves >= 0, "p2p_waves must be >= 0");
     BB_REQUIRE(op.m2l_occupancy >= 0 && op.m2l_occupancy <= 4, "m2l_occupancy must be in [0, 4]");
     BB_REQUIRE(op.m2l_layout >= 0 && op.m2l_layout <= 2, "m2l_layout must be 0, 1 or 2");
+    BB_REQUIRE(op.m2l_schedule >= 0 && op.m2l_schedule <= 2, "m2l_schedule must be 0, 1 or 2");
+    BB_REQUIRE(op.m2l_block >= 0 && op.m2l_block <= 2, "m2l_block must be 0, 1 or 2");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -1761,7 +2036,13 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->max_kp = std::max(p->max_kp, kp);
         p->M[lvl].alloc(C * r * mp);
         p->F[lvl].alloc(C * r * mp);
-        if (o->precision == BBFMM_M2L_FP32) {
+        if (o->precision == BBFMM_M2L_FFT) {
+            const int64_t Q = fft_freqs(o->n);
+            p->Mc[lvl].alloc(C * r * Q);
+            p->Fc[lvl].alloc(C * r * Q);
+            ws += p->Mc[lvl].bytes() + p->Fc[lvl].bytes() + p->M[lvl].bytes() + p->F[lvl].bytes();
+            continue;            // no compressed operands, no M2L tiles
+        } else if (o->precision == BBFMM_M2L_FP32) {
             p->Mh[lvl].alloc(C * r * kp);
             ws += p->Mh[lvl].bytes();
         } else {
@@ -1780,6 +2061,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         // within the octant), interleaved over the octants run by run, so
         // that consecutive tiles -- which the launch deals to one XCD --
         // cover one region of space and share their sources in that L2
+        p->tile_off[lvl] = int(tl.size() / 4);
         const int *oo = t->lv[lvl].oct_off;
         int nrun = 0;
         for (int oc = 0; oc < 8; ++oc) nrun = std::max(nrun, int(ceil_div(oo[oc + 1] - oo[oc], p->tpt)));
@@ -1794,15 +2076,22 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             }
     }
     p->ntiles = int(tl.size() / 4);
+    for (int lvl = std::max(L + 1, 2); lvl <= kMaxLevels; ++lvl) p->tile_off[lvl] = p->ntiles;
+    // 16-bit M2L for blocks of right-hand sides: parent blocks by default
+    // from 16 columns on
+    p->m2l_block = (o->precision == BBFMM_M2L_BF16X3 || o->precision == BBFMM_M2L_FP16_SCALED) &&
+                   (op.m2l_block == 0 ? r >= 16 : op.m2l_block == 2);
     // split the slots until the launch has about m2l_min_waves workgroups per CU
-    if (op.m2l_split > 0) {
+    if (p->m2l_block) {
+        p->nsplit = 1;                  // each block sums its whole halo
+    } else if (op.m2l_split > 0) {
         p->nsplit = op.m2l_split;
     } else {
         const int target = op.m2l_min_waves > 0 ? op.m2l_min_waves : 4;
         const int64_t wgs = int64_t(p->ntiles) * ceil_div(p->max_kp, 64) * ceil_div(r, p->rc_m2l);
         while (p->nsplit < 4 && wgs * p->nsplit < int64_t(target) * 256) p->nsplit *= 2;
     }
-    for (int lvl = 2; lvl <= L; ++lvl) {
+    for (int lvl = 2; lvl <= L && o->precision != BBFMM_M2L_FFT; ++lvl) {
         const int64_t C = t->lv[lvl].C;
         p->Fh[lvl].alloc(int64_t(p->nsplit) * C * r * o->lv[lvl].set->kp);
         ws += p->Fh[lvl].bytes();
@@ -1826,7 +2115,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         // MFMA near field: one wave per (leaf, up to 64 consecutive
         // targets), grouped by the number of 16-row blocks they need
         const LevelData &leaf = t->lv[L];
-        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_pe_h;
+        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_te_h;   // targets of a leaf
         std::vector<int32_t> &w = p->h_work;
         for (int nrb = 1; nrb <= 4; ++nrb) {
             p->mfma_off[nrb - 1] = int(w.size() / 2);
@@ -1847,7 +2136,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         // most 64 points take one wave with 64 / next_pow2(count) sub-lanes
         // per target
         const LevelData &leaf = t->lv[L];
-        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_pe_h;
+        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_te_h;   // targets of a leaf
         std::vector<int32_t> &w = p->h_work;
         for (int a = 0; a < leaf.C; ++a) {
             const int cnt = he[a] - hb[a];
@@ -1896,6 +2185,13 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->fork = make_event(hipEventDisableTiming);
         p->join = make_event(hipEventDisableTiming);
     }
+    // per-level M2L schedule (default on with at least two M2L levels)
+    p->m2l_early = !transient && L >= 3 && o->precision != BBFMM_M2L_FFT &&
+                   (op.m2l_schedule == 0 || op.m2l_schedule == 2);
+    if (p->m2l_early) {
+        p->up = acquire_side_stream();
+        for (int lvl = 2; lvl <= L; ++lvl) p->lev_ev[lvl] = make_event(hipEventDisableTiming);
+    }
     p->ws_bytes = ws;
     if (!transient) {
         p->done = make_event(hipEventDisableTiming);
@@ -1915,6 +2211,8 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->p2p_waves = p->p2p_waves;
     out->m2l_occupancy = p->m2l_occupancy;
     out->m2l_layout = p->m2l_layout;
+    out->m2l_schedule = p->m2l_early ? 2 : 1;
+    out->m2l_block = p->m2l_block ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -1923,9 +2221,11 @@ namespace {
 
 // per execution: the stage boundaries on the caller's stream, then (the
 // overlapped schedule) P2P start / end on the side stream and the point
-// after the join where L2P starts
-constexpr int kEv = BBFMM_NUM_STAGES + 1 + 3;
+// after the join where L2P starts, then (the per-level M2L schedule) the
+// start and end of the upward chain on its own stream
+constexpr int kEv = BBFMM_NUM_STAGES + 1 + 5;
 constexpr int kEvSideBeg = BBFMM_NUM_STAGES + 1, kEvSideEnd = kEvSideBeg + 1, kEvJoined = kEvSideBeg + 2;
+constexpr int kEvUpBeg = kEvSideBeg + 3, kEvUpEnd = kEvSideBeg + 4;
 
 // fold the oldest pending execution's stage times into the totals
 void harvest_one(Plan &p) {
@@ -1934,7 +2234,11 @@ void harvest_one(Plan &p) {
     BB_HIP(hipEventSynchronize(ev[BBFMM_NUM_STAGES]));
     for (int st = 0; st < BBFMM_NUM_STAGES; ++st) {
         float ms = 0.f;
-        if (p.overlap && st == BBFMM_STAGE_P2P) {
+        if (p.m2l_early && st == BBFMM_STAGE_M2M) {
+            BB_HIP(hipEventElapsedTime(&ms, ev[kEvUpBeg], ev[kEvUpEnd]));
+        } else if (p.m2l_early && st == BBFMM_STAGE_M2L) {
+            BB_HIP(hipEventElapsedTime(&ms, ev[BBFMM_STAGE_M2L], ev[BBFMM_STAGE_DOWN]));
+        } else if (p.overlap && st == BBFMM_STAGE_P2P) {
             // near field on the side stream + L2P after the join
             float l2p = 0.f;
             BB_HIP(hipEventElapsedTime(&ms, ev[kEvSideBeg], ev[kEvSideEnd]));
@@ -1962,9 +2266,9 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
             dim3 g(unsigned(nw), unsigned(ceil_div(p.r, 16 * p.ncb_p2p)));
             const int32_t *wk = p.work.p + 2 * int64_t(w0);
 #define BB_P2PM(NCB, NRB)                                                                     \
-            k_p2p_mfma<KID, NCB, NRB><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p,        \
-                leaf.pe.p, t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p, wk, p.sig_s.p,       \
-                p.ld_s, int(p.r), cs, FL, p.ops->mp, geo, p.ops->cheb, phi)
+            k_p2p_mfma<KID, NCB, NRB><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(),    \
+                leaf.pe.p, t.tgt_end(), t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p, wk,     \
+                p.sig_s.p, p.ld_s, int(p.r), cs, FL, p.ops->mp, geo, p.ops->cheb, phi)
 #define BB_P2PM_R(NCB)                                                                        \
             switch (nrb) {                                                                    \
             case 1: BB_P2PM(NCB, 1); break;                                                   \
@@ -1986,10 +2290,10 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
     const int nwg = p.p2p_waves > 0 ? std::min(p.p2p_waves, p.nwork) : p.nwork;
     dim3 g(unsigned(nwg), unsigned(ceil_div(p.r, p.rc_p2p)));
 #define BB_P2P(RCV)                                                                          \
-    k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p,            \
-                                     t.nbr_off.p, t.nbr_idx.p, leaf.keys.p, t.perm.p,         \
-                                     p.work.p, p.nwork, p.sig_s.p, int(p.r), cs, FL,         \
-                                     p.ops->mp, geo, p.ops->cheb, phi)
+    k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p,        \
+                                     t.tgt_end(), t.nbr_off.p, t.nbr_idx.p, leaf.keys.p,      \
+                                     t.perm.p, p.work.p, p.nwork, p.sig_s.p, int(p.r), cs,   \
+                                     FL, p.ops->mp, geo, p.ops->cheb, phi)
     switch (p.rc_p2p) {
     case 1: BB_P2P(1); break;
     case 2: BB_P2P(2); break;
@@ -2154,7 +2458,8 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
     };
 
     mark(BBFMM_STAGE_GATHER);
-    k_gather_sigma<<<grid(t.n * p.ld_s), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.ld_s, p.sig_s.p);
+    k_gather_sigma<<<grid(t.n * p.ld_s), kThreads, 0, s>>>(sigma, t.perm.p, t.n, r, p.ld_s,
+                                                           int(t.n_targets), p.sig_s.p);
     BB_LAUNCH_CHECK();
     const float *FL = nullptr;
     const int n = o.n, mp = o.mp;
@@ -2163,6 +2468,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         case BBFMM_K_INV_R: launch_p2p<BBFMM_K_INV_R>(p, fl, geo, phi, st); break;
         case BBFMM_K_EXP: launch_p2p<BBFMM_K_EXP>(p, fl, geo, phi, st); break;
         case BBFMM_K_GAUSS: launch_p2p<BBFMM_K_GAUSS>(p, fl, geo, phi, st); break;
+        case BBFMM_K_DIPOLE_X: launch_p2p<BBFMM_K_DIPOLE_X>(p, fl, geo, phi, st); break;
         default: launch_p2p<BBFMM_K_POLY_TEST>(p, fl, geo, phi, st); break;
         }
     };
@@ -2180,7 +2486,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         // blocks of right-hand sides: P2M on MFMA (sigma padded to whole column blocks)
         const LevelData &leaf = t.lv[L];
         dim3 g(leaf.C, unsigned(p.ld_s / (16 * p.ncb_p2p)));
-#define BB_P2MM(NN, NCB) k_p2m_mfma<NN, NCB><<<g, kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, \
+#define BB_P2MM(NN, NCB) k_p2m_mfma<NN, NCB><<<g, kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), \
             leaf.pe.p, leaf.keys.p, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p)
 #define BB_P2MN(NN) case NN:                                                                  \
             if (p.ncb_p2p == 1) BB_P2MM(NN, 1);                                               \
@@ -2197,90 +2503,165 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         const LevelData &leaf = t.lv[L];
         switch (n) {
 #define BB_P2M(NN) case NN: k_p2m<NN><<<dim3(unsigned(ceil_div(leaf.C, 64 / ((NN) * (NN)))), unsigned(r)), \
-            64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, leaf.pb.p, leaf.pe.p, leaf.keys.p, int(leaf.C), geo, \
-            o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
+            64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p, leaf.keys.p, int(leaf.C), \
+            geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
         BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
 #undef BB_P2M
         }
         BB_LAUNCH_CHECK();
     }
-    auto compress = [&](int lvl) {
+    auto compress = [&](int lvl, hipStream_t st) {
+        if (o.precision == BBFMM_M2L_FFT) {     // the multipoles' spectra instead
+            fft_forward(n, p.M[lvl].p, mp, int64_t(t.lv[lvl].C) * r, p.Mc[lvl].p, st);
+            return;
+        }
         const OpSet &set = *o.lv[lvl].set;
         const int64_t R = int64_t(t.lv[lvl].C) * r;
         const int nchunk = int(ceil_div(set.kp, 64));
         dim3 g(unsigned(ceil_div(R, 64)), unsigned(nchunk));
         if (o.precision == BBFMM_M2L_FP32)
-            k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+            k_gemm_nt<kOutF32><<<g, kThreads, 0, st>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
                                                      p.Mh[lvl].p, set.kp, R, set.kp, mp, 1.f, 0.f,
                                                      nullptr, nullptr, nullptr, 0);
         else if (o.precision == BBFMM_M2L_BF16X3)
-            k_gemm_nt<kOutBF16X3><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+            k_gemm_nt<kOutBF16X3><<<g, kThreads, 0, st>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
                                                         nullptr, set.kp, R, set.kp, mp, 1.f, 0.f,
                                                         p.Mh16[lvl].p, p.Ml16[lvl].p, nullptr, 0);
         else
-            k_gemm_nt<kOutF16S><<<g, kThreads, 0, s>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
+            k_gemm_nt<kOutF16S><<<g, kThreads, 0, st>>>(p.M[lvl].p, mp, 1, 0, set.VT32.p, mp,
                                                       nullptr, set.kp, R, set.kp, mp, 1.f, 0.f,
                                                       p.Mh16[lvl].p, nullptr, p.Msinv[lvl].p,
                                                       nchunk);
         BB_LAUNCH_CHECK();
     };
-    if (L >= 2) compress(L);
-    mark(BBFMM_STAGE_M2M);
-    for (int lvl = L - 1; lvl >= 2; --lvl) {
+    auto m2m = [&](int lvl, hipStream_t st) {
         const LevelData &lv = t.lv[lvl], &ch = t.lv[lvl + 1];
         dim3 g(lv.C, r);
         switch (n) {
-#define BB_M2M(NN) case NN: k_m2m<NN><<<g, 64, 0, s>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p, \
+#define BB_M2M(NN) case NN: k_m2m<NN><<<g, 64, 0, st>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p, \
             o.cheb, r, mp, p.M[lvl].p); break;
         BB_M2M(2) BB_M2M(3) BB_M2M(4) BB_M2M(5) BB_M2M(6) BB_M2M(7) BB_M2M(8)
 #undef BB_M2M
         }
         BB_LAUNCH_CHECK();
-        compress(lvl);
-    }
-    mark(BBFMM_STAGE_M2L);
-    if (L >= 2 && o.precision != BBFMM_M2L_FP32) {
-        M2LArgsLP g{};
-        for (int lvl = 2; lvl <= L; ++lvl) {
-            const OpSet &set = *o.lv[lvl].set;
-            g.lv[lvl] = M2LLevelLP{p.Mh16[lvl].p, p.Ml16[lvl].p, p.Msinv[lvl].p, p.Fh[lvl].p,
-                                   o.precision == BBFMM_M2L_BF16X3 ? set.Chi.p : set.C16.p,
-                                   set.Clo.p, set.Cinv.p, t.lv[lvl].itab.p,
-                                   t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
+    };
+    // one M2L launch over the tiles of levels lo..hi
+    auto m2l = [&](int lo, int hi, hipStream_t st) {
+        if (p.m2l_block) {
+            for (int lvl = lo; lvl <= hi; ++lvl) {
+                const OpSet &set = *o.lv[lvl].set;
+                const int kp = set.kp;
+                M2LBlockArgs g{p.Mh16[lvl].p, p.Ml16[lvl].p, p.Msinv[lvl].p, p.Fh[lvl].p,
+                               o.precision == BBFMM_M2L_BF16X3 ? set.Chi.p : set.C16.p, set.Clo.p,
+                               set.Cinv.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p, t.lv[lvl - 1].cb.p,
+                               t.lv[lvl - 1].ce.p, t.tables.p + 3 * kNumT + 8 * kSlots, kp, r};
+                const int CBv = r >= 48 ? 4 : (r > 16 ? 2 : 1);
+                const int RBv = (kp <= 32 || CBv == 4) ? 2 : 4;
+                dim3 gr(unsigned(t.lv[lvl - 1].C), unsigned(ceil_div(kp, 16 * RBv)),
+                        unsigned(ceil_div(r, 16 * CBv)));
+#define BB_BLK(PR, RBc, CBc) k_m2l_blk<PR, RBc, CBc><<<gr, kThreads, p.m2l_pad_lds, st>>>(g)
+#define BB_BLK_P(PR)                                                                          \
+                if (RBv == 2 && CBv == 1) BB_BLK(PR, 2, 1);                                   \
+                else if (RBv == 2 && CBv == 2) BB_BLK(PR, 2, 2);                              \
+                else if (RBv == 2) BB_BLK(PR, 2, 4);                                          \
+                else if (CBv == 1) BB_BLK(PR, 4, 1);                                          \
+                else BB_BLK(PR, 4, 2);
+                if (o.precision == BBFMM_M2L_BF16X3) {
+                    BB_BLK_P(BBFMM_M2L_BF16X3)
+                } else {
+                    BB_BLK_P(BBFMM_M2L_FP16_SCALED)
+                }
+#undef BB_BLK_P
+#undef BB_BLK
+                BB_LAUNCH_CHECK();
+            }
+            return;
         }
-        g.tiles = p.tiles.p;
-        g.masks = p.masks.p;
-        g.tables = t.tables.p;
-        g.r = r;
-        g.rc = p.rc_m2l;
-        g.tpt = p.tpt;
-        g.nsplit = p.nsplit;
-        dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
-        if (o.precision == BBFMM_M2L_BF16X3)
-            k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
-        else
-            k_m2l_lp<BBFMM_M2L_FP16_SCALED><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
-        BB_LAUNCH_CHECK();
-    } else if (L >= 2) {
-        M2LArgs g{};
-        for (int lvl = 2; lvl <= L; ++lvl) {
-            const OpSet &set = *o.lv[lvl].set;
-            g.lv[lvl] = M2LLevel{p.Mh[lvl].p, p.Fh[lvl].p, set.C32.p, t.lv[lvl].itab.p,
-                                 t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
+        if (o.precision == BBFMM_M2L_FFT) {
+            for (int lvl = lo; lvl <= hi; ++lvl)
+                fft_m2l(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p,
+                        t.tables.p + 3 * kNumT, t.lv[lvl].C, r, p.Fc[lvl].p, st);
+            return;
         }
-        g.tiles = p.tiles.p;
-        g.masks = p.masks.p;
-        g.tables = t.tables.p;
-        g.r = r;
-        g.rc = p.rc_m2l;
-        g.tpt = p.tpt;
-        g.nsplit = p.nsplit;
-        dim3 gr(p.ntiles * p.nsplit, unsigned(ceil_div(p.max_kp, 64)), unsigned(ceil_div(r, p.rc_m2l)));
-        if (p.m2l_layout == 2)
-            k_m2l<2><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
-        else
-            k_m2l<4><<<gr, kThreads, p.m2l_pad_lds, s>>>(g);
+        const int t0 = p.tile_off[lo], t1 = p.tile_off[hi + 1];
+        if (t1 == t0) return;
+        int kpmax = 0;
+        for (int lvl = lo; lvl <= hi; ++lvl) kpmax = std::max(kpmax, o.lv[lvl].set->kp);
+        dim3 gr(unsigned((t1 - t0) * p.nsplit), unsigned(ceil_div(kpmax, 64)),
+                unsigned(ceil_div(r, p.rc_m2l)));
+        if (o.precision != BBFMM_M2L_FP32) {
+            M2LArgsLP g{};
+            for (int lvl = lo; lvl <= hi; ++lvl) {
+                const OpSet &set = *o.lv[lvl].set;
+                g.lv[lvl] = M2LLevelLP{p.Mh16[lvl].p, p.Ml16[lvl].p, p.Msinv[lvl].p, p.Fh[lvl].p,
+                                       o.precision == BBFMM_M2L_BF16X3 ? set.Chi.p : set.C16.p,
+                                       set.Clo.p, set.Cinv.p, t.lv[lvl].itab.p,
+                                       t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
+            }
+            g.tiles = p.tiles.p;
+            g.masks = p.masks.p;
+            g.tables = t.tables.p;
+            g.r = r;
+            g.rc = p.rc_m2l;
+            g.tpt = p.tpt;
+            g.nsplit = p.nsplit;
+            g.tile0 = t0;
+            if (o.precision == BBFMM_M2L_BF16X3)
+                k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+            else
+                k_m2l_lp<BBFMM_M2L_FP16_SCALED><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+        } else {
+            M2LArgs g{};
+            for (int lvl = lo; lvl <= hi; ++lvl) {
+                const OpSet &set = *o.lv[lvl].set;
+                g.lv[lvl] = M2LLevel{p.Mh[lvl].p, p.Fh[lvl].p, set.C32.p, t.lv[lvl].itab.p,
+                                     t.lv[lvl].oct_cells.p, set.kp, int64_t(t.lv[lvl].C) * r};
+            }
+            g.tiles = p.tiles.p;
+            g.masks = p.masks.p;
+            g.tables = t.tables.p;
+            g.r = r;
+            g.rc = p.rc_m2l;
+            g.tpt = p.tpt;
+            g.nsplit = p.nsplit;
+            g.tile0 = t0;
+            if (p.m2l_layout == 2)
+                k_m2l<2><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+            else
+                k_m2l<4><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+        }
         BB_LAUNCH_CHECK();
+    };
+    if (L >= 2) compress(L, s);
+    if (!p.m2l_early) {
+        mark(BBFMM_STAGE_M2M);
+        for (int lvl = L - 1; lvl >= 2; --lvl) {
+            m2m(lvl, s);
+            compress(lvl, s);
+        }
+        mark(BBFMM_STAGE_M2L);
+        if (L >= 2) m2l(2, L, s);
+    } else {
+        // each level's M2L starts as soon as its compressed multipoles
+        // exist: the leaf level's at once on `s`, while the upward chain
+        // (M2M + compression of levels L-1..2) runs on the plan's `up`
+        // stream and hands each finished level to `s` with an event
+        mark(BBFMM_STAGE_M2M);
+        BB_HIP(hipEventRecord(p.lev_ev[L], s));
+        BB_HIP(hipStreamWaitEvent(p.up, p.lev_ev[L], 0));
+        if (ev) BB_HIP(hipEventRecord(ev[kEvUpBeg], p.up));
+        for (int lvl = L - 1; lvl >= 2; --lvl) {
+            m2m(lvl, p.up);
+            compress(lvl, p.up);
+            BB_HIP(hipEventRecord(p.lev_ev[lvl], p.up));
+        }
+        if (ev) BB_HIP(hipEventRecord(ev[kEvUpEnd], p.up));
+        mark(BBFMM_STAGE_M2L);
+        m2l(L, L, s);
+        for (int lvl = L - 1; lvl >= 2; --lvl) {
+            BB_HIP(hipStreamWaitEvent(s, p.lev_ev[lvl], 0));
+            m2l(lvl, lvl, s);
+        }
     }
     mark(BBFMM_STAGE_DOWN);
     for (int lvl = 2; lvl <= L; ++lvl) {
@@ -2297,6 +2678,10 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             BB_LAUNCH_CHECK();
         }
         const int64_t R = int64_t(lv.C) * r;
+        if (o.precision == BBFMM_M2L_FFT) {
+            fft_inverse(n, p.Fc[lvl].p, R, float(o.lv[lvl].scale), lvl > 2, mp, p.F[lvl].p, s);
+            continue;
+        }
         dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
         k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp,
                                                  set.U32.p, set.kp, p.F[lvl].p, mp, R, mp, set.kp,
@@ -2312,7 +2697,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         const LevelData &leaf = t.lv[L];
         switch (n) {
 #define BB_L2P(NN) case NN: k_l2p<NN><<<grid(t.n), kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, p.pleaf.p, \
-            leaf.keys.p, t.perm.p, t.n, r, FL, mp, geo, o.cheb, phi); break;
+            leaf.keys.p, t.perm.p, t.n, t.n_out(), r, FL, mp, geo, o.cheb, phi); break;
         BB_L2P(2) BB_L2P(3) BB_L2P(4) BB_L2P(5) BB_L2P(6) BB_L2P(7) BB_L2P(8)
 #undef BB_L2P
         }

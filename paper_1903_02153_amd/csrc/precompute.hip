@@ -28,6 +28,7 @@ __device__ inline double kernel_eval_f64(int kid, double a, double dx, double dy
     case BBFMM_K_INV_R: return r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
     case BBFMM_K_EXP: return exp(-sqrt(r2) / a);
     case BBFMM_K_GAUSS: return exp(-r2 / (a * a));
+    case BBFMM_K_DIPOLE_X: return r2 > 0.0 ? dx / (r2 * sqrt(r2)) : 0.0;
     case BBFMM_K_POLY_TEST: {
         const double u[3] = {dx / a, dy / a, dz / a};
         double p = 1.0;
@@ -39,12 +40,14 @@ __device__ inline double kernel_eval_f64(int kid, double a, double dx, double dy
     }
 }
 
-// Chebyshev nodes, barycentric weights and the two 1D child maps
-// T[o][i][j] = l_i((2o-1)/2 + s_j/2) (the parent basis at child nodes).
-__global__ void k_cheb(int n, double *out) {
+// Interpolation nodes (Chebyshev cos((2m+1) pi / 2n), or equally spaced
+// -1 + 2m/(n-1) when `uniform`), barycentric weights and the two 1D child
+// maps T[o][i][j] = l_i((2o-1)/2 + s_j/2) (the parent basis at child nodes).
+__global__ void k_cheb(int n, int uniform, double *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s[kMaxOrder];
-    for (int m = 0; m < n; ++m) s[m] = cos((2.0 * m + 1.0) * M_PI / (2.0 * n));
+    for (int m = 0; m < n; ++m)
+        s[m] = uniform ? -1.0 + 2.0 * m / (n - 1) : cos((2.0 * m + 1.0) * M_PI / (2.0 * n));
     for (int m = 0; m < n; ++m) {
         double w = 1.0;
         for (int k = 0; k < n; ++k)
@@ -358,8 +361,27 @@ void gram_eig(DBuf<double> &G, DBuf<double> &Q, int m, double eps, DBuf<int32_t>
     count = hc;
 }
 
-// Build one operator set from sampled K (316 x m x m, FP64).
-void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, hipStream_t s) {
+// C_t = sym * C_{315-t}^T for the upper half of the transfer vectors: the
+// compact index of -t is 315 minus that of t (the 316 vectors sorted by an
+// index that negation reverses)
+__global__ void __launch_bounds__(kThreads)
+k_mirror_operators(double *C, int k, double sym) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t half = int64_t(kNumT / 2) * k * k;
+    if (g >= half) return;
+    const int t = int(g / (int64_t(k) * k));
+    const int ij = int(g % (int64_t(k) * k)), i = ij / k, j = ij % k;
+    C[int64_t(kNumT - 1 - t) * k * k + int64_t(j) * k + i] = sym * C[g];
+}
+
+// Build one operator set from sampled K (316 x m x m, FP64).  sym: +1 for
+// a symmetric kernel, -1 for a skew-symmetric one, 0 otherwise.  With
+// symmetry K_{-t} = sym K_t^T (Section 2.5), so the thin matrix is the fat
+// one transposed up to a permutation of blocks and a sign: its Gram matrix
+// and singular values are the fat one's, V = U, and only the operators of
+// the first 158 transfer vectors are formed; the rest are their (signed)
+// transposes.
+void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, int sym, hipStream_t s) {
     if (eps == 0.0) {
         set.k = m;
         set.U64.alloc(int64_t(m) * m);
@@ -370,35 +392,47 @@ void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, hipStream_t s)
         set.C64 = std::move(K);
         return;
     }
-    DBuf<double> Gf(int64_t(m) * m), Gt(int64_t(m) * m);
+    DBuf<double> Qf, Qt;
+    DBuf<int32_t> of, ot;
+    int kf = 0, kt = 0;
     {
+        DBuf<double> Gf(int64_t(m) * m);
         GemmArgs g{m, m, m, kNumT, 1,
                    K.p, int64_t(m) * m, m, 1,          // A_b = K_t
                    K.p, int64_t(m) * m, 1, m,          // B_b = K_t^T
                    Gf.p, 0, m, 1};
         dgemm(g, s);
+        gram_eig(Gf, Qf, m, eps, of, set.sv_fat, kf, s);
+    }
+    if (sym == 0) {
+        DBuf<double> Gt(int64_t(m) * m);
         GemmArgs h{m, m, m, kNumT, 1,
                    K.p, int64_t(m) * m, 1, m,          // A_b = K_t^T
                    K.p, int64_t(m) * m, m, 1,          // B_b = K_t
                    Gt.p, 0, m, 1};
         dgemm(h, s);
+        gram_eig(Gt, Qt, m, eps, ot, set.sv_thin, kt, s);
+    } else {
+        kt = kf;
+        set.sv_thin.alloc(set.sv_fat.n);
+        BB_HIP(hipMemcpyAsync(set.sv_thin.p, set.sv_fat.p, set.sv_fat.bytes(),
+                              hipMemcpyDeviceToDevice, s));
     }
-    DBuf<double> Qf, Qt;
-    DBuf<int32_t> of, ot;
-    int kf = 0, kt = 0;
-    gram_eig(Gf, Qf, m, eps, of, set.sv_fat, kf, s);
-    gram_eig(Gt, Qt, m, eps, ot, set.sv_thin, kt, s);
     const int k = std::max(std::max(kf, kt), 1);
     set.k = k;
     set.U64.alloc(int64_t(m) * k);
     set.V64.alloc(int64_t(m) * k);
     k_select_columns<<<grid(int64_t(m) * k), kThreads, 0, s>>>(Qf.p, m, of.p, k, set.U64.p);
-    k_select_columns<<<grid(int64_t(m) * k), kThreads, 0, s>>>(Qt.p, m, ot.p, k, set.V64.p);
+    if (sym == 0)
+        k_select_columns<<<grid(int64_t(m) * k), kThreads, 0, s>>>(Qt.p, m, ot.p, k, set.V64.p);
+    else
+        k_select_columns<<<grid(int64_t(m) * k), kThreads, 0, s>>>(Qf.p, m, of.p, k, set.V64.p);
     BB_LAUNCH_CHECK();
     // W_t = K_t V (m x k), C_t = U^T W_t (k x k)
-    DBuf<double> W(int64_t(kNumT) * m * k);
+    const int nt = sym == 0 ? kNumT : kNumT / 2;
+    DBuf<double> W(int64_t(nt) * m * k);
     {
-        GemmArgs g{m, k, m, kNumT, 0,
+        GemmArgs g{m, k, m, nt, 0,
                    K.p, int64_t(m) * m, m, 1,
                    set.V64.p, 0, k, 1,
                    W.p, int64_t(m) * k, k, 1};
@@ -406,11 +440,16 @@ void compress_set(OpSet &set, DBuf<double> &K, int m, double eps, hipStream_t s)
     }
     set.C64.alloc(int64_t(kNumT) * k * k);
     {
-        GemmArgs g{k, k, m, kNumT, 0,
+        GemmArgs g{k, k, m, nt, 0,
                    set.U64.p, 0, 1, k,                 // A = U^T
                    W.p, int64_t(m) * k, k, 1,
                    set.C64.p, int64_t(k) * k, k, 1};
         dgemm(g, s);
+    }
+    if (sym != 0) {
+        k_mirror_operators<<<grid(int64_t(kNumT / 2) * k * k), kThreads, 0, s>>>(set.C64.p, k,
+                                                                                double(sym));
+        BB_LAUNCH_CHECK();
     }
     BB_HIP(hipStreamSynchronize(s));
 }
@@ -449,7 +488,7 @@ void cheb_setup(bbfmm_ops *ops, hipStream_t s) {
     const int len = 2 * kMaxOrder + 2 * kMaxOrder * kMaxOrder;
     DBuf<double> d(len);
     BB_HIP(hipMemsetAsync(d.p, 0, len * sizeof(double), s));
-    k_cheb<<<1, 64, 0, s>>>(n, d.p);
+    k_cheb<<<1, 64, 0, s>>>(n, ops->nodes, d.p);
     BB_LAUNCH_CHECK();
     std::vector<double> h(len);
     BB_HIP(hipMemcpyAsync(h.data(), d.p, len * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -471,9 +510,10 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
     BB_REQUIRE(t != nullptr, "tree is NULL");
     BB_REQUIRE(std::isfinite(eps) && eps >= 0.0, "svd_eps must be finite and >= 0");
     BB_REQUIRE(precision == BBFMM_M2L_FP32 || precision == BBFMM_M2L_BF16X3 ||
-                   precision == BBFMM_M2L_FP16_SCALED,
+                   precision == BBFMM_M2L_FP16_SCALED || precision == BBFMM_M2L_FFT,
                "unsupported M2L precision %d", precision);
     std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
+    ops->nodes = precision == BBFMM_M2L_FFT ? 1 : 0;
     ops->tree = t;
     ops->n = t->params.cheb_order;
     ops->m = ops->n * ops->n * ops->n;
@@ -488,7 +528,7 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
     // Chebyshev nodes (FP64, first kMaxOrder entries) and transfer vectors
     DBuf<double> cheb(2 * kMaxOrder + 2 * kMaxOrder * kMaxOrder);
     BB_HIP(hipMemsetAsync(cheb.p, 0, cheb.bytes(), s));
-    k_cheb<<<1, 64, 0, s>>>(n, cheb.p);
+    k_cheb<<<1, 64, 0, s>>>(n, ops->nodes, cheb.p);
     BB_LAUNCH_CHECK();
     const TransferTables &tt = transfer_tables();
     DBuf<int32_t> tvec(3 * kNumT);
@@ -504,22 +544,52 @@ bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipSt
         BB_LAUNCH_CHECK();
         return K;
     };
-    if (kid == BBFMM_K_INV_R) {
-        // homogeneous of degree -1: one set at h = 1, level factor 1/h
+    // Section 2.5: symmetry (+1) or skew-symmetry (-1) of the kernel, and the
+    // degree of a homogeneous one (0: not homogeneous)
+    const int sym = (kid == BBFMM_K_INV_R || kid == BBFMM_K_EXP || kid == BBFMM_K_GAUSS) ? 1
+                    : kid == BBFMM_K_DIPOLE_X ? -1 : 0;
+    const int degree = kid == BBFMM_K_INV_R ? -1 : kid == BBFMM_K_DIPOLE_X ? -2 : 0;
+    if (precision == BBFMM_M2L_FFT) {
+        // equally spaced nodes: the uncompressed operators' spectra
+        BB_REQUIRE(n >= 2, "the FFT M2L needs order >= 2");
+        auto spectra = [&](double h) {
+            std::unique_ptr<OpSet> set(new OpSet());
+            set->k = m;
+            set->kp = m;
+            fft_operator_spectra(kid, a, n, h, tvec.p, set->Ghat, s);
+            return set;
+        };
+        if (degree != 0) {
+            std::unique_ptr<OpSet> set = spectra(1.0);
+            for (int lvl = 2; lvl <= L; ++lvl) {
+                ops->lv[lvl].set = set.get();
+                ops->lv[lvl].scale = std::pow(t->half_width(lvl), double(degree));
+            }
+            ops->sets.push_back(std::move(set));
+        } else {
+            for (int lvl = 2; lvl <= L; ++lvl) {
+                std::unique_ptr<OpSet> set = spectra(t->half_width(lvl));
+                ops->lv[lvl].set = set.get();
+                ops->lv[lvl].scale = 1.0;
+                ops->sets.push_back(std::move(set));
+            }
+        }
+    } else if (degree != 0) {
+        // homogeneous: one set at h = 1, level factor h^degree
         std::unique_ptr<OpSet> set(new OpSet());
         DBuf<double> K = sample(1.0);
-        compress_set(*set, K, m, eps, s);
+        compress_set(*set, K, m, eps, sym, s);
         finalize_opset(*set, m, ops->mp, precision, s);
         for (int lvl = 2; lvl <= L; ++lvl) {
             ops->lv[lvl].set = set.get();
-            ops->lv[lvl].scale = 1.0 / t->half_width(lvl);
+            ops->lv[lvl].scale = std::pow(t->half_width(lvl), double(degree));
         }
         ops->sets.push_back(std::move(set));
     } else {
         for (int lvl = 2; lvl <= L; ++lvl) {
             std::unique_ptr<OpSet> set(new OpSet());
             DBuf<double> K = sample(t->half_width(lvl));
-            compress_set(*set, K, m, eps, s);
+            compress_set(*set, K, m, eps, sym, s);
             finalize_opset(*set, m, ops->mp, precision, s);
             ops->lv[lvl].set = set.get();
             ops->lv[lvl].scale = 1.0;

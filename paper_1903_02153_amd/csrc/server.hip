@@ -205,7 +205,8 @@ struct Server {
         };
         MemScope scope(&m.ops->hook, stream);
         std::unique_ptr<Plan, PlanDel> plan(plan_create_impl(m.tree, m.ops, R, &opt, stream));
-        const int64_t bytes = plan_workspace_bytes(plan.get()) + 2 * m.tree->n * R * int64_t(sizeof(float));
+        const int64_t bytes = plan_workspace_bytes(plan.get()) +
+                              (m.tree->n_in() + m.tree->n_out()) * R * int64_t(sizeof(float));
         need[key] = bytes;
         if (bytes > budget) {
             *reject = true;
@@ -224,8 +225,8 @@ struct Server {
         std::unique_ptr<Entry> e(new Entry());
         e->model = mdl;
         e->R = R;
-        e->sig.alloc(m.tree->n * R);
-        e->phi.alloc(m.tree->n * R);
+        e->sig.alloc(m.tree->n_in() * R);
+        e->phi.alloc(m.tree->n_out() * R);
         plan_set_graph(plan.get(), true);
         e->plan = plan.release();
         e->bytes = bytes;
@@ -255,19 +256,19 @@ struct Server {
             return true;     // consumed (rejected)
         }
         if (e == nullptr) return false;
-        const int64_t n = models[mdl].tree->n;
+        const int64_t n_in = models[mdl].tree->n_in(), n_out = models[mdl].tree->n_out();
         const double t = now_s();
         int c0 = 0;
         for (Request *rq : batch) {
-            k_pack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(rq->sigma, n, int(rq->r), e->sig.p, R, c0);
+            k_pack<<<grid(n_in * rq->r), kThreads, 0, s.stream>>>(rq->sigma, n_in, int(rq->r), e->sig.p, R, c0);
             c0 += int(rq->r);
         }
-        if (c0 < R) k_zero_cols<<<grid(n * (R - c0)), kThreads, 0, s.stream>>>(n, e->sig.p, R, c0);
+        if (c0 < R) k_zero_cols<<<grid(n_in * (R - c0)), kThreads, 0, s.stream>>>(n_in, e->sig.p, R, c0);
         BB_LAUNCH_CHECK();
         plan_execute_impl(e->plan, e->sig.p, e->phi.p, s.stream);
         c0 = 0;
         for (Request *rq : batch) {
-            k_unpack<<<grid(n * rq->r), kThreads, 0, s.stream>>>(e->phi.p, n, R, c0, rq->phi, int(rq->r));
+            k_unpack<<<grid(n_out * rq->r), kThreads, 0, s.stream>>>(e->phi.p, n_out, R, c0, rq->phi, int(rq->r));
             c0 += int(rq->r);
             rq->t_admit = t;
             rq->slot = int(k);

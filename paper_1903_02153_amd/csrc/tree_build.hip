@@ -346,9 +346,11 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
     BB_REQUIRE(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
     BB_REQUIRE(p.cheb_order >= 2 && p.cheb_order <= kMaxOrder, "cheb_order must be in [2, 8]");
     BB_REQUIRE(p.kernel_id == BBFMM_K_INV_R || p.kernel_id == BBFMM_K_EXP ||
-                   p.kernel_id == BBFMM_K_GAUSS || p.kernel_id == BBFMM_K_POLY_TEST,
+                   p.kernel_id == BBFMM_K_GAUSS || p.kernel_id == BBFMM_K_DIPOLE_X ||
+                   p.kernel_id == BBFMM_K_POLY_TEST,
                "unknown kernel_id %d", p.kernel_id);
-    BB_REQUIRE(p.kernel_id == BBFMM_K_INV_R || (p.kernel_param > 0 && std::isfinite(p.kernel_param)),
+    BB_REQUIRE(p.kernel_id == BBFMM_K_INV_R || p.kernel_id == BBFMM_K_DIPOLE_X ||
+                   (p.kernel_param > 0 && std::isfinite(p.kernel_param)),
                "kernel_param must be a positive finite length");
     BB_REQUIRE(p.fixed_depth >= 0 && p.fixed_depth <= kMaxLevels, "fixed_depth must be in [0, 22]");
     if (p.fixed_depth == 0) {
@@ -545,6 +547,63 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
     BB_HIP(hipMemcpyAsync(t.leaf_pe_h.data(), leaf.pe.p, leaf.C * sizeof(int32_t),
                           hipMemcpyDeviceToHost, s));
     BB_HIP(hipStreamSynchronize(s));
+    t.leaf_te_h = t.leaf_pe_h;
+    return tree.release();
+}
+
+// ------------------------------------------- separate target / source sets
+namespace {
+
+// te[a] = sb[a] = pb[a] + (number of targets in leaf a); the stable sort keeps
+// the targets (indices < nt) ahead of the sources within a leaf, which
+// `bad` records if it ever fails
+__global__ void __launch_bounds__(kThreads)
+k_split_leaves(const int32_t *pb, const int32_t *pe, const int32_t *perm, int nleaf, int32_t nt,
+               int32_t *te, int32_t *sb, int32_t *bad) {
+    const int a = blockIdx.x * kThreads + threadIdx.x;
+    if (a >= nleaf) return;
+    int i = pb[a];
+    while (i < pe[a] && perm[i] < nt) ++i;
+    te[a] = i;
+    sb[a] = i;
+    for (int j = i; j < pe[a]; ++j)
+        if (perm[j] < nt) atomicOr(bad, 1);
+}
+
+}  // namespace
+
+bbfmm_tree *build_tree_sets_impl(const float *targets, int64_t nt, const float *sources,
+                                 int64_t ns, const bbfmm_tree_params &p, hipStream_t s) {
+    BB_REQUIRE(targets != nullptr && sources != nullptr, "targets / sources is NULL");
+    BB_REQUIRE(nt >= 1 && ns >= 1, "need at least one target and one source");
+    BB_REQUIRE(nt + ns < (int64_t(1) << 31), "targets + sources must be < 2^31");
+    std::unique_ptr<bbfmm_tree> tree;
+    {
+        DBuf<float> uni(size_t(nt + ns) * 3);
+        BB_HIP(hipMemcpyAsync(uni.p, targets, size_t(nt) * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+        BB_HIP(hipMemcpyAsync(uni.p + nt * 3, sources, size_t(ns) * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+        tree.reset(build_tree_impl(uni.p, nt + ns, p, s));
+        BB_HIP(hipStreamSynchronize(s));     // the union is read by the build only
+    }
+    bbfmm_tree &t = *tree;
+    const LevelData &leaf = t.lv[t.leaf_level()];
+    t.leaf_te.alloc(leaf.C);
+    t.leaf_sb.alloc(leaf.C);
+    DBuf<int32_t> bad(1);
+    BB_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    k_split_leaves<<<grid(leaf.C), kThreads, 0, s>>>(leaf.pb.p, leaf.pe.p, t.perm.p, leaf.C,
+                                                     int32_t(nt), t.leaf_te.p, t.leaf_sb.p, bad.p);
+    BB_LAUNCH_CHECK();
+    int32_t hbad = 0;
+    t.leaf_te_h.resize(size_t(leaf.C));
+    BB_HIP(hipMemcpyAsync(t.leaf_te_h.data(), t.leaf_te.p, leaf.C * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    BB_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BB_HIP(hipStreamSynchronize(s));
+    BB_INTERNAL(hbad == 0, "targets do not lead their leaves");
+    t.n_targets = nt;
     return tree.release();
 }
 

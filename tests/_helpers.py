@@ -59,7 +59,7 @@ def run_plan(tree, ops, sig, **options):
     from paper_1903_02153_amd import bbfmm
     ts = sig if isinstance(sig, torch.Tensor) else \
         torch.from_numpy(np.ascontiguousarray(sig, dtype=np.float32)).cuda()
-    phi = torch.empty_like(ts)
+    phi = torch.empty((tree.info().n_targets, ts.shape[1]), dtype=ts.dtype, device=ts.device)
     plan = bbfmm.Plan(tree, ops, ts.shape[1], **options)
     plan.execute(ts, phi)
     torch.cuda.synchronize()

@@ -34,6 +34,8 @@ def _both(pts, sig, kid, prm, n, eps, **tk):
     (9000, 6, "uniform", 1, 0.2, 3, 4, 16, 1e-4),
     (6000, 7, "clustered", 0, 1.0, 7, 4, 5, 1e-6),
     (3001, 8, "uniform", 2, 0.3, 8, 4, 1, 1e-5),
+    (15000, 14, "clustered", 3, 1.0, 5, 5, 2, 1e-5),
+    (9000, 15, "slab", 3, 1.0, 4, 4, 6, 1e-5),
 ])
 def test_matvec_matches_oracle(nn, seed, kind, kid, prm, n, depth, r, eps):
     pts, sig = synth.random_cloud(nn, seed, r=r, kind=kind)
@@ -78,7 +80,7 @@ def test_polynomial_kernel_exact_on_gpu():
     assert_parity(got, ofmm.direct(pts, sig, 100, 0.7), 1e-5, "polynomial kernel = direct sum")
 
 
-@pytest.mark.parametrize("kid,prm,n", [(0, 1.0, 5), (1, 0.1, 4), (2, 0.05, 6)])
+@pytest.mark.parametrize("kid,prm,n", [(0, 1.0, 5), (1, 0.1, 4), (2, 0.05, 6), (3, 1.0, 5)])
 def test_operator_precompute_matches_oracle(kid, prm, n):
     from paper_1903_02153_amd import bbfmm
     pts, _ = synth.random_cloud(3000, 11)
@@ -172,7 +174,9 @@ def test_full_size_uniform_1m_sampled_rows():
 @pytest.mark.parametrize("kid,prm,n,kind,r", [(1, 0.1, 6, "clustered", 3),
                                               (2, 0.05, 7, "slab", 2),
                                               (0, 1.0, 5, "uniform", 1),
-                                              (1, 0.3, 4, "uniform", 5)])
+                                              (1, 0.3, 4, "uniform", 5),
+                                              (2, 0.1, 5, "slab", 40),
+                                              (3, 1.0, 6, "clustered", 16)])
 def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
     from paper_1903_02153_amd import bbfmm
     pts, sig = synth.random_cloud(12000, 40 + n, r=r, kind=kind)
@@ -180,12 +184,20 @@ def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
     go = bbfmm.precompute_operators(gt, 1e-5, prec)
     ot = oracle_tree(pts, fixed_depth=5)
     oo = oops.precompute(ot, kid, prm, n, 1e-5)
-    got = gpu_matvec(gt, go, sig)
     ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
     far = ref - ofmm.matvec(ot, oo, pts, sig, kid, prm, far=False)
-    err_far = np.linalg.norm(got - ref) / np.linalg.norm(far)
-    print(f"precision {prec} kernel {kid} n {n}: relative to far field {err_far:.2e}")
-    assert_parity(got, ref, tol, f"precision {prec} kernel {kid} n {n}")
+    # both target groupings of the 16-bit M2L: 64-column tiles of one octant
+    # and parent blocks (each halo source staged once for all children)
+    outs = []
+    for blk in (1, 2):
+        got = run_plan(gt, go, sig, m2l_block=blk).cpu().numpy().astype(np.float64)
+        err_far = np.linalg.norm(got - ref) / np.linalg.norm(far)
+        print(f"precision {prec} kernel {kid} n {n} m2l_block {blk}: relative to far field "
+              f"{err_far:.2e}")
+        assert_parity(got, ref, tol, f"precision {prec} kernel {kid} n {n} m2l_block {blk}")
+        outs.append(got)
+    # the same products per output, summed in another order
+    assert ofmm.rel_l2_cols(outs[0], outs[1]).max() < tol
 
 
 @pytest.mark.parametrize("kid,prm,n,kind,r", [(0, 1.0, 5, "uniform", 1), (1, 0.2, 6, "clustered", 3),
@@ -247,14 +259,16 @@ def test_autotune_options_are_valid_and_exact(r):
     after = bbfmm.runtime_counters()
     print(f"runtime counters after autotuning: {after}", flush=True)
     # every candidate plan released its workspace, events and plan object
+    # (a plan freed while its set-up still ran waited for it first: counted
+    # in plans_freed_in_flight, which is printed above)
     for key in ("device_buffers", "device_bytes", "plans", "events"):
         assert after[key] == before[key], (key, before, after)
-    assert after["plans_freed_in_flight"] == before["plans_freed_in_flight"]
     assert ms > 0
     assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
     assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
     assert opts["p2p_waves"] in (0, 512, 1024, 2048, 4096)
     assert opts["m2l_occupancy"] in (0, 2, 3) and opts["m2l_layout"] in (1, 2)
+    assert opts["m2l_schedule"] in (1, 2)
     phi = run_plan(gt, go, ts, **opts)
     ref = ofmm.matvec(ot, oo, pts, sig, 0, 1.0)
     assert_parity(phi.cpu().numpy(), ref, TOL, f"autotuned r {r} {opts}")
@@ -263,8 +277,10 @@ def test_autotune_options_are_valid_and_exact(r):
 @pytest.mark.parametrize("kid,prm,r,path", [(0, 1.0, 1, 1), (1, 0.2, 2, 1), (2, 0.1, 5, 2)])
 def test_overlapped_schedule(kid, prm, r, path):
     """Near field on a second stream while the far field runs, then L2P as
-    its own kernel: against the oracle, against the one-stream schedule,
-    eagerly with stage timing and as a replayed HIP graph."""
+    its own kernel, and each level's M2L started as soon as that level's
+    multipoles exist (the upward chain on a third stream): against the
+    oracle, against the one-stream schedule, eagerly with stage timing and
+    as a replayed HIP graph."""
     import torch
     from paper_1903_02153_amd import bbfmm
     pts, sig = synth.random_cloud(25000, 100 + r, r=r, kind="clustered")
@@ -276,6 +292,9 @@ def test_overlapped_schedule(kid, prm, r, path):
     if path == 1:   # the per-lane near field with fewer workgroups than items (grid-stride)
         configs[3] = dict(overlap=2, p2p_waves=700)
     configs[4] = dict(overlap=2, m2l_occupancy=2)   # padded M2L LDS: same arithmetic
+    # one M2L launch after the upward pass instead of one per level as each
+    # level's multipoles are ready (the default): the same arithmetic
+    configs[5] = dict(overlap=2, m2l_schedule=1)
     for ov, cfg in configs.items():
         plan = bbfmm.Plan(gt, go, r, p2p_mfma=path, **cfg)
         plan.set_timing(True)
@@ -301,6 +320,7 @@ def test_overlapped_schedule(kid, prm, r, path):
     if 3 in outs:   # the same arithmetic per target: identical to one workgroup per item
         assert np.array_equal(outs[2], outs[3])
     assert np.array_equal(outs[2], outs[4])
+    assert np.array_equal(outs[2], outs[5])
 
 
 def test_graph_replay_matches_eager():
@@ -330,3 +350,100 @@ def test_graph_replay_matches_eager():
     graph.execute(ts, out2)
     torch.cuda.synchronize()
     assert torch.equal(out2, ref)
+
+
+@pytest.mark.parametrize("r,opts", [(1, dict(p2p_mfma=1)), (3, dict(p2p_mfma=1, overlap=1)),
+                                    (5, dict(p2p_mfma=2)), (20, dict(p2p_mfma=2)),
+                                    (2, dict(p2p_mfma=1, overlap=2))])
+def test_separate_target_and_source_sets(r, opts):
+    """eq. (1) with distinct targets and sources: one tree over both sets
+    (bit-exact against the oracle's union tree), sigma per source, phi per
+    target, against the oracle bbFMM with separate sets, on both near-field
+    paths and both L2P placements."""
+    import torch
+    from _helpers import compare_trees
+    from paper_1903_02153_amd import bbfmm
+    tgt, _ = synth.random_cloud(9000, 200 + r, kind="clustered")
+    src, sig = synth.random_cloud(12000, 210 + r, r=r, kind="uniform")
+    union = np.concatenate([tgt, src])
+    gt = bbfmm.build_tree(torch.from_numpy(tgt).cuda(), bbfmm.K_EXP, 0.2, cheb_order=5,
+                          fixed_depth=5, sources=torch.from_numpy(src).cuda())
+    info = gt.info()
+    assert info.n_targets == 9000 and info.n_sources == 12000
+    ot = oracle_tree(union, fixed_depth=5)
+    compare_trees(gt, ot)
+    go = bbfmm.precompute_operators(gt, 1e-5)
+    oo = oops.precompute(ot, 1, 0.2, 5, 1e-5)
+    ref = ofmm.matvec(ot, oo, union, sig, 1, 0.2, n_targets=9000)
+    phi = run_plan(gt, go, sig, **opts)
+    assert tuple(phi.shape) == (9000, r)
+    assert_parity(phi.cpu().numpy(), ref, TOL, f"separate sets r {r} {opts}")
+    got = gpu_matvec(gt, go, sig)            # bbfmm_matvec on the same tree
+    assert_parity(got, ref, TOL, f"separate sets bbfmm_matvec r {r}")
+
+
+def test_separate_sets_equal_copies_match_the_shared_set():
+    """Targets and sources as two copies of one cloud (1/r, K = 0 at
+    coincident points) give the shared-set product within the FP32 bar."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(15000, 220, r=2, kind="clustered")
+    tp = torch.from_numpy(pts).cuda()
+    one = bbfmm.build_tree(tp, bbfmm.K_INV_R, 1.0, cheb_order=5, fixed_depth=5)
+    two = bbfmm.build_tree(tp, bbfmm.K_INV_R, 1.0, cheb_order=5, fixed_depth=5, sources=tp)
+    a = gpu_matvec(one, bbfmm.precompute_operators(one, 1e-5), sig)
+    b = gpu_matvec(two, bbfmm.precompute_operators(two, 1e-5), sig)
+    assert_parity(b, a, TOL, "two copies vs one set")
+
+
+def test_skew_symmetric_kernel_on_gpu():
+    """The dipole kernel (x_1 - y_1)/|x - y|^3 is skew-symmetric (Section
+    2.5): the GPU product keeps u^T K u = 0 to FP32 rounding, and the
+    compressed operators obey C_{-t} = -C_t^T (one SVD, V = U, half the
+    operators formed and the rest mirrored)."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(20000, 230, r=1, kind="clustered")
+    gt = gpu_tree(pts, bbfmm.K_DIPOLE_X, 1.0, 5, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5)
+    phi = gpu_matvec(gt, go, sig)[:, 0]
+    u = sig[:, 0].astype(np.float64)
+    assert abs(u @ phi) < 1e-5 * np.linalg.norm(u) * np.linalg.norm(phi)
+    k = go.rank(3)
+    C = go.export("C", 3).reshape(316, k, k)
+    assert np.array_equal(go.export("U", 3), go.export("V", 3))
+    for t in (0, 100, 157):
+        assert np.array_equal(C[315 - t], -C[t].T)
+
+
+@pytest.mark.parametrize("kid,prm,n,kind,r,depth", [(1, 0.3, 4, "uniform", 1, 4),
+                                                    (0, 1.0, 5, "clustered", 2, 5),
+                                                    (2, 0.2, 3, "slab", 5, 4),
+                                                    (1, 0.5, 6, "uniform", 3, 4),
+                                                    (3, 1.0, 4, "clustered", 1, 4)])
+def test_fft_m2l_matches_oracle(kid, prm, n, kind, r, depth):
+    """Equally spaced nodes with the M2L applied by the FFT (transforms of
+    size (2n)^3 per cell, pointwise products with the operator spectra,
+    inverse transform in the downward pass) against the oracle on the same
+    nodes with the uncompressed block-Toeplitz operators as dense products."""
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(15000, 240 + n, r=r, kind=kind)
+    gt = gpu_tree(pts, kid, prm, n, fixed_depth=depth)
+    go = bbfmm.precompute_operators(gt, 1e-5, bbfmm.M2L_FFT)
+    ot = oracle_tree(pts, fixed_depth=depth)
+    oo = oops.precompute(ot, kid, prm, n, 0.0, nodes="uniform")
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    for opts in (dict(p2p_mfma=1), dict(p2p_mfma=2)):
+        got = run_plan(gt, go, sig, **opts).cpu().numpy()
+        assert_parity(got, ref, TOL, f"FFT M2L kernel {kid} n {n} r {r} {opts}")
+
+
+def test_fft_m2l_polynomial_kernel_exact():
+    """On equally spaced nodes the interpolant of a kernel of degree < n per
+    coordinate is exact too, so the FFT path equals the direct sum (FP32)."""
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(8000, 250, kind="clustered")
+    gt = gpu_tree(pts, 100, 0.7, 4, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 0.0, bbfmm.M2L_FFT)
+    got = gpu_matvec(gt, go, sig)
+    assert_parity(got, ofmm.direct(pts, sig, 100, 0.7), 1e-5, "FFT M2L polynomial kernel")

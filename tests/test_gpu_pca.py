@@ -49,3 +49,64 @@ def test_randomized_eigenvalues_match_exact_products():
     dense = np.sort(np.linalg.eigvalsh(Kd))[::-1][:10]
     ext_sub = _exact_randomized(x, omega[:sub].astype(np.float64), 10)
     assert np.abs(ext_sub - dense).max() / dense[0] < 1e-2
+
+
+def _dense_exp_top(pts, k):
+    """Top-k eigenvalues of the dense FP64 kernel matrix exp(-|x - y|) by
+    Lanczos (ARPACK) on the explicitly formed matrix."""
+    from scipy.sparse.linalg import eigsh
+    x = pts.astype(np.float64)
+    n = len(x)
+    K = np.empty((n, n))
+    for b in range(0, n, 1000):
+        K[b:b + 1000] = np.exp(-np.linalg.norm(x[b:b + 1000, None, :] - x[None, :, :], axis=2))
+    lam = eigsh(K, k=k, which="LA", tol=1e-12, return_eigenvectors=False)
+    return np.sort(lam)[::-1]
+
+
+def test_randomized_eigenvalues_against_dense_solver_and_large_n():
+    """N = 10^4: the GPU eigenvalues against a dense FP64 eigensolver (the
+    leading ten to 1e-3, all 100 reported).  N = 8 * 10^4 (4 levels, the
+    paper's second run): against the same algorithm with exact FP64 block
+    products (dense kernel blocks on the device, test-side code), where the
+    paper reports 2.8e-5 (soft: its SVD tolerance is not stated)."""
+    import torch
+    from paper_1903_02153_amd import bbfmm, pca
+    k, l = 100, 120
+    rng = np.random.default_rng(141)
+    n = 10_000
+    pts = rng.random((n, 3)).astype(np.float32)
+    omega = rng.standard_normal((n, l)).astype(np.float32)
+    tree = gpu_tree(pts, 1, 1.0, 4, fixed_depth=3)
+    ops = bbfmm.precompute_operators(tree, 1e-5)
+    lam, _ = pca.randomized_eigh(tree, ops, torch.from_numpy(omega).cuda(), k)
+    dense = _dense_exp_top(pts, k)
+    rel = np.abs(lam - dense) / dense[0]
+    print(f"N {n}: vs dense eigensolver, top-10 max {rel[:10].max():.2e}, "
+          f"top-100 max {rel.max():.2e} (relative to lambda_1)")
+    assert rel[:10].max() < 1e-3
+    del tree, ops
+
+    n = 80_000
+    pts = rng.random((n, 3)).astype(np.float32)
+    omega = rng.standard_normal((n, l)).astype(np.float32)
+    tree = gpu_tree(pts, 1, 1.0, 4, fixed_depth=4)
+    ops = bbfmm.precompute_operators(tree, 1e-5)
+    om = torch.from_numpy(omega).cuda()
+    lam, _ = pca.randomized_eigh(tree, ops, om, k)
+    x = torch.from_numpy(pts.astype(np.float64)).cuda()
+
+    def dense_product(S):
+        out = torch.empty_like(S)
+        for b in range(0, n, 4096):
+            Kb = torch.exp(-torch.cdist(x[b:b + 4096], x))
+            out[b:b + 4096] = Kb @ S
+        return out
+
+    Y = dense_product(om.double())
+    Q, _ = torch.linalg.qr(Y)
+    B = Q.T @ dense_product(Q.contiguous())
+    ext = np.sort(np.linalg.eigvalsh(0.5 * (B + B.T).cpu().numpy()))[::-1][:k]
+    err = np.linalg.norm(lam - ext) / np.linalg.norm(ext)
+    print(f"N {n}: eigenvalue error vs exact products {err:.2e} (the paper: 2.8e-5)")
+    assert err < 1e-3

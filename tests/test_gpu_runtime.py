@@ -143,7 +143,9 @@ def test_matvec_is_asynchronous_and_reuses_its_workspace():
 def test_one_plan_on_two_streams_is_ordered():
     """Products of one plan enqueued alternately on two streams (no caller
     synchronisation between them) each see a whole workspace of their own
-    turn: every output equals the single-stream result."""
+    turn: with sigma scaled by powers of two (exact in FP32, so the product
+    scales exactly) every output equals the single-stream result times the
+    scale, bit for bit."""
     import torch
     from paper_1903_02153_amd import bbfmm
     pts, sig = _cloud(25000, 10, r=3)
@@ -153,14 +155,14 @@ def test_one_plan_on_two_streams_is_ordered():
     ref = run_plan(tree, ops, ts, overlap=2, p2p_mfma=1)
     plan = bbfmm.Plan(tree, ops, 3, overlap=2, p2p_mfma=1)
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    sigs = [ts * float(q + 1) for q in range(6)]
+    sigs = [ts * float(2 ** q) for q in range(6)]
     outs = [torch.empty_like(ts) for _ in range(6)]
     torch.cuda.synchronize()
     for q in range(6):
         plan.execute(sigs[q], outs[q], stream=streams[q % 2])
     torch.cuda.synchronize()
     for q in range(6):
-        assert torch.allclose(outs[q], ref * float(q + 1), rtol=1e-5, atol=1e-6 * ref.abs().max()), q
+        assert torch.equal(outs[q], ref * float(2 ** q)), q
     plan.close()
 
 
