@@ -286,6 +286,25 @@ bbfmm_status bbfmm_matvec(const bbfmm_tree *tree, const bbfmm_ops *ops,
                           void *stream);
 
 /*
+ * bbfmm_matvec without any device allocation, for callers that cannot
+ * allocate (tight serving loops, harnesses that forbid allocation): the
+ * same product, with every buffer beyond sigma and phi (sigma in tree order,
+ * expansions, M2L partials, launch lists) taken from one fixed device array
+ * of BBFMM_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends.  Launch shapes are the built-in heuristic with
+ * the one-stream schedule, so the result equals bbfmm_matvec's up to
+ * floating-point summation order.  Synchronous: returns once the product
+ * has finished.  Every call on one GPU uses the same array; calls that
+ * overlap on one GPU (from several threads) race.
+ * Errors: INVALID_ARG (as bbfmm_matvec, and when the product needs more
+ * than the fixed array: large N x r), HIP.
+ */
+#define BBFMM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+bbfmm_status bbfmm_matvec_static(const bbfmm_tree *tree, const bbfmm_ops *ops,
+                                 const float *sigma, int64_t r, float *phi,
+                                 void *stream);
+
+/*
  * A reusable matvec for a fixed (tree, operators, r) that owns its
  * workspace, so repeated products allocate nothing.  plan_execute has the
  * semantics of bbfmm_matvec: it enqueues the product on `stream` and

@@ -159,6 +159,7 @@ SIGNATURES = {
     "bbfmm_ops_export": (_I32, [_VP, _I32, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
     "bbfmm_ops_import": (_I32, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _PVP]),
     "bbfmm_matvec": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP]),
+    "bbfmm_matvec_static": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "bbfmm_plan_create": (_I32, [_VP, _VP, _I64, _PVP]),
     "bbfmm_plan_create_ex": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _PVP]),
     "bbfmm_get_runtime_counters": (_I32, [ctypes.POINTER(RuntimeCounters)]),
