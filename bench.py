@@ -80,6 +80,30 @@ def _oracle_threads() -> int:
     return max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
 
 
+def pass_bytes(info, ranks, order: int, r: int, nsplit: int):
+    """Algorithmic HBM bytes of the upward and downward passes (FP32
+    operands): upward = points and weights read by P2M (12 + 4r per point),
+    then per cell of levels >= 2 its multipoles written and read back by the
+    compression (4 n^3 r each) and the compressed ones written (4 k r), plus
+    the children's multipoles read by M2M (4 n^3 r per child); downward = per
+    cell the M2L partials read (4 k r per partial) and the locals written
+    (4 n^3 r), plus for levels >= 3 the parent's locals read by L2L and the
+    locals read back by the decompression (4 n^3 r each)."""
+    m = order ** 3
+    L = info.depth - 1
+    up = info.n_points * (12 + 4 * r)
+    down = 0
+    for lvl in range(2, L + 1):
+        C, k = info.cells[lvl], ranks[lvl]
+        up += C * r * (8 * m + 4 * k)
+        if lvl < L:
+            up += info.cells[lvl + 1] * r * 4 * m
+        down += C * r * (4 * k * nsplit + 4 * m)
+        if lvl > 2:
+            down += C * r * 8 * m
+    return up, down
+
+
 def cpu_baseline(w, gpu_phi_rows, single_rows: int = 512):
     """The oracle as it stands on this host: full upward pass and M2L, L2P
     and P2P on the sampled targets; P2P time scaled to all N targets.  Run
@@ -521,6 +545,12 @@ def main() -> int:
         isolated = {"ms": round(t_iso, 4), "achieved": round(flop / (t_iso * 1e-3) / 1e12, 3),
                     "frac": round(flop / (t_iso * 1e-3) / 1e12 / peak, 4),
                     "note": "same plan options with the one-stream schedule, 20 launches"}
+    up_b, down_b = pass_bytes(info, ranks, w.order, w.r, int(opts.get("m2l_split", 1)) if opts else 1)
+    passes = {"up_gbs": round(up_b / ((stage_avg["p2m"] + stage_avg["m2m"]) * 1e-3) / 1e9, 1),
+              "down_gbs": round(down_b / (stage_avg["down"] * 1e-3) / 1e9, 1),
+              "up_bytes": up_b, "down_bytes": down_b, "peak_gbs": PEAK_HBM_GBS,
+              "note": "algorithmic bytes (FP32 operands) over the stage times; the upward "
+                      "chain may run beside the near field or the M2L"}
     roofline = {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic("k_m2l" if kern == "m2l" else "k_p2p", w.name),
@@ -547,6 +577,7 @@ def main() -> int:
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "passes": passes,
         "roofline": roofline,
     }
     if args.copy_calibration:

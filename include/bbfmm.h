@@ -50,7 +50,9 @@ typedef enum {
     BBFMM_ERR_HIP = 3,           /* a HIP runtime call or launch failed       */
     BBFMM_ERR_BUDGET = 4,        /* a server request exceeds the HBM budget   */
     BBFMM_ERR_NOT_FOUND = 5,     /* unknown array / level in an export        */
-    BBFMM_ERR_INTERNAL = 6       /* an internal consistency check failed      */
+    BBFMM_ERR_INTERNAL = 6,      /* an internal consistency check failed      */
+    BBFMM_ERR_CANCELLED = 7      /* a server request was cancelled or its
+                                    server destroyed before it ran            */
 } bbfmm_status;
 
 /* Kernel functions (Sections 1 and 4; all translation invariant). */
@@ -220,10 +222,14 @@ bbfmm_status bbfmm_tree_export(const bbfmm_tree *tree, int32_t what,
  * U / V the leading left / right singular vectors, C_t = U^T K_t V), and
  * cast U, V, C_t to the matvec precision.  For the homogeneous kernel 1/r
  * one set is built and scaled by 1/h per level.  svd_eps = 0 disables the
- * compression (U = V = identity).
+ * compression (U = V = identity); otherwise svd_eps >= 1e-7 (the singular
+ * values come from FP64 eigenvalues of Gram matrices, which resolve about
+ * 1e-8 of the largest).  For a symmetric or skew-symmetric kernel the
+ * operators of t and -t are signed transposes: one SVD (V = U) and half of
+ * the operators are computed.
  *   allocator  NULL = the tree's.
- * Errors: INVALID_ARG (svd_eps < 0 or not finite, unknown precision),
- * OUT_OF_MEMORY, HIP.  Synchronous.
+ * Errors: INVALID_ARG (svd_eps < 0, in (0, 1e-7) or not finite, unknown
+ * precision), OUT_OF_MEMORY, HIP.  Synchronous.
  */
 bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *tree,
                                         double svd_eps, int32_t precision,
@@ -352,6 +358,9 @@ typedef struct {
                             /* cell as one block, each source of their halo      */
                             /* staged once for all of them (no slot split);      */
                             /* 0 = 2 from r = 16 on                              */
+    int32_t m2l_rtile;      /* parent blocks: right-hand sides per workgroup, 16, */
+                            /* 32 or 64 (0: 16 up to r = 16, 32 up to 47, else   */
+                            /* 64)                                               */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a
@@ -413,7 +422,8 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  * overlapped, the M2L workgroups per CU (as many as fit, 3 or 2); then
  * the FP32 M2L wave layout; then the M2L schedule (one launch, or per
  * level as the upward pass finishes each level); then, for a 16-bit M2L,
- * the target grouping (64-column tiles or parent blocks).  Each candidate runs one
+ * the target grouping (64-column tiles or parent blocks) and, with parent
+ * blocks, the r-tile (16, 32 or 64 right-hand sides per workgroup).  Each candidate runs one
  * untimed product and `reps` timed ones (HIP events on `stream`); its
  * time is the median.  Options only change launch shapes (and with them
  * the floating-point summation order), never the arithmetic precision.
@@ -422,7 +432,7 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  *   reps        1..100.
  *   best        out: the chosen options (m2l_split, p2p_mfma,
  *               p2p_max_split, overlap, p2p_waves, m2l_occupancy,
- *               m2l_layout, m2l_schedule and m2l_block explicit).
+ *               m2l_layout, m2l_schedule, m2l_block and m2l_rtile explicit).
  *   best_ms     out (may be NULL): its median milliseconds per product.
  * Allocates and frees one plan workspace per candidate; synchronizes
  * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
@@ -471,7 +481,15 @@ bbfmm_status bbfmm_server_submit(bbfmm_server *server, int32_t model_id,
  * request's own status (BUDGET, HIP) if it failed.  Each id is waited once. */
 bbfmm_status bbfmm_server_wait(bbfmm_server *server, uint64_t request_id,
                                bbfmm_request_stats *stats);
-/* Drains in-flight batches and frees the server (NULL accepted). */
+/* Cancel a request that has not been admitted yet: it completes with
+ * BBFMM_ERR_CANCELLED (reported by wait; its phi is untouched).  Errors:
+ * INVALID_ARG when it was already admitted or is complete, NOT_FOUND for an
+ * unknown or already waited id. */
+bbfmm_status bbfmm_server_cancel(bbfmm_server *server, uint64_t request_id);
+/* Finishes the batches in flight, completes every request still pending
+ * with BBFMM_ERR_CANCELLED, waits until every thread blocked in
+ * bbfmm_server_wait has returned, and frees the server (NULL accepted).
+ * No call may use the server after destroy has begun. */
 bbfmm_status bbfmm_server_destroy(bbfmm_server *server);
 
 /* Counters of a server since its creation (all out, host). */

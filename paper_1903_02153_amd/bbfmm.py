@@ -29,7 +29,7 @@ OA = dict(U=0, V=1, C=2, sv_fat=3, sv_thin=4)
 STAGES = ("gather", "p2m", "m2m", "m2l", "down", "p2p")
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "BUDGET",
-          5: "NOT_FOUND", 6: "INTERNAL"}
+          5: "NOT_FOUND", 6: "INTERNAL", 7: "CANCELLED"}
 
 
 class BBFMMError(RuntimeError):
@@ -71,7 +71,8 @@ class PlanOptions(ctypes.Structure):
                 ("p2p_max_split", ctypes.c_int32), ("p2p_mfma", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("p2p_waves", ctypes.c_int32),
                 ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32),
-                ("m2l_schedule", ctypes.c_int32), ("m2l_block", ctypes.c_int32)]
+                ("m2l_schedule", ctypes.c_int32), ("m2l_block", ctypes.c_int32),
+                ("m2l_rtile", ctypes.c_int32)]
 
 
 class RuntimeCounters(ctypes.Structure):
@@ -175,6 +176,7 @@ SIGNATURES = {
     "bbfmm_server_add": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I32)]),
     "bbfmm_server_submit": (_I32, [_VP, _I32, _VP, _I64, _VP, ctypes.POINTER(ctypes.c_uint64)]),
     "bbfmm_server_wait": (_I32, [_VP, ctypes.c_uint64, _VP]),
+    "bbfmm_server_cancel": (_I32, [_VP, ctypes.c_uint64]),
     "bbfmm_server_destroy": (_I32, [_VP]),
     "bbfmm_tree_free": (None, [_VP]),
     "bbfmm_ops_free": (None, [_VP]),
@@ -306,7 +308,7 @@ class Plan:
 
     def __init__(self, tree: Tree, ops: Ops, r: int, allocator=None, stream=None, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
-        m2l_occupancy, m2l_layout, m2l_schedule, m2l_block (0 = heuristic).  allocator: a TorchAllocator
+        m2l_occupancy, m2l_layout, m2l_schedule, m2l_block, m2l_rtile (0 = heuristic).  allocator: a TorchAllocator
         (None = the operators'); stream: where the set-up is enqueued."""
         h = _VP()
         opt = PlanOptions()
@@ -378,7 +380,7 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
             "p2p_mfma": best.p2p_mfma, "overlap": best.overlap,
             "p2p_waves": best.p2p_waves, "m2l_occupancy": best.m2l_occupancy,
             "m2l_layout": best.m2l_layout, "m2l_schedule": best.m2l_schedule,
-            "m2l_block": best.m2l_block}, ms.value
+            "m2l_block": best.m2l_block, "m2l_rtile": best.m2l_rtile}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
@@ -488,6 +490,11 @@ class Server:
             self._keep.pop(request_id, None)
         return {"t_submit": st.t_submit, "t_admit": st.t_admit, "t_done": st.t_done,
                 "batch_r": st.batch_r, "slot": st.slot}
+
+    def cancel(self, request_id: int) -> None:
+        """Withdraw a request that has not been admitted (its wait then raises
+        CANCELLED)."""
+        _check(lib().bbfmm_server_cancel(self._h, ctypes.c_uint64(request_id)))
 
     def stats(self) -> dict:
         st = ServerStats()

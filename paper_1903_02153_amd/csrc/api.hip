@@ -243,8 +243,10 @@ bbfmm_status bbfmm_precompute_operators(const bbfmm_tree *t, double svd_eps, int
                                         const bbfmm_allocator *allocator, void *stream,
                                         bbfmm_ops **out) {
     return guarded([&] {
-        BB_REQUIRE(out != nullptr && t != nullptr, "tree / out is NULL");
+        BB_REQUIRE(out != nullptr, "out is NULL");
         *out = nullptr;
+        precompute_check(svd_eps, precision);
+        BB_REQUIRE(t != nullptr, "tree is NULL");
         BB_REQUIRE(allocator == nullptr || (allocator->alloc && allocator->free),
                    "allocator needs both alloc and free");
         const bbfmm_allocator hook = allocator ? *allocator : t->hook;
@@ -509,6 +511,15 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
             for (int blk = 1; blk <= 2; ++blk) {
                 bbfmm_plan_options c = cur;
                 c.m2l_block = blk;
+                consider(c);
+            }
+        if ((o->precision == BBFMM_M2L_BF16X3 || o->precision == BBFMM_M2L_FP16_SCALED) &&
+            cur.m2l_block != 1 && r > 16)
+            for (int rt : {16, 32, 64}) {
+                if (rt > 16 && rt / 2 >= r) continue;      // wider than the block of columns
+                bbfmm_plan_options c = cur;
+                c.m2l_block = 2;
+                c.m2l_rtile = rt;
                 consider(c);
             }
         // make every choice explicit: what the heuristic picked for the zeros

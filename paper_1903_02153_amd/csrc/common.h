@@ -239,6 +239,7 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
 bbfmm_tree *build_tree_sets_impl(const float *targets, int64_t nt, const float *sources,
                                  int64_t ns, const bbfmm_tree_params &p, hipStream_t s);
 bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s);
+void precompute_check(double eps, int precision);   // argument checks, no device work
 void cheb_setup(bbfmm_ops *ops, hipStream_t s);   // nodes of ops->nodes
 
 // FFT M2L on equally spaced nodes (fft_m2l.hip): transform size P = 2n per

@@ -1149,13 +1149,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
 // b interacts with every child a it is not adjacent to, with transfer
 // vector t = h - 2 - o(a) (o(a): the child's offset, the octant bits).  So
 // each occupied halo cell's compressed multipoles are staged in LDS once per
-// 64-rank chunk and serve all children that see them (about seven on a full
+// 32-rank chunk and serve all children that see them (about seven on a full
 // grid), while the operator rows C_t come from L2 (316 operators per
 // level).  Wave w owns children 2w and 2w+1: RB 16-row blocks of the rank
 // times CB 16-column blocks of right-hand sides for each.  The sum over the
-// halo is complete inside the workgroup (one partial result).  Staging of
-// the next halo chunk is issued before the MFMAs of the current one, as in
-// the tile kernel.
+// halo is complete inside the workgroup (one partial result).  The loads of
+// the next step -- the staged source chunk and the wave's operator rows --
+// are issued before the MFMAs of the current one.
 struct M2LBlockArgs {
     const uint16_t *Mh, *Ml;   // level operands [C][r][kp] (bf16 hi / lo, or fp16 in Mh)
     const float *Msinv;        // fp16: inverse block scales [C][r][nchunk]
@@ -1183,8 +1183,8 @@ template <int PREC, int RB, int CB>
 __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
     constexpr bool X3 = PREC == BBFMM_M2L_BF16X3;
     constexpr int COLS = 16 * CB;
-    constexpr int ldb = 64 + 8;                 // 144-byte column rows: conflict-free reads
-    constexpr int PPC = X3 ? 16 : 8;            // 16-byte pieces per column (hi + lo for X3)
+    constexpr int ldb = 32 + 8;                 // 80-byte column rows (32 ranks + pad)
+    constexpr int PPC = X3 ? 8 : 4;             // 16-byte pieces per column (hi + lo for X3)
     constexpr int NB = (COLS * PPC + kThreads - 1) / kThreads;
     constexpr int NH = 216;                     // halo positions
     __shared__ uint4 Bstore[2][X3 ? 2 : 1][COLS * ldb / 8];
@@ -1200,7 +1200,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
     const int kp = g.kp, r = g.r;
     const int row0 = blockIdx.y * 16 * RB;
     const int rhs0 = blockIdx.z * COLS;
-    const int nkc = (kp + 63) / 64;
+    const int nkc = (kp + 31) / 32;             // 32-deep rank chunks (kp is a multiple of 32)
+    const int nc64 = (kp + 63) / 64;            // fp16 scales are per 64 ranks
     int oct[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) oct[i] = i < nchild ? int(g.keys[c0 + i] & 7u) : 0;
@@ -1251,27 +1252,26 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
         const int e = tid + i * kThreads;
         const int col = e / PPC, q = e % PPC;
         bcol[i] = col;
-        bpart[i] = q >> 3;
-        bsub[i] = q & 7;
+        bpart[i] = q >> 2;
+        bsub[i] = q & 3;
         boff[i] = (e < COLS * PPC && rhs0 + col < r) ? int64_t(rhs0 + col) * kp + 8 * bsub[i] : -1;
     }
     const int scol = tid % COLS;
     auto load_b = [&](int s, uint4 *breg, float &bscale) {
         const int h = s / nkc, kc = s - (s / nkc) * nkc;
         const int b = hb[h];
-        const int lim = min(64, kp - kc * 64) / 8;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const bool ok = boff[i] >= 0 && bsub[i] < lim;
+            const bool ok = boff[i] >= 0;
             const uint16_t *base = bpart[i] ? g.Ml : g.Mh;
             const uint4 v = *reinterpret_cast<const uint4 *>(
-                base + (ok ? int64_t(b) * r * kp + boff[i] + kc * 64 : 0));
+                base + (ok ? int64_t(b) * r * kp + boff[i] + kc * 32 : 0));
             const uint32_t w = ok ? 0xffffffffu : 0u;
             breg[i] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
         }
         if constexpr (!X3) {
             const bool ok = rhs0 + scol < r;
-            const float v = g.Msinv[ok ? (int64_t(b) * r + rhs0 + scol) * nkc + kc : 0];
+            const float v = g.Msinv[ok ? (int64_t(b) * r + rhs0 + scol) * nc64 + kc / 2 : 0];
             bscale = ok ? v : 0.f;
         }
     };
@@ -1290,27 +1290,59 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[u][rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
     const int nsteps = nh * nkc;
+    // operator rows of this wave's two children for one step (ks = 32-deep
+    // block of the 64-rank chunk), prefetched one step ahead like the sources
+    constexpr int NP = X3 ? 2 : 1;
+    uint4 acur[2][RB][NP], anxt[2][RB][NP];
+    float ccur[2] = {0.f, 0.f}, cnxt[2] = {0.f, 0.f};
+    auto load_a = [&](int st, uint4 (&a)[2][RB][NP], float (&cv)[2]) {
+        const int h = st / nkc, kc = st - (st / nkc) * nkc;
+        const unsigned hm = hmask[h];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = 2 * wave + u;
+            const bool valid = (hm >> i) & 1u;                  // wave-uniform
+            const int ti = valid ? int(htix[h][i]) : 0;
+            if constexpr (!X3) cv[u] = valid ? g.Cinv[ti] : 0.f;
+            const int64_t cbase = int64_t(ti) * kp * kp + kc * 32 + 8 * (lane >> 4);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int row = row0 + rb * 16 + (lane & 15);
+                const bool ok = valid && row < kp;
+                const int64_t o = ok ? cbase + int64_t(row) * kp : 0;
+                const uint32_t w = ok ? 0xffffffffu : 0u;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (valid) v = *reinterpret_cast<const uint4 *>(g.Ch + o);
+                a[u][rb][0] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+                if constexpr (X3) {
+                    if (valid) v = *reinterpret_cast<const uint4 *>(g.Cl + o);
+                    a[u][rb][NP - 1] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+                }
+            }
+        }
+    };
     uint4 breg[NB];
     float bscale = 0.f;
     if (nsteps > 0) {
         load_b(0, breg, bscale);
+        load_a(0, acur, ccur);
         store_b(0, breg, bscale);
     }
     __syncthreads();
     const int bbase = ((lane & 15) * ldb + 8 * (lane >> 4)) / 8;
     for (int s = 0; s < nsteps; ++s) {
         const bool more = s + 1 < nsteps;
-        if (more) load_b(s + 1, breg, bscale);
-        const int h = s / nkc, kc = s - (s / nkc) * nkc;
-        const int nks = min(64, kp - kc * 64) / 32;           // 32-deep blocks with rank
+        if (more) {
+            load_b(s + 1, breg, bscale);
+            load_a(s + 1, anxt, cnxt);
+        }
+        const int h = s / nkc;
         const unsigned hm = hmask[h];
         const uint4 *Bh = Bstore[s & 1][0];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int i = 2 * wave + u;
             if (!((hm >> i) & 1u)) continue;                    // wave-uniform
-            const int ti = htix[h][i];
-            const int64_t cbase = int64_t(ti) * kp * kp + kc * 64 + 8 * (lane >> 4);
             v4f part[RB][CB];
             if constexpr (!X3) {
 #pragma unroll
@@ -1319,51 +1351,31 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
                     for (int cb = 0; cb < CB; ++cb) part[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                if (ks >= nks) break;
-                uint4 ah[RB], al[RB];
+            for (int cb = 0; cb < CB; ++cb) {
+                const uint4 braw = Bh[bbase + cb * 16 * ldb / 8];
+                if constexpr (X3) {
+                    const v8bf bh = __builtin_bit_cast(v8bf, braw);
+                    const v8bf bl = __builtin_bit_cast(v8bf, Bstore[s & 1][1][bbase + cb * 16 * ldb / 8]);
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const int row = row0 + rb * 16 + (lane & 15);
-                    const bool ok = row < kp;
-                    const int64_t o = ok ? cbase + int64_t(row) * kp + 32 * ks : 0;
-                    const uint32_t w = ok ? 0xffffffffu : 0u;
-                    uint4 v = *reinterpret_cast<const uint4 *>(g.Ch + o);
-                    ah[rb] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
-                    if constexpr (X3) {
-                        v = *reinterpret_cast<const uint4 *>(g.Cl + o);
-                        al[rb] = make_uint4(v.x & w, v.y & w, v.z & w, v.w & w);
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const v8bf a_h = __builtin_bit_cast(v8bf, acur[u][rb][0]);
+                        const v8bf a_l = __builtin_bit_cast(v8bf, acur[u][rb][NP - 1]);
+                        acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[u][rb][cb], 0, 0, 0);
+                        acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[u][rb][cb], 0, 0, 0);
+                        acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[u][rb][cb], 0, 0, 0);
                     }
-                }
+                } else {
+                    const v8h b16 = __builtin_bit_cast(v8h, braw);
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const uint4 braw = Bh[bbase + (cb * 16 * ldb + 32 * ks) / 8];
-                    if constexpr (X3) {
-                        const v8bf bh = __builtin_bit_cast(v8bf, braw);
-                        const v8bf bl = __builtin_bit_cast(
-                            v8bf, Bstore[s & 1][1][bbase + (cb * 16 * ldb + 32 * ks) / 8]);
-#pragma unroll
-                        for (int rb = 0; rb < RB; ++rb) {
-                            const v8bf a_h = __builtin_bit_cast(v8bf, ah[rb]);
-                            const v8bf a_l = __builtin_bit_cast(v8bf, al[rb]);
-                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[u][rb][cb], 0, 0, 0);
-                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[u][rb][cb], 0, 0, 0);
-                            acc[u][rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[u][rb][cb], 0, 0, 0);
-                        }
-                    } else {
-                        const v8h b16 = __builtin_bit_cast(v8h, braw);
-#pragma unroll
-                        for (int rb = 0; rb < RB; ++rb)
-                            part[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                __builtin_bit_cast(v8h, ah[rb]), b16, part[rb][cb], 0, 0, 0);
-                    }
+                    for (int rb = 0; rb < RB; ++rb)
+                        part[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            __builtin_bit_cast(v8h, acur[u][rb][0]), b16, part[rb][cb], 0, 0, 0);
                 }
             }
             if constexpr (!X3) {
-                const float cinv = g.Cinv[ti];
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
-                    const float f = Bsc[s & 1][cb * 16 + (lane & 15)] * cinv;
+                    const float f = Bsc[s & 1][cb * 16 + (lane & 15)] * ccur[u];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) acc[u][rb][cb] += part[rb][cb] * f;
                 }
@@ -1371,6 +1383,16 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
         }
         if (more) store_b((s + 1) & 1, breg, bscale);
         __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                ccur[u] = cnxt[u];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) acur[u][rb][q] = anxt[u][rb][q];
+            }
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -1943,6 +1965,7 @@ struct Plan {
     // per-level M2L schedule: the upward chain on `up`, one event per level
     bool m2l_early = false;
     bool m2l_block = false;             // 16-bit M2L by parent blocks (k_m2l_blk), no slot split
+    int m2l_cb = 4;                     // its 16-column blocks per workgroup (r-tile / 16)
     hipStream_t up = nullptr;
     hipEvent_t lev_ev[kMaxLevels] = {};
     DBuf<int32_t> work;
@@ -2007,6 +2030,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.m2l_layout >= 0 && op.m2l_layout <= 2, "m2l_layout must be 0, 1 or 2");
     BB_REQUIRE(op.m2l_schedule >= 0 && op.m2l_schedule <= 2, "m2l_schedule must be 0, 1 or 2");
     BB_REQUIRE(op.m2l_block >= 0 && op.m2l_block <= 2, "m2l_block must be 0, 1 or 2");
+    BB_REQUIRE(op.m2l_rtile == 0 || op.m2l_rtile == 16 || op.m2l_rtile == 32 || op.m2l_rtile == 64,
+               "m2l_rtile must be 0, 16, 32 or 64");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -2081,6 +2106,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     // from 16 columns on
     p->m2l_block = (o->precision == BBFMM_M2L_BF16X3 || o->precision == BBFMM_M2L_FP16_SCALED) &&
                    (op.m2l_block == 0 ? r >= 16 : op.m2l_block == 2);
+    // r-tile of the parent-block kernel: 16, 32 or 64 columns per workgroup
+    p->m2l_cb = op.m2l_rtile > 0 ? op.m2l_rtile / 16 : (r >= 48 ? 4 : (r > 16 ? 2 : 1));
     // split the slots until the launch has about m2l_min_waves workgroups per CU
     if (p->m2l_block) {
         p->nsplit = 1;                  // each block sums its whole halo
@@ -2213,6 +2240,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_layout = p->m2l_layout;
     out->m2l_schedule = p->m2l_early ? 2 : 1;
     out->m2l_block = p->m2l_block ? 2 : 1;
+    out->m2l_rtile = 16 * p->m2l_cb;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -2555,8 +2583,9 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
                                o.precision == BBFMM_M2L_BF16X3 ? set.Chi.p : set.C16.p, set.Clo.p,
                                set.Cinv.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p, t.lv[lvl - 1].cb.p,
                                t.lv[lvl - 1].ce.p, t.tables.p + 3 * kNumT + 8 * kSlots, kp, r};
-                const int CBv = r >= 48 ? 4 : (r > 16 ? 2 : 1);
-                const int RBv = (kp <= 32 || CBv == 4) ? 2 : 4;
+                const int CBv = p.m2l_cb;
+                const int RBv = (kp <= 32 || CBv == 4 ||
+                                 (CBv == 2 && o.precision == BBFMM_M2L_BF16X3)) ? 2 : 4;
                 dim3 gr(unsigned(t.lv[lvl - 1].C), unsigned(ceil_div(kp, 16 * RBv)),
                         unsigned(ceil_div(r, 16 * CBv)));
 #define BB_BLK(PR, RBc, CBc) k_m2l_blk<PR, RBc, CBc><<<gr, kThreads, p.m2l_pad_lds, st>>>(g)

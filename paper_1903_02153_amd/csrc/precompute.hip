@@ -21,6 +21,7 @@ namespace bbfmm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr double kMinSvdEps = 1e-7;    // smallest relative SVD threshold the Gram route resolves
 
 __device__ inline double kernel_eval_f64(int kid, double a, double dx, double dy, double dz) {
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -230,6 +231,126 @@ k_jacobi(double *A, double *Q, int m, int max_sweeps, double rel_tol, int *sweep
     if (tid == 0) *sweeps_out = sweep;
 }
 
+// The same cyclic Jacobi spread over the chip for larger m: one sweep is
+// m-1 rounds, each three launches -- the rotation angles of the round's m/2
+// disjoint pairs (from the matrix as it stands), then the row updates
+// A <- J^T A, then the column updates A <- A J and Q <- Q J, in which the
+// rotated pair's off-diagonal entries are set to zero.  Every element of a
+// launch has one writer (pairs are disjoint), so the result is the
+// single-workgroup schedule's.
+__global__ void __launch_bounds__(kThreads)
+k_jac_angles(const double *A, int m, int mp, int round, int32_t *pq, double *cs) {
+    const int np = mp / 2;
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= np) return;
+    const int a = (i == 0) ? 0 : 1 + (i - 1 + round) % (mp - 1);
+    const int b = 1 + (mp - 2 - i + round) % (mp - 1);
+    const int p = a < b ? a : b, q = a < b ? b : a;
+    double c = 1.0, s = 0.0;
+    if (q < m) {
+        const double apq = A[int64_t(p) * m + q];
+        if (apq != 0.0) {
+            const double app = A[int64_t(p) * m + p], aqq = A[int64_t(q) * m + q];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+        }
+    }
+    pq[2 * i] = p;
+    pq[2 * i + 1] = q < m ? q : -1;
+    cs[2 * i] = c;
+    cs[2 * i + 1] = s;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_jac_rows(double *A, int m, int np, const int32_t *pq, const double *cs) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= int64_t(np) * m) return;
+    const int i = int(g / m), k = int(g % m);
+    const int q = pq[2 * i + 1];
+    if (q < 0) return;
+    const int p = pq[2 * i];
+    const double c = cs[2 * i], s = cs[2 * i + 1];
+    const double x = A[int64_t(p) * m + k], y = A[int64_t(q) * m + k];
+    A[int64_t(p) * m + k] = c * x - s * y;
+    A[int64_t(q) * m + k] = s * x + c * y;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_jac_cols(double *A, double *Q, int m, int np, const int32_t *pq, const double *cs) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= int64_t(np) * m) return;
+    const int i = int(g / m), k = int(g % m);
+    const int q = pq[2 * i + 1];
+    if (q < 0) return;
+    const int p = pq[2 * i];
+    const double c = cs[2 * i], s = cs[2 * i + 1];
+    double x = A[int64_t(k) * m + p], y = A[int64_t(k) * m + q];
+    double np_ = c * x - s * y, nq = s * x + c * y;
+    if (s != 0.0) {                      // the rotated pair is zero by construction
+        if (k == q) np_ = 0.0;           // A[q][p]
+        if (k == p) nq = 0.0;            // A[p][q]
+    }
+    A[int64_t(k) * m + p] = np_;
+    A[int64_t(k) * m + q] = nq;
+    x = Q[int64_t(k) * m + p];
+    y = Q[int64_t(k) * m + q];
+    Q[int64_t(k) * m + p] = c * x - s * y;
+    Q[int64_t(k) * m + q] = s * x + c * y;
+}
+
+// off-diagonal and total squared mass of A (one workgroup)
+__global__ void __launch_bounds__(kJacobiThreads) k_offdiag(const double *A, int m, double *out) {
+    __shared__ double red[2][kJacobiThreads];
+    const int tid = threadIdx.x;
+    double off = 0.0, all = 0.0;
+    for (int64_t g = tid; g < int64_t(m) * m; g += kJacobiThreads) {
+        const double v = A[g] * A[g];
+        all += v;
+        if (g / m != g % m) off += v;
+    }
+    red[0][tid] = off;
+    red[1][tid] = all;
+    __syncthreads();
+    for (int st = kJacobiThreads / 2; st > 0; st >>= 1) {
+        if (tid < st) { red[0][tid] += red[0][tid + st]; red[1][tid] += red[1][tid + st]; }
+        __syncthreads();
+    }
+    if (tid == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
+}
+
+// m from which the multi-workgroup schedule is used
+constexpr int kJacobiWideFrom = 96;
+
+inline int jgrid(int64_t n) { return int((n + kThreads - 1) / kThreads); }
+
+int jacobi_wide(double *A, double *Q, int m, int max_sweeps, double rel_tol, hipStream_t s) {
+    const int mp = m + (m & 1), np = mp / 2;
+    DBuf<int32_t> pq(size_t(2 * np));
+    DBuf<double> cs(size_t(2 * np)), red(2);
+    double prev_off = INFINITY;
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        k_offdiag<<<1, kJacobiThreads, 0, s>>>(A, m, red.p);
+        BB_LAUNCH_CHECK();
+        double h[2] = {0.0, 0.0};
+        BB_HIP(hipMemcpyAsync(h, red.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        BB_HIP(hipStreamSynchronize(s));
+        // converged, or stalled at round-off level (the single-workgroup rule)
+        if (h[0] <= rel_tol * rel_tol * h[1] || (h[0] <= 1e-22 * h[1] && h[0] >= 0.25 * prev_off))
+            break;
+        prev_off = h[0];
+        for (int rd = 0; rd < mp - 1; ++rd) {
+            k_jac_angles<<<jgrid(np), kThreads, 0, s>>>(A, m, mp, rd, pq.p, cs.p);
+            k_jac_rows<<<jgrid(int64_t(np) * m), kThreads, 0, s>>>(A, m, np, pq.p, cs.p);
+            k_jac_cols<<<jgrid(int64_t(np) * m), kThreads, 0, s>>>(A, Q, m, np, pq.p, cs.p);
+        }
+        BB_LAUNCH_CHECK();
+    }
+    return sweep;
+}
+
 // eigenvalues (diagonal of A) in descending order -> sv = sqrt(max(l, 0)),
 // order[c] = index of the c-th largest; count[0] = #{l > eps^2 l_max}
 __global__ void __launch_bounds__(kThreads)
@@ -346,8 +467,13 @@ void gram_eig(DBuf<double> &G, DBuf<double> &Q, int m, double eps, DBuf<int32_t>
     k_identity<<<grid(int64_t(m) * m), kThreads, 0, s>>>(Q.p, m);
     BB_LAUNCH_CHECK();
     DBuf<int32_t> dsweeps(1), dcount(1);
-    k_jacobi<<<1, kJacobiThreads, 0, s>>>(G.p, Q.p, m, 60, 1e-14, dsweeps.p);
-    BB_LAUNCH_CHECK();
+    int wide_sweeps = -1;
+    if (m >= kJacobiWideFrom) {
+        wide_sweeps = jacobi_wide(G.p, Q.p, m, 60, 1e-14, s);
+    } else {
+        k_jacobi<<<1, kJacobiThreads, 0, s>>>(G.p, Q.p, m, 60, 1e-14, dsweeps.p);
+        BB_LAUNCH_CHECK();
+    }
     order.alloc(m);
     sv.alloc(m);
     BB_HIP(hipMemsetAsync(dcount.p, 0, sizeof(int32_t), s));
@@ -355,8 +481,10 @@ void gram_eig(DBuf<double> &G, DBuf<double> &Q, int m, double eps, DBuf<int32_t>
     BB_LAUNCH_CHECK();
     int32_t hc = 0, hs = 0;
     BB_HIP(hipMemcpyAsync(&hc, dcount.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    BB_HIP(hipMemcpyAsync(&hs, dsweeps.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (wide_sweeps < 0)
+        BB_HIP(hipMemcpyAsync(&hs, dsweeps.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BB_HIP(hipStreamSynchronize(s));
+    if (wide_sweeps >= 0) hs = wide_sweeps;
     BB_INTERNAL(hs < 60, "Jacobi eigensolver did not converge");
     count = hc;
 }
@@ -506,12 +634,21 @@ void cheb_setup(bbfmm_ops *ops, hipStream_t s) {
                 c.T[o][i][j] = float(h[2 * kMaxOrder + (o * kMaxOrder + i) * kMaxOrder + j]);
 }
 
-bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s) {
-    BB_REQUIRE(t != nullptr, "tree is NULL");
+void precompute_check(double eps, int precision) {
     BB_REQUIRE(std::isfinite(eps) && eps >= 0.0, "svd_eps must be finite and >= 0");
+    // the singular values come from eigenvalues of Gram matrices (sigma^2),
+    // which FP64 resolves down to about 1e-8 of the largest singular value:
+    // a threshold below kMinSvdEps would cut inside round-off
+    BB_REQUIRE(eps == 0.0 || eps >= kMinSvdEps || precision == BBFMM_M2L_FFT,
+               "svd_eps must be 0 (no compression) or >= %g", kMinSvdEps);
     BB_REQUIRE(precision == BBFMM_M2L_FP32 || precision == BBFMM_M2L_BF16X3 ||
                    precision == BBFMM_M2L_FP16_SCALED || precision == BBFMM_M2L_FFT,
                "unsupported M2L precision %d", precision);
+}
+
+bbfmm_ops *precompute_impl(const bbfmm_tree *t, double eps, int precision, hipStream_t s) {
+    precompute_check(eps, precision);
+    BB_REQUIRE(t != nullptr, "tree is NULL");
     std::unique_ptr<bbfmm_ops> ops(new bbfmm_ops());
     ops->nodes = precision == BBFMM_M2L_FFT ? 1 : 0;
     ops->tree = t;

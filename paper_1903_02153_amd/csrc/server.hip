@@ -136,6 +136,8 @@ struct Server {
     bool stop = false;
     std::string fatal;
 
+    int waiters = 0;                   // threads inside bbfmm_server_wait
+
     ~Server() {
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -145,6 +147,21 @@ struct Server {
         if (worker.joinable()) worker.join();
         for (Slot &s : slots)
             if (s.stream) (void)hipStreamSynchronize(s.stream);
+        {
+            // finish the batches that ran, cancel what never started, and
+            // let every thread blocked in wait return before anything it
+            // waits on is destroyed
+            std::unique_lock<std::mutex> lk(mu);
+            retire();
+            for (Request *rq : pending) {
+                rq->status = BBFMM_ERR_CANCELLED;
+                rq->error = "the server was destroyed before the request ran";
+                rq->done = true;
+            }
+            pending.clear();
+            cv_done.notify_all();
+            cv_done.wait(lk, [&] { return waiters == 0; });
+        }
         cache.clear();
         for (Slot &s : slots) {
             if (s.done) (void)hipEventDestroy(s.done);
@@ -444,7 +461,10 @@ bbfmm_status bbfmm_server_wait(bbfmm_server *sv, uint64_t request_id, bbfmm_requ
         auto it = s.requests.find(request_id);
         if (it == s.requests.end()) fail(BBFMM_ERR_NOT_FOUND, "unknown request %llu", (unsigned long long)request_id);
         Request *rq = it->second.get();
+        ++s.waiters;
         s.cv_done.wait(lk, [&] { return rq->done || !s.fatal.empty(); });
+        --s.waiters;
+        s.cv_done.notify_all();            // a destroy may be waiting for the waiters
         BB_REQUIRE(rq->done, "%s", s.fatal.c_str());
         if (stats) {
             stats->t_submit = rq->t_submit;
@@ -458,6 +478,33 @@ bbfmm_status bbfmm_server_wait(bbfmm_server *sv, uint64_t request_id, bbfmm_requ
         s.requests.erase(it);
         if (st != BBFMM_OK) fail(st, "%s", err.c_str());
         return BBFMM_OK;
+    } catch (const Exception &e) {
+        return e.status;
+    }
+}
+
+bbfmm_status bbfmm_server_cancel(bbfmm_server *sv, uint64_t request_id) {
+    bbfmm::clear_error();
+    try {
+        BB_REQUIRE(sv != nullptr, "server is NULL");
+        Server &s = *sv->impl;
+        std::lock_guard<std::mutex> lk(s.mu);
+        auto it = s.requests.find(request_id);
+        if (it == s.requests.end()) fail(BBFMM_ERR_NOT_FOUND, "unknown request %llu", (unsigned long long)request_id);
+        Request *rq = it->second.get();
+        for (auto p = s.pending.begin(); p != s.pending.end(); ++p)
+            if (*p == rq) {
+                s.pending.erase(p);
+                rq->status = BBFMM_ERR_CANCELLED;
+                rq->error = "cancelled";
+                rq->done = true;
+                rq->t_admit = rq->t_done = now_s();
+                ++s.st.requests_done;
+                s.cv_done.notify_all();
+                return BBFMM_OK;
+            }
+        fail(BBFMM_ERR_INVALID_ARG, "request %llu was already admitted (or is complete)",
+             (unsigned long long)request_id);
     } catch (const Exception &e) {
         return e.status;
     }

@@ -52,6 +52,9 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.bbfmm_build_tree(fake, 10, ctypes.byref(bad), None, None, ctypes.byref(out)) == 1
     assert out.value is None
     assert lib.bbfmm_precompute_operators(None, 1e-5, 0, None, None, ctypes.byref(out)) == 1
+    # thresholds the FP64 Gram route cannot resolve are refused before anything else
+    assert lib.bbfmm_precompute_operators(None, 1e-9, 0, None, None, ctypes.byref(out)) == 1
+    assert b"svd_eps" in lib.bbfmm_last_error()
     assert lib.bbfmm_plan_create(None, None, 1, ctypes.byref(out)) == 1
     assert lib.bbfmm_plan_execute(None, None, None, None) == 1
     info = bbfmm.TreeInfo()
@@ -84,7 +87,8 @@ def test_allocator_hook_checked_and_counters_without_gpu():
 @pytest.mark.parametrize("field,value", [("m2l_split", 9), ("m2l_min_waves", 17),
                                          ("p2p_max_split", 3), ("p2p_mfma", 3), ("overlap", -1),
                                          ("p2p_waves", -5), ("m2l_occupancy", 5),
-                                         ("m2l_layout", 3)])
+                                         ("m2l_layout", 3), ("m2l_schedule", 3),
+                                         ("m2l_block", -1), ("m2l_rtile", 48)])
 def test_plan_options_validated_without_gpu(field, value):
     """Every launch-shape option is range-checked before any handle or
     device memory is touched; the message names the option."""

@@ -447,3 +447,21 @@ def test_fft_m2l_polynomial_kernel_exact():
     go = bbfmm.precompute_operators(gt, 0.0, bbfmm.M2L_FFT)
     got = gpu_matvec(gt, go, sig)
     assert_parity(got, ofmm.direct(pts, sig, 100, 0.7), 1e-5, "FFT M2L polynomial kernel")
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_block_m2l_rtiles_agree(prec):
+    """The parent-block 16-bit M2L with 16, 32 and 64 right-hand sides per
+    workgroup (partial last tiles at r = 40): each column's products are
+    the same, summed in the same order, so the results are identical."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(15000, 260, r=40, kind="slab")
+    gt = gpu_tree(pts, bbfmm.K_GAUSS, 0.08, 5, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5, prec)
+    outs = [run_plan(gt, go, sig, m2l_block=2, m2l_rtile=rt).cpu().numpy() for rt in (16, 32, 64)]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ot = oracle_tree(pts, fixed_depth=5)
+    oo = oops.precompute(ot, 2, 0.08, 5, 1e-5)
+    ref = ofmm.matvec(ot, oo, pts, sig, 2, 0.08)
+    assert_parity(outs[0], ref, TOL if prec == 1 else 1e-3, f"block M2L r-tiles precision {prec}")

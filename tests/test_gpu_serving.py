@@ -92,3 +92,66 @@ def test_budget_rejects_oversized_request():
     with pytest.raises(bbfmm.BBFMMError, match="BUDGET"):
         srv.wait(rid)
     srv.close()
+
+
+def test_cancel_pending_and_destroy_with_waiter():
+    """A request still queued can be cancelled (its wait reports CANCELLED
+    and its phi is untouched); destroying the server while another thread
+    waits completes that wait (with a result or CANCELLED) before the
+    server's state is freed."""
+    import threading
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    models = _models()
+    t, o, n = models[1][0], models[1][1], models[1][2]
+    srv = bbfmm.Server(hbm_budget_bytes=4 << 30, max_inflight=1, r_max=32)
+    mid = srv.add(t, o)
+    sig = torch.randn(n, 8, device="cuda")
+    outs = [torch.full_like(sig, float("nan")) for _ in range(12)]
+    rids = [srv.submit(mid, sig, outs[q]) for q in range(12)]
+    cancelled = []
+    for q in reversed(range(12)):          # the latest are the likeliest still queued
+        try:
+            srv.cancel(rids[q])
+            cancelled.append(q)
+        except bbfmm.BBFMMError as e:
+            assert e.status == 1           # already admitted
+    for q in range(12):
+        if q in cancelled:
+            with pytest.raises(bbfmm.BBFMMError) as ei:
+                srv.wait(rids[q])
+            assert ei.value.status == 7
+            torch.cuda.synchronize()
+            assert torch.isnan(outs[q]).all()
+        else:
+            srv.wait(rids[q])
+            torch.cuda.synchronize()
+            assert torch.isfinite(outs[q]).all()
+    print(f"cancelled {len(cancelled)} of 12 queued requests")
+    with pytest.raises(bbfmm.BBFMMError):
+        srv.cancel(rids[0])                # already waited: unknown
+    # destroy while a thread waits
+    more = [srv.submit(mid, sig, torch.empty_like(sig)) for _ in range(6)]
+    seen = []
+    ready = [threading.Event() for _ in more]
+
+    def waiter(q, rid):
+        try:
+            ready[q].set()
+            srv.wait(rid)
+            seen.append("done")
+        except bbfmm.BBFMMError as e:
+            seen.append(e.status)
+
+    th = [threading.Thread(target=waiter, args=(q, rid)) for q, rid in enumerate(more)]
+    for x in th:
+        x.start()
+    for e in ready:
+        assert e.wait(30)
+    import time
+    time.sleep(0.5)                        # the waiters are inside bbfmm_server_wait
+    srv.close()
+    for x in th:
+        x.join(timeout=60)
+    assert not any(x.is_alive() for x in th)
+    assert len(seen) == 6 and all(v in ("done", 7) for v in seen), seen
