@@ -91,6 +91,11 @@ typedef struct {
                               most leaf_size points (>= 1)                          */
     int32_t max_depth;     /* cap on the number of levels incl. the root, 1..22     */
     int32_t fixed_depth;   /* > 0: use exactly this many levels (1..22)             */
+    int32_t adaptive;      /* 0: uniform tree (every leaf on the last level);
+                              1: level-adaptive (Section 2.1): a cell of at most
+                              leaf_size points is a leaf, on whatever level; the
+                              last level is the uniform tree's (depth rule or
+                              fixed_depth).  One point set only.                 */
 } bbfmm_tree_params;
 
 /*
@@ -136,6 +141,9 @@ typedef struct {
     int64_t n_targets;         /* rows of phi: N, or the targets of a tree over
                                   separate sets                                   */
     int64_t n_sources;         /* rows of sigma: N, or the sources                 */
+    int32_t adaptive;          /* 1 for a level-adaptive tree                      */
+    int32_t n_leaves;          /* leaves on all levels                             */
+    int64_t w_entries;         /* W-list entries (adaptive trees; 0 otherwise)     */
 } bbfmm_tree_info;
 
 /*
@@ -143,8 +151,14 @@ typedef struct {
  * Definition 2.1).
  *   points  device, N x 3 float32 row-major, original order; read only.
  *   n       number of points, >= 1 and < 2^31.
- * The tree is uniform: every leaf sits on level depth-1; empty cells are not
- * stored.  Binning: q_d = clamp(floor((x_d - lo_d) * scale), 0, 2^21-1) in
+ * The tree is uniform (every leaf on level depth-1) unless params->adaptive
+ * is set; empty cells are not stored.  A level-adaptive tree is the uniform
+ * tree with the descendants of every cell of at most leaf_size points
+ * removed (trailing empty levels dropped), and carries the lists of the
+ * adaptive FMM: U (adjacent leaves, near field), V (Definition 2.1, M2L),
+ * W (cells finer than a leaf, not adjacent to it, whose parent is: their
+ * multipole expansions are evaluated at the leaf's points) and X (the dual
+ * of W: a coarser leaf's points feed the local expansion of a cell).  Binning: q_d = clamp(floor((x_d - lo_d) * scale), 0, 2^21-1) in
  * float32 (one rounding per operation), the level-l coordinate is
  * q_d >> (21-l); points are ordered by a stable sort of the Morton leaf key
  * (bit b of x, y, z at bits 3b, 3b+1, 3b+2).  Also built: the leaf
@@ -190,12 +204,24 @@ enum {
     BBFMM_TA_PARENT = 4,    /* int32[C_l]: parent index on level l-1 (-1 at root)  */
     BBFMM_TA_CB = 5,        /* int32[C_l]: first child on level l+1 (-1 on leaves) */
     BBFMM_TA_CE = 6,        /* int32[C_l]: one past the last child                 */
-    BBFMM_TA_NBR_OFF = 7,   /* int32[C_L+1]: leaf neighbour CSR offsets            */
-    BBFMM_TA_NBR_IDX = 8,   /* int32[nnz]: neighbours, ascending cell index        */
+    BBFMM_TA_NBR_OFF = 7,   /* int32[C_L+1]: leaf neighbour CSR offsets (adaptive
+                               trees: int32[NL+1], the U lists over the leaf table) */
+    BBFMM_TA_NBR_IDX = 8,   /* int32[nnz]: neighbours, ascending cell index (adaptive
+                               trees: ascending leaf-table index)                   */
     BBFMM_TA_PAIR_T = 9,    /* int32[P_l]: transfer-vector index 0..315 per pair   */
     BBFMM_TA_PAIR_TGT = 10, /* int32[P_l]: target cell of each pair                */
     BBFMM_TA_PAIR_SRC = 11, /* int32[P_l]: source cell of each pair                */
-    BBFMM_TA_PAIR_GOFF = 12 /* int32[317]: group offsets by transfer vector        */
+    BBFMM_TA_PAIR_GOFF = 12,/* int32[317]: group offsets by transfer vector        */
+    BBFMM_TA_LEAF_LEVEL = 13,/* int32[NL]: level of each leaf (leaf table: by level,
+                                then cell index)                                    */
+    BBFMM_TA_LEAF_CELL = 14,/* int32[NL]: cell index of each leaf on its level     */
+    BBFMM_TA_W_OFF = 15,    /* int32[NL+1]: W-list CSR offsets (adaptive trees)    */
+    BBFMM_TA_W_LEVEL = 16,  /* int32[nW]: level of each W cell, ascending (level,
+                               cell) per row                                       */
+    BBFMM_TA_W_CELL = 17,   /* int32[nW]: cell index of each W cell                */
+    BBFMM_TA_X_OFF = 18,    /* int32[C_l+1]: X-list CSR offsets of level l         */
+    BBFMM_TA_X_LEAF = 19    /* int32[nX_l]: leaf-table index of each X leaf,
+                               ascending per row                                   */
 };
 
 /*

@@ -13,8 +13,9 @@ Readings taken:
     binning, depth rule and point order) with every cell that holds at most
     ``leaf_size`` points made a leaf and its descendants removed.  The
     finest level keeps the uniform tree's leaf level, so a cell on it is a
-    leaf whatever its count.  Every cell is a contiguous range of the sorted
-    points, and the cells of each level stay in ascending key order.
+    leaf whatever its count; trailing levels left without cells are dropped.
+    Every cell is a contiguous range of the sorted points, and the cells of
+    each level stay in ascending key order.
   * Cells A and B are adjacent when their closed boxes touch or overlap (on
     any level pair).  The lists are the standard ones of the adaptive FMM
     (Greengard-Rokhlin / the kernel-independent FMM), stated for the
@@ -107,6 +108,10 @@ def build_adaptive_tree(points: np.ndarray, leaf_size: int = 64, max_depth: int 
         if lvl < F:
             child = ut.levels[lvl + 1]
             keep.append(keep[lvl][child.parent] & ~lf[child.parent])
+    # levels left without cells (every cell above them a leaf) are dropped
+    while D > 1 and not keep[D - 1].any():
+        D -= 1
+    F = D - 1
     levels: List[ALevel] = []
     new_index = []
     for lvl in range(D):
@@ -187,8 +192,10 @@ def _points(tr: ATree, level: int, cell: int) -> np.ndarray:
 
 
 def matvec(tr: ATree, ops: Optional[Ops], points: np.ndarray, sigma: np.ndarray,
-           kernel_id: int, param: float, rows: Optional[np.ndarray] = None) -> np.ndarray:
-    """phi ~ K sigma over the adaptive tree, FP64; (len(rows) or N, r)."""
+           kernel_id: int, param: float, rows: Optional[np.ndarray] = None,
+           near: bool = True, far: bool = True) -> np.ndarray:
+    """phi ~ K sigma over the adaptive tree, FP64; (len(rows) or N, r).
+    near / far: include the U-list direct sums / everything else."""
     pts = np.asarray(points, dtype=np.float32).astype(np.float64)
     sig = np.asarray(sigma, dtype=np.float64)
     sig = sig[:, None] if sig.ndim == 1 else sig
@@ -248,14 +255,15 @@ def matvec(tr: ATree, ops: Optional[Ops], points: np.ndarray, sigma: np.ndarray,
         i = _points(tr, lvl, b)
         if len(i) == 0:
             continue
-        if lvl >= 2:
+        if far and lvl >= 2:
             Sx = cheb.lagrange_3d(n, (Y[i] - tr.centers(lvl)[b]) / tr.half_width(lvl), kind)
             out_sorted[i] += Sx @ Fl[lvl][b]
-        for (la, ca) in tr.W[q]:
+        for (la, ca) in (tr.W[q] if far else []):
             out_sorted[i] += direct_sum(Y[i], _nodes(tr, n, kind, int(la), int(ca)),
                                         M[int(la)][int(ca)], kernel_id, param)
-        src = np.concatenate([_points(tr, int(la), int(ca)) for la, ca in tr.U[q]])
-        out_sorted[i] += direct_sum(Y[i], Y[src], S[src], kernel_id, param)
+        if near:
+            src = np.concatenate([_points(tr, int(la), int(ca)) for la, ca in tr.U[q]])
+            out_sorted[i] += direct_sum(Y[i], Y[src], S[src], kernel_id, param)
     out = np.empty((N, r))
     out[tr.perm] = out_sorted
     return out if rows is None else out[np.asarray(rows)]

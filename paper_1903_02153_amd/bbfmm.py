@@ -23,7 +23,8 @@ K_INV_R, K_EXP, K_GAUSS, K_DIPOLE_X, K_POLY_TEST = 0, 1, 2, 3, 100
 M2L_FP32, M2L_BF16X3, M2L_FP16_SCALED, M2L_FFT = 0, 1, 2, 3
 
 TA = dict(perm=0, keys=1, pb=2, pe=3, parent=4, cb=5, ce=6, nbr_off=7, nbr_idx=8,
-          pair_t=9, pair_tgt=10, pair_src=11, pair_goff=12)
+          pair_t=9, pair_tgt=10, pair_src=11, pair_goff=12, leaf_level=13, leaf_cell=14,
+          w_off=15, w_level=16, w_cell=17, x_off=18, x_leaf=19)
 _TA_DTYPE = dict(keys=np.uint64)
 OA = dict(U=0, V=1, C=2, sv_fat=3, sv_thin=4)
 STAGES = ("gather", "p2m", "m2m", "m2l", "down", "p2p")
@@ -41,7 +42,8 @@ class BBFMMError(RuntimeError):
 class TreeParams(ctypes.Structure):
     _fields_ = [("kernel_id", ctypes.c_int32), ("kernel_param", ctypes.c_double),
                 ("cheb_order", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
-                ("max_depth", ctypes.c_int32), ("fixed_depth", ctypes.c_int32)]
+                ("max_depth", ctypes.c_int32), ("fixed_depth", ctypes.c_int32),
+                ("adaptive", ctypes.c_int32)]
 
 
 class TreeInfo(ctypes.Structure):
@@ -51,7 +53,9 @@ class TreeInfo(ctypes.Structure):
                 ("side", ctypes.c_float), ("scale", ctypes.c_float),
                 ("max_leaf_points", ctypes.c_int32), ("cells", ctypes.c_int32 * 22),
                 ("pairs", ctypes.c_int64 * 22), ("near_pairs", ctypes.c_int64),
-                ("n_targets", ctypes.c_int64), ("n_sources", ctypes.c_int64)]
+                ("n_targets", ctypes.c_int64), ("n_sources", ctypes.c_int64),
+                ("adaptive", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
+                ("w_entries", ctypes.c_int64)]
 
 
 class RequestStats(ctypes.Structure):
@@ -385,10 +389,13 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
                cheb_order: int = 4, leaf_size: int = 64, max_depth: int = 22,
-               fixed_depth: int = 0, stream=None, allocator="torch", sources=None) -> Tree:
+               fixed_depth: int = 0, stream=None, allocator="torch", sources=None,
+               adaptive: bool = False) -> Tree:
     """Octree over the bounding cube of ``points`` ((N,3) float32 on the GPU).
     sources: a second (M,3) set; then ``points`` are the targets, products
     take sigma of M rows and give phi of N rows (bbfmm_build_tree_sets).
+    adaptive: a level-adaptive tree (a cell of at most leaf_size points is a
+    leaf on whatever level; one point set only).
     allocator: "torch" (torch's caching allocator owns the library's device
     memory; the default), a TorchAllocator, or None (hipMalloc)."""
     for name, pts in (("points", points), ("sources", sources)):
@@ -397,7 +404,8 @@ def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,
     _device_f32(points, "points")
     if allocator == "torch":
         allocator = torch_allocator()
-    p = TreeParams(kernel_id, kernel_param, cheb_order, leaf_size, max_depth, fixed_depth)
+    p = TreeParams(kernel_id, kernel_param, cheb_order, leaf_size, max_depth, fixed_depth,
+                   1 if adaptive else 0)
     h = _VP()
     if sources is None:
         _check(lib().bbfmm_build_tree(points.data_ptr(), points.shape[0], ctypes.byref(p),

@@ -205,6 +205,9 @@ bbfmm_status bbfmm_tree_info_get(const bbfmm_tree *t, bbfmm_tree_info *out) {
         out->near_pairs = t->near_pairs;
         out->n_targets = t->n_out();
         out->n_sources = t->n_in();
+        out->adaptive = t->adaptive ? 1 : 0;
+        out->n_leaves = t->leaves().C;
+        out->w_entries = t->w_nnz;
     });
 }
 
@@ -212,14 +215,18 @@ bbfmm_status bbfmm_tree_export(const bbfmm_tree *t, int32_t what, int32_t level,
                                int64_t capacity, int64_t *size) {
     return guarded([&] {
         BB_REQUIRE(t != nullptr, "tree is NULL");
-        const bool per_level = what >= BBFMM_TA_KEYS && what <= BBFMM_TA_CE;
+        const bool per_level = (what >= BBFMM_TA_KEYS && what <= BBFMM_TA_CE) ||
+                               what == BBFMM_TA_X_OFF || what == BBFMM_TA_X_LEAF;
         const bool pair = what >= BBFMM_TA_PAIR_T && what <= BBFMM_TA_PAIR_GOFF;
         if (per_level || pair) {
             if (level < 0 || level >= t->depth || (pair && level < 2))
                 fail(BBFMM_ERR_NOT_FOUND, "level %d has no such array", level);
         }
+        const bool adaptive_only = what >= BBFMM_TA_W_OFF && what <= BBFMM_TA_X_LEAF;
+        if (adaptive_only && !t->adaptive)
+            fail(BBFMM_ERR_NOT_FOUND, "tree array %d exists on level-adaptive trees only", what);
         const LevelData *lv = (per_level || pair) ? &t->lv[level] : nullptr;
-        const int L = t->leaf_level();
+        const int64_t NL = t->leaves().C;
         switch (what) {
         case BBFMM_TA_PERM: copy_out(t->perm.p, t->n, dst, capacity, size); break;
         case BBFMM_TA_KEYS: copy_out(lv->keys.p, lv->C, dst, capacity, size); break;
@@ -228,12 +235,25 @@ bbfmm_status bbfmm_tree_export(const bbfmm_tree *t, int32_t what, int32_t level,
         case BBFMM_TA_PARENT: copy_out(lv->parent.p, lv->C, dst, capacity, size); break;
         case BBFMM_TA_CB: copy_out(lv->cb.p, lv->C, dst, capacity, size); break;
         case BBFMM_TA_CE: copy_out(lv->ce.p, lv->C, dst, capacity, size); break;
-        case BBFMM_TA_NBR_OFF: copy_out(t->nbr_off.p, int64_t(t->lv[L].C) + 1, dst, capacity, size); break;
+        case BBFMM_TA_NBR_OFF: copy_out(t->nbr_off.p, NL + 1, dst, capacity, size); break;
         case BBFMM_TA_NBR_IDX: copy_out(t->nbr_idx.p, t->nbr_nnz, dst, capacity, size); break;
         case BBFMM_TA_PAIR_T: copy_out(lv->pair_t.p, lv->npairs, dst, capacity, size); break;
         case BBFMM_TA_PAIR_TGT: copy_out(lv->pair_tgt.p, lv->npairs, dst, capacity, size); break;
         case BBFMM_TA_PAIR_SRC: copy_out(lv->pair_src.p, lv->npairs, dst, capacity, size); break;
         case BBFMM_TA_PAIR_GOFF: copy_out(lv->pair_goff.p, int64_t(kNumT) + 1, dst, capacity, size); break;
+        case BBFMM_TA_LEAF_LEVEL: copy_out(t->fl_level.p, NL, dst, capacity, size); break;
+        case BBFMM_TA_LEAF_CELL: copy_out(t->fl_cell.p, NL, dst, capacity, size); break;
+        case BBFMM_TA_W_OFF: copy_out(t->w_off.p, NL + 1, dst, capacity, size); break;
+        case BBFMM_TA_W_LEVEL: copy_out(t->w_level.p, t->w_nnz, dst, capacity, size); break;
+        case BBFMM_TA_W_CELL: copy_out(t->w_cell.p, t->w_nnz, dst, capacity, size); break;
+        case BBFMM_TA_X_OFF: copy_out(lv->x_off.p, int64_t(lv->C) + 1, dst, capacity, size); break;
+        case BBFMM_TA_X_LEAF: {
+            int32_t nx = 0;
+            if (lv->C > 0)
+                BB_HIP(hipMemcpy(&nx, lv->x_off.p + lv->C, sizeof(int32_t), hipMemcpyDeviceToHost));
+            copy_out(lv->x_leaf.p, nx, dst, capacity, size);
+            break;
+        }
         default: fail(BBFMM_ERR_NOT_FOUND, "unknown tree array %d", what);
         }
     });

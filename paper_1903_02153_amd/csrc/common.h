@@ -145,6 +145,13 @@ struct LevelData {
     int32_t oct_off[9] = {0};       // group boundaries in oct_cells
     int64_t npairs = 0;
     DBuf<int32_t> pair_t, pair_tgt, pair_src, pair_goff;
+    // level-adaptive trees only
+    DBuf<int32_t> isleaf;           // [C]: 1 for a leaf
+    DBuf<int32_t> flat;             // [C]: index in the tree's leaf table, -1 if not a leaf
+    int32_t nleaf = 0, leaf0 = 0;   // leaves of this level: leaf table [leaf0, leaf0 + nleaf)
+    DBuf<int32_t> x_off, x_leaf;    // X lists: CSR over the cells, leaf-table indices
+    DBuf<int32_t> x_cells;          // cells whose X list is not empty
+    int32_t nx_cells = 0;
 };
 
 }  // namespace bbfmm
@@ -172,9 +179,20 @@ struct bbfmm_tree {
     bbfmm::DBuf<int32_t> leaf_sb, leaf_te;      // per leaf, only with separate sets
     std::vector<int32_t> leaf_te_h;             // host copy of the target ends (pe for one set)
     bbfmm_allocator hook{};         // allocator of the tree, inherited by its operators and plans
+    // Level-adaptive tree: leaves on every level, gathered in one leaf table
+    // (by level, then cell) on which the near field runs; nbr_off / nbr_idx
+    // are then the U lists over that table.  W lists (per leaf) name cells
+    // of any level >= 2; X lists live on the levels.
+    bool adaptive = false;
+    bbfmm::LevelData fleaf;         // C, keys, pb, pe of the leaf table
+    bbfmm::DBuf<int32_t> fl_level, fl_cell;
+    bbfmm::DBuf<int32_t> w_off, w_level, w_cell;
+    int64_t w_nnz = 0;
     int leaf_level() const { return depth - 1; }
-    const int32_t *src_begin() const { return n_targets ? leaf_sb.p : lv[depth - 1].pb.p; }
-    const int32_t *tgt_end() const { return n_targets ? leaf_te.p : lv[depth - 1].pe.p; }
+    // the leaves the near field and the leaf stages run over
+    const bbfmm::LevelData &leaves() const { return adaptive ? fleaf : lv[depth - 1]; }
+    const int32_t *src_begin() const { return n_targets ? leaf_sb.p : leaves().pb.p; }
+    const int32_t *tgt_end() const { return n_targets ? leaf_te.p : leaves().pe.p; }
     int64_t n_out() const { return n_targets ? n_targets : n; }          // rows of phi
     int64_t n_in() const { return n - n_targets; }                       // rows of sigma
     double half_width(int level) const { return double(side) / double(1ull << (level + 1)); }

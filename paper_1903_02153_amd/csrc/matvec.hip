@@ -184,8 +184,8 @@ struct NodeIdx {
 template <int N>
 __global__ void __launch_bounds__(64)
 k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-      const uint64_t *keys, int nleaf, Geo geo, ChebConst cc, const float *sig_s, int ld, int r,
-      int mp, float *M) {
+      const uint64_t *keys, const int32_t *rows, int nleaf, Geo geo, ChebConst cc,
+      const float *sig_s, int ld, int r, int mp, float *M) {
     constexpr int m = N * N * N, NP = N * N, G = 64 / NP;
     __shared__ float wx[G][64][N], wy[G][64][N], wz[G][64][N];   // Lx sigma, Ly, Lz per point
     const int lane = threadIdx.x;
@@ -252,7 +252,8 @@ k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
         }
     }
     if (g < G && a0 + g < nleaf) {
-        float *out = M + (int64_t(a0 + g) * r + c) * mp;
+        const int row = rows != nullptr ? rows[a0 + g] : a0 + g;
+        float *out = M + (int64_t(row) * r + c) * mp;
 #pragma unroll
         for (int k = 0; k < N; ++k) out[pq * N + k] = acc[k];
         for (int i = m + pq; i < mp; i += NP) out[i] = 0.f;
@@ -268,8 +269,8 @@ k_p2m(const float *xs, const float *ys, const float *zs, const int32_t *pb, cons
 template <int N, int NCB>
 __global__ void __launch_bounds__(kThreads)
 k_p2m_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb, const int32_t *pe,
-           const uint64_t *keys, Geo geo, ChebConst cc, const float *sig_s, int ld, int r, int mp,
-           float *M) {
+           const uint64_t *keys, const int32_t *rows, Geo geo, ChebConst cc, const float *sig_s,
+           int ld, int r, int mp, float *M) {
     constexpr int m = N * N * N;
     constexpr int NRBT = (m + 15) / 16;         // 16-node row blocks (mp = 16 NRBT)
     constexpr int RBQ = (NRBT + 3) / 4;         // row blocks per wave
@@ -343,6 +344,7 @@ k_p2m_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
         }
     }
     // D[i][j] sits in lane j + 16 (i / 4), register i % 4: four consecutive nodes
+    const int row = rows != nullptr ? rows[a] : a;
 #pragma unroll
     for (int q = 0; q < RBQ; ++q) {
         if (wave + 4 * q >= NRBT) break;
@@ -351,7 +353,7 @@ k_p2m_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
         for (int cb = 0; cb < NCB; ++cb) {
             const int c = col0 + cb * 16 + (lane & 15);
             if (c < r)
-                *reinterpret_cast<float4 *>(M + (int64_t(a) * r + c) * mp + node0) =
+                *reinterpret_cast<float4 *>(M + (int64_t(row) * r + c) * mp + node0) =
                     make_float4(acc[q][cb][0], acc[q][cb][1], acc[q][cb][2], acc[q][cb][3]);
         }
     }
@@ -432,6 +434,7 @@ k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *
         i3[q] = (i / (N * N)) % N;
     }
     const int c0 = cb[P], nc = min(ce[P] - c0, 8);
+    if (nc <= 0) return;        // a leaf above the last level: P2M writes its coefficients
     float v[8][Q];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -1893,6 +1896,136 @@ k_l2p(const float *xs, const float *ys, const float *zs, const int32_t *pleaf, c
     }
 }
 
+// ------------------------------------------ level-adaptive tree stages ----
+// Chebyshev node i of a cell (key on a level of half-width h), in kernel
+// coordinates (times the kernel's coordinate scale cs).
+template <int N>
+__device__ inline void node_coords(const ChebConst &cc, const float *lo, uint64_t key, float h,
+                                   float cs, int i, float *out) {
+    const int id[3] = {i % N, (i / N) % N, i / (N * N)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float chi, clo;
+        center_pair(lo[d], compact3(key >> d), h, chi, clo);
+        out[d] = (chi + __fmaf_rn(h, cc.s[id[d]], clo)) * cs;
+    }
+}
+
+// P2L over the X lists of one level: F[cell][c][i] += sum over the points
+// y_j of the cell's X leaves of K(x*_i, y_j) sigma_j[c], x*_i the cell's
+// Chebyshev nodes (the local expansion holds the far field at the nodes).
+// One wave per (cell with an X list, column); lanes own nodes, sources are
+// staged 64 at a time.
+template <int N, int KID>
+__global__ void __launch_bounds__(64)
+k_p2l(const int32_t *xcells, const int32_t *xoff, const int32_t *xleaf, const int32_t *lpb,
+      const int32_t *lpe, const uint64_t *keys, const float *xs, const float *ys, const float *zs,
+      const float *sig_s, int ld, Geo geo, ChebConst cc, float cs, int r, int mp, float *F) {
+    constexpr int m = N * N * N, Q = (m + 63) / 64;
+    __shared__ float4 sp[64];
+    const int lane = threadIdx.x;
+    const int cell = xcells[blockIdx.x], c = blockIdx.y;
+    const uint64_t key = keys[cell];
+    float nx[Q][3], acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        node_coords<N>(cc, geo.lo, key, geo.h, cs, min(lane + 64 * q, m - 1), nx[q]);
+        acc[q] = 0.f;
+    }
+    for (int e = xoff[cell]; e < xoff[cell + 1]; ++e) {
+        const int a = xleaf[e], b = lpb[a], en = lpe[a];
+        for (int p0 = b; p0 < en; p0 += 64) {
+            const int np = min(64, en - p0);
+            __syncthreads();                       // previous chunk consumed
+            if (lane < np) {
+                const int j = p0 + lane;
+                sp[lane] = make_float4(xs[j] * cs, ys[j] * cs, zs[j] * cs, sig_s[int64_t(j) * ld + c]);
+            }
+            __syncthreads();
+            for (int j = 0; j < np; ++j) {
+                const float4 y = sp[j];
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    acc[q] += kernel_eval<KID>(nx[q][0] - y.x, nx[q][1] - y.y, nx[q][2] - y.z) * y.w;
+            }
+        }
+    }
+    float *f = F + (int64_t(cell) * r + c) * mp;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + 64 * q < m) f[lane + 64 * q] += acc[q];
+}
+
+// Per-level arrays of a plan over a level-adaptive tree, by value.
+struct LevelExp {
+    const float *F[kMaxLevels];      // local expansions (levels >= 2)
+    const float *M[kMaxLevels];      // multipole expansions (levels >= 2)
+    const uint64_t *keys[kMaxLevels];
+    float h[kMaxLevels], inv_h[kMaxLevels];
+};
+
+// The far field at the points of every leaf of a level-adaptive tree, added
+// to phi after the near field: L2P from the leaf's local expansion (leaves on
+// levels >= 2) and M2P over its W list, phi(x) += sum_i K(x, y*_i) M_A[i]
+// with y*_i the Chebyshev nodes of cell A.  One wave per (leaf, column);
+// lanes own targets; a W cell's nodes and coefficients are staged in LDS.
+template <int N, int KID>
+__global__ void __launch_bounds__(64)
+k_leaf_far(const int32_t *lpb, const int32_t *lpe, const uint64_t *lkey, const int32_t *llev,
+           const int32_t *lcell, const int32_t *woff, const int32_t *wlev, const int32_t *wcell,
+           LevelExp X, const float *xs, const float *ys, const float *zs, const int32_t *perm,
+           Geo geo, ChebConst cc, float cs, int r, int mp, float *phi) {
+    constexpr int m = N * N * N, Q = (m + 63) / 64;
+    __shared__ float4 nd[64 * Q];        // a W cell: node coordinates (kernel units), M
+    __shared__ float fs[64 * Q];         // the leaf's local expansion
+    const int lane = threadIdx.x;
+    const int q = blockIdx.x, c = blockIdx.y;
+    const int lv = llev[q], b = lpb[q], e = lpe[q];
+    const uint64_t key = lkey[q];
+    const int w0 = woff[q], w1 = woff[q + 1];
+    if (lv >= 2) {
+        const float *f = X.F[lv] + (int64_t(lcell[q]) * r + c) * mp;
+        for (int i = lane; i < m; i += 64) fs[i] = f[i];
+    }
+    for (int p0 = b; p0 < e; p0 += 64) {
+        const int i = p0 + lane;
+        const bool valid = i < e;
+        const int ii = valid ? i : b;
+        const float x = xs[ii], y = ys[ii], z = zs[ii];
+        float acc = 0.f;
+        __syncthreads();                         // fs written, nd of the last chunk consumed
+        if (lv >= 2) {
+            float l[3][N];
+            const float p3[3] = {x, y, z};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                float chi, clo;
+                center_pair(geo.lo[d], compact3(key >> d), X.h[lv], chi, clo);
+                lagrange_t<N>(cc, local_coord(p3[d], chi, clo, X.inv_h[lv]), l[d]);
+            }
+            acc = l2p_sum<N>(fs, l);
+        }
+        const float xc = x * cs, yc = y * cs, zc = z * cs;
+        for (int w = w0; w < w1; ++w) {
+            const int la = wlev[w], a = wcell[w];
+            const uint64_t ka = X.keys[la][a];
+            const float *M = X.M[la] + (int64_t(a) * r + c) * mp;
+            __syncthreads();                     // previous W cell consumed
+            for (int k = lane; k < m; k += 64) {
+                float t[3];
+                node_coords<N>(cc, geo.lo, ka, X.h[la], cs, k, t);
+                nd[k] = make_float4(t[0], t[1], t[2], M[k]);
+            }
+            __syncthreads();
+            for (int k = 0; k < m; ++k) {
+                const float4 v = nd[k];
+                acc += kernel_eval<KID>(xc - v.x, yc - v.y, zc - v.z) * v.w;
+            }
+        }
+        if (valid) phi[int64_t(perm[i]) * r + c] += acc;
+    }
+}
+
 // pleaf[i] = leaf holding point i (tree order)
 __global__ void __launch_bounds__(kThreads)
 k_point_leaf(const int32_t *pb, const int32_t *pe, int nleaf, int32_t *pleaf) {
@@ -2035,6 +2168,10 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
+    // the near field's launch lists index the leaf table through the host copies
+    BB_INTERNAL(t->leaf_pb_h.size() == size_t(t->leaves().C) &&
+                    t->leaf_te_h.size() == size_t(t->leaves().C),
+                "leaf ranges do not match the tree's leaves");
     std::unique_ptr<Plan> p(new Plan());
     p->tree = t;
     p->ops = o;
@@ -2141,7 +2278,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     if (p->p2p_mfma) {
         // MFMA near field: one wave per (leaf, up to 64 consecutive
         // targets), grouped by the number of 16-row blocks they need
-        const LevelData &leaf = t->lv[L];
+        const LevelData &leaf = t->leaves();
         const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_te_h;   // targets of a leaf
         std::vector<int32_t> &w = p->h_work;
         for (int nrb = 1; nrb <= 4; ++nrb) {
@@ -2162,7 +2299,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         // per-lane P2P work items (leaf, first target, log2 S): leaves of at
         // most 64 points take one wave with 64 / next_pow2(count) sub-lanes
         // per target
-        const LevelData &leaf = t->lv[L];
+        const LevelData &leaf = t->leaves();
         const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_te_h;   // targets of a leaf
         std::vector<int32_t> &w = p->h_work;
         for (int a = 0; a < leaf.C; ++a) {
@@ -2203,11 +2340,14 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         p->m2l_pad_lds = per_wg > fa.sharedSizeBytes ? per_wg - fa.sharedSizeBytes : 0;
     }
     if (p->overlap) {
-        const LevelData &leaf = t->lv[L];
-        p->pleaf.alloc(t->n);
-        ws += p->pleaf.bytes();
-        k_point_leaf<<<grid(leaf.C), kThreads, 0, setup>>>(leaf.pb.p, leaf.pe.p, leaf.C, p->pleaf.p);
-        BB_LAUNCH_CHECK();
+        if (!t->adaptive) {         // k_l2p after the join (adaptive trees: k_leaf_far)
+            const LevelData &leaf = t->lv[L];
+            p->pleaf.alloc(t->n);
+            ws += p->pleaf.bytes();
+            k_point_leaf<<<grid(leaf.C), kThreads, 0, setup>>>(leaf.pb.p, leaf.pe.p, leaf.C,
+                                                               p->pleaf.p);
+            BB_LAUNCH_CHECK();
+        }
         p->side = acquire_side_stream();
         p->fork = make_event(hipEventDisableTiming);
         p->join = make_event(hipEventDisableTiming);
@@ -2284,7 +2424,7 @@ void harvest_one(Plan &p) {
 template <int KID>
 void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipStream_t s) {
     const bbfmm_tree &t = *p.tree;
-    const LevelData &leaf = t.lv[t.leaf_level()];
+    const LevelData &leaf = t.leaves();
     const double a = t.params.kernel_param;
     const float cs = coord_scale(t.params.kernel_id, a);
     if (p.p2p_mfma) {
@@ -2332,6 +2472,45 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
     }
 #undef BB_P2P
     BB_LAUNCH_CHECK();
+}
+
+// L2P + M2P at every leaf of a level-adaptive tree (k_leaf_far)
+template <int KID>
+void launch_leaf_far(const Plan &p, const Geo &geo, float *phi, hipStream_t s) {
+    const bbfmm_tree &t = *p.tree;
+    const LevelData &fl = t.leaves();
+    if (fl.C == 0) return;
+    LevelExp X{};
+    for (int l = 0; l < t.depth; ++l) {
+        X.keys[l] = t.lv[l].keys.p;
+        X.h[l] = float(t.half_width(l));
+        X.inv_h[l] = 1.0f / X.h[l];
+        if (l >= 2) {
+            X.F[l] = p.F[l].p;
+            X.M[l] = p.M[l].p;
+        }
+    }
+    const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
+    const int mp = p.ops->mp, r = int(p.r);
+    dim3 g(unsigned(fl.C), unsigned(r));
+#define BB_LF(NN) case NN: k_leaf_far<NN, KID><<<g, 64, 0, s>>>(fl.pb.p, fl.pe.p, fl.keys.p,       \
+        t.fl_level.p, t.fl_cell.p, t.w_off.p, t.w_level.p, t.w_cell.p, X, t.xs.p, t.ys.p, t.zs.p, \
+        t.perm.p, geo, p.ops->cheb, cs, r, mp, phi); break;
+    switch (p.ops->n) {
+    BB_LF(2) BB_LF(3) BB_LF(4) BB_LF(5) BB_LF(6) BB_LF(7) BB_LF(8)
+    }
+#undef BB_LF
+    BB_LAUNCH_CHECK();
+}
+
+void leaf_far(const Plan &p, const Geo &geo, float *phi, hipStream_t s) {
+    switch (p.tree->params.kernel_id) {
+    case BBFMM_K_INV_R: launch_leaf_far<BBFMM_K_INV_R>(p, geo, phi, s); break;
+    case BBFMM_K_EXP: launch_leaf_far<BBFMM_K_EXP>(p, geo, phi, s); break;
+    case BBFMM_K_GAUSS: launch_leaf_far<BBFMM_K_GAUSS>(p, geo, phi, s); break;
+    case BBFMM_K_DIPOLE_X: launch_leaf_far<BBFMM_K_DIPOLE_X>(p, geo, phi, s); break;
+    default: launch_leaf_far<BBFMM_K_POLY_TEST>(p, geo, phi, s); break;
+    }
 }
 
 }  // namespace
@@ -2510,12 +2689,42 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         BB_HIP(hipEventRecord(p.join, p.side));
     }
     mark(BBFMM_STAGE_P2M);
-    if (L >= 2 && p.p2p_mfma) {
+    if (L >= 2 && t.adaptive) {
+        // leaves of every level >= 2 (M2M skips them)
+        const LevelData &fl = t.leaves();
+        for (int lvl = 2; lvl <= L; ++lvl) {
+            const LevelData &lv = t.lv[lvl];
+            if (lv.nleaf == 0) continue;
+            Geo gl = geo;
+            gl.h = float(t.half_width(lvl));
+            gl.inv_h = 1.0f / gl.h;
+            const int32_t *lpb = fl.pb.p + lv.leaf0, *lpe = fl.pe.p + lv.leaf0;
+            const uint64_t *lk = fl.keys.p + lv.leaf0;
+            const int32_t *rows = t.fl_cell.p + lv.leaf0;
+            if (p.p2p_mfma) {
+                dim3 g(unsigned(lv.nleaf), unsigned(p.ld_s / (16 * p.ncb_p2p)));
+#define BB_P2MM(NN, NCB) k_p2m_mfma<NN, NCB><<<g, kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, lpb,                     lpe, lk, rows, gl, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[lvl].p)
+#define BB_P2MN(NN) case NN:                                                                                      if (p.ncb_p2p == 1) BB_P2MM(NN, 1);                                                           else if (p.ncb_p2p == 2) BB_P2MM(NN, 2);                                                      else BB_P2MM(NN, 4);                                                                          break;
+                switch (n) {
+                    BB_P2MN(2) BB_P2MN(3) BB_P2MN(4) BB_P2MN(5) BB_P2MN(6) BB_P2MN(7) BB_P2MN(8)
+                }
+#undef BB_P2MN
+#undef BB_P2MM
+            } else {
+                switch (n) {
+#define BB_P2M(NN) case NN: k_p2m<NN><<<dim3(unsigned(ceil_div(lv.nleaf, 64 / ((NN) * (NN)))), unsigned(r)),                     64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, lpb, lpe, lk, rows, lv.nleaf, gl, o.cheb,                          p.sig_s.p, p.ld_s, r, mp, p.M[lvl].p); break;
+                BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
+#undef BB_P2M
+                }
+            }
+            BB_LAUNCH_CHECK();
+        }
+    } else if (L >= 2 && p.p2p_mfma) {
         // blocks of right-hand sides: P2M on MFMA (sigma padded to whole column blocks)
         const LevelData &leaf = t.lv[L];
         dim3 g(leaf.C, unsigned(p.ld_s / (16 * p.ncb_p2p)));
 #define BB_P2MM(NN, NCB) k_p2m_mfma<NN, NCB><<<g, kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), \
-            leaf.pe.p, leaf.keys.p, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p)
+            leaf.pe.p, leaf.keys.p, nullptr, geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p)
 #define BB_P2MN(NN) case NN:                                                                  \
             if (p.ncb_p2p == 1) BB_P2MM(NN, 1);                                               \
             else if (p.ncb_p2p == 2) BB_P2MM(NN, 2);                                          \
@@ -2531,8 +2740,8 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         const LevelData &leaf = t.lv[L];
         switch (n) {
 #define BB_P2M(NN) case NN: k_p2m<NN><<<dim3(unsigned(ceil_div(leaf.C, 64 / ((NN) * (NN)))), unsigned(r)), \
-            64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p, leaf.keys.p, int(leaf.C), \
-            geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
+            64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p, leaf.keys.p, nullptr, \
+            int(leaf.C), geo, o.cheb, p.sig_s.p, p.ld_s, r, mp, p.M[L].p); break;
         BB_P2M(2) BB_P2M(3) BB_P2M(4) BB_P2M(5) BB_P2M(6) BB_P2M(7) BB_P2M(8)
 #undef BB_P2M
         }
@@ -2709,18 +2918,59 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         const int64_t R = int64_t(lv.C) * r;
         if (o.precision == BBFMM_M2L_FFT) {
             fft_inverse(n, p.Fc[lvl].p, R, float(o.lv[lvl].scale), lvl > 2, mp, p.F[lvl].p, s);
-            continue;
+        } else {
+            dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
+            k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp,
+                                                     set.U32.p, set.kp, p.F[lvl].p, mp, R, mp,
+                                                     set.kp, float(o.lv[lvl].scale),
+                                                     lvl > 2 ? 1.f : 0.f, nullptr, nullptr,
+                                                     nullptr, 0);
+            BB_LAUNCH_CHECK();
         }
-        dim3 g(unsigned(ceil_div(R, 64)), unsigned(ceil_div(mp, 64)));
-        k_gemm_nt<kOutF32><<<g, kThreads, 0, s>>>(p.Fh[lvl].p, set.kp, p.nsplit, R * set.kp,
-                                                 set.U32.p, set.kp, p.F[lvl].p, mp, R, mp, set.kp,
-                                                 float(o.lv[lvl].scale), lvl > 2 ? 1.f : 0.f,
-                                                 nullptr, nullptr, nullptr, 0);
-        BB_LAUNCH_CHECK();
+        if (t.adaptive && lv.nx_cells > 0) {
+            // P2L: the X leaves' points into this level's local expansions
+            Geo gl = geo;
+            gl.h = float(t.half_width(lvl));
+            gl.inv_h = 1.0f / gl.h;
+            const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
+            const LevelData &fl = t.leaves();
+            dim3 g(unsigned(lv.nx_cells), unsigned(r));
+#define BB_P2L(KK)                                                                                    \
+            switch (n) {                                                                              \
+            case 2: k_p2l<2, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            case 3: k_p2l<3, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            case 4: k_p2l<4, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            case 5: k_p2l<5, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            case 6: k_p2l<6, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            case 7: k_p2l<7, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
+            default: k_p2l<8, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                               \
+            }
+#define BB_P2L_ARGS lv.x_cells.p, lv.x_off.p, lv.x_leaf.p, fl.pb.p, fl.pe.p, lv.keys.p, t.xs.p, \
+                    t.ys.p, t.zs.p, p.sig_s.p, p.ld_s, gl, o.cheb, cs, r, mp, p.F[lvl].p
+            switch (t.params.kernel_id) {
+            case BBFMM_K_INV_R: BB_P2L(BBFMM_K_INV_R) break;
+            case BBFMM_K_EXP: BB_P2L(BBFMM_K_EXP) break;
+            case BBFMM_K_GAUSS: BB_P2L(BBFMM_K_GAUSS) break;
+            case BBFMM_K_DIPOLE_X: BB_P2L(BBFMM_K_DIPOLE_X) break;
+            default: BB_P2L(BBFMM_K_POLY_TEST) break;
+            }
+#undef BB_P2L_ARGS
+#undef BB_P2L
+            BB_LAUNCH_CHECK();
+        }
     }
-    if (L >= 2) FL = p.F[L].p;
+    if (L >= 2 && !t.adaptive) FL = p.F[L].p;
     mark(BBFMM_STAGE_P2P);
-    if (p.overlap) {
+    if (t.adaptive) {
+        // near field over the U lists, then L2P and M2P added at every leaf
+        if (p.overlap) {
+            BB_HIP(hipStreamWaitEvent(s, p.join, 0));
+            if (ev) BB_HIP(hipEventRecord(ev[kEvJoined], s));
+        } else {
+            near_field(nullptr, s);
+        }
+        if (L >= 2) leaf_far(p, geo, phi, s);
+    } else if (p.overlap) {
         BB_HIP(hipStreamWaitEvent(s, p.join, 0));
         if (ev) BB_HIP(hipEventRecord(ev[kEvJoined], s));
         const LevelData &leaf = t.lv[L];

@@ -206,6 +206,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_iota_i32(int32_t *p, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) p[i] = int32_t(i);
+}
+
 // leaf neighbour lists: pass 1 counts (idx == nullptr), pass 2 writes
 __global__ void __launch_bounds__(kThreads)
 k_neighbors(const uint64_t *keys, int32_t C, int L, const int32_t *off, int32_t *out,
@@ -314,6 +319,229 @@ k_octant_fill(int32_t C, const int32_t *flag, const int32_t *pos, int32_t *cells
     cells[pos[g]] = int32_t(g % C);
 }
 
+// ------------------------------------------- level-adaptive tree
+// The adaptive tree (Section 2.1: split a cell only while it holds more than
+// leaf_size points) is the uniform tree with the descendants of every such
+// small cell removed.  Flags are computed top-down on the uniform tree's
+// indices, then every level is compacted.
+
+__global__ void __launch_bounds__(kThreads)
+k_adapt_flags(const int32_t *pb, const int32_t *pe, const int32_t *parent, int32_t C, int finest,
+              int leaf_size, const int32_t *keep_up, const int32_t *leaf_up, int32_t *keep,
+              int32_t *leaf) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= C) return;
+    int32_t k = 1;
+    if (keep_up != nullptr) {
+        const int32_t up = parent[c];
+        k = (keep_up[up] && !leaf_up[up]) ? 1 : 0;
+    }
+    keep[c] = k;
+    leaf[c] = (finest || pe[c] - pb[c] <= leaf_size) ? 1 : 0;
+}
+
+struct AdaptCompact {
+    const uint64_t *keys;
+    const int32_t *pb, *pe, *parent, *cb, *ce, *leaf, *keep, *pos;
+    const int32_t *pos_up;      // new index of the level above (nullptr at the root)
+    const int32_t *pos_down;    // new index of the level below (nullptr at the last level)
+    int32_t C;
+    uint64_t *okeys;
+    int32_t *opb, *ope, *oparent, *ocb, *oce, *oleaf;
+};
+
+// A kept cell that is not a leaf keeps all of its children, which stay one
+// contiguous run on the level below.
+__global__ void __launch_bounds__(kThreads) k_adapt_compact(AdaptCompact a) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= a.C || !a.keep[c]) return;
+    const int32_t j = a.pos[c];
+    a.okeys[j] = a.keys[c];
+    a.opb[j] = a.pb[c];
+    a.ope[j] = a.pe[c];
+    a.oparent[j] = a.pos_up != nullptr ? a.pos_up[a.parent[c]] : -1;
+    const bool lf = a.leaf[c] != 0 || a.pos_down == nullptr;
+    a.ocb[j] = lf ? -1 : a.pos_down[a.cb[c]];
+    a.oce[j] = lf ? -1 : a.pos_down[a.ce[c] - 1] + 1;
+    a.oleaf[j] = lf ? 1 : 0;
+}
+
+// leaf table entries of one level (rank = exclusive scan of the leaf flags)
+__global__ void __launch_bounds__(kThreads)
+k_adapt_table(const int32_t *leaf, const int32_t *rank, int32_t C, int lvl, int32_t off,
+              const uint64_t *keys, const int32_t *pb, const int32_t *pe, int32_t *flat,
+              uint64_t *fkey, int32_t *fpb, int32_t *fpe, int32_t *flev, int32_t *fcell) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= C) return;
+    if (!leaf[c]) {
+        flat[c] = -1;
+        return;
+    }
+    const int32_t q = off + rank[c];
+    flat[c] = q;
+    fkey[q] = keys[c];
+    fpb[q] = pb[c];
+    fpe[q] = pe[c];
+    flev[q] = lvl;
+    fcell[q] = c;
+}
+
+// Per-level arrays of the adaptive tree, by value.
+struct LevelTab {
+    const uint64_t *keys[kMaxLevels];
+    const int32_t *leaf[kMaxLevels], *flat[kMaxLevels], *cb[kMaxLevels], *ce[kMaxLevels];
+    int32_t C[kMaxLevels];
+    int32_t base[kMaxLevels + 1];   // global cell id = base[level] + cell
+    int L;                          // last level
+};
+
+// Append buffers of the list construction.  A pass with null arrays only
+// counts (n[0] U entries, n[1] frontier cells, n[2] W entries).
+struct ListOut {
+    unsigned long long *n;
+    uint64_t *u;                    // (leaf << 32) | leaf-table index of the U leaf
+    int32_t *fq, *flev, *fcell;     // frontier: (leaf, level, cell) adjacent, not a leaf
+    uint64_t *w;                    // (leaf << 32) | global id of the W cell
+};
+
+__device__ inline void emit_u(const ListOut &o, int32_t q, int32_t v) {
+    const unsigned long long i = atomicAdd(&o.n[0], 1ull);
+    if (o.u) o.u[i] = (uint64_t(q) << 32) | uint32_t(v);
+}
+__device__ inline void emit_f(const ListOut &o, int32_t q, int lvl, int32_t c) {
+    const unsigned long long i = atomicAdd(&o.n[1], 1ull);
+    if (o.fq) { o.fq[i] = q; o.flev[i] = lvl; o.fcell[i] = c; }
+}
+__device__ inline void emit_w(const ListOut &o, int32_t q, int32_t g) {
+    const unsigned long long i = atomicAdd(&o.n[2], 1ull);
+    if (o.w) o.w[i] = (uint64_t(q) << 32) | uint32_t(g);
+}
+
+// closed boxes of two cells (level, Morton key) touch or overlap, measured
+// in cells of the last level L
+__device__ inline bool cells_adjacent(int la, uint64_t ka, int lb, uint64_t kb, int L) {
+    const int32_t sa = 1 << (L - la), sb = 1 << (L - lb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int32_t a0 = int32_t(compact3(ka >> d)) << (L - la);
+        const int32_t b0 = int32_t(compact3(kb >> d)) << (L - lb);
+        if (a0 > b0 + sb || b0 > a0 + sa) return false;
+    }
+    return true;
+}
+
+// Seeds, one thread per (leaf q, offset of its 3x3x3 neighbourhood on its
+// own level): an existing same-level cell is a U leaf or a frontier cell
+// (adjacent, to be opened); a missing one may lie inside a coarser leaf,
+// which is then adjacent (U).
+__global__ void __launch_bounds__(kThreads)
+k_adapt_seed(LevelTab T, const uint64_t *fkey, const int32_t *flev, int32_t NL, ListOut o) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= int64_t(NL) * 27) return;
+    const int32_t q = int32_t(g / 27);
+    const int off = int(g % 27);
+    const int lb = flev[q];
+    const uint64_t key = fkey[q];
+    const int x = int(compact3(key)) + off % 3 - 1;
+    const int y = int(compact3(key >> 1)) + (off / 3) % 3 - 1;
+    const int z = int(compact3(key >> 2)) + off / 9 - 1;
+    const int lim = 1 << lb;
+    if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return;
+    const int32_t c = lookup(T.keys[lb], T.C[lb], morton3(x, y, z));
+    if (c >= 0) {
+        if (T.leaf[lb][c]) emit_u(o, q, T.flat[lb][c]);
+        else emit_f(o, q, lb, c);
+        return;
+    }
+    for (int l2 = lb - 1; l2 >= 0; --l2) {
+        const int sh = lb - l2;
+        const int32_t a = lookup(T.keys[l2], T.C[l2], morton3(x >> sh, y >> sh, z >> sh));
+        if (a >= 0) {
+            if (T.leaf[l2][a]) emit_u(o, q, T.flat[l2][a]);
+            return;             // an existing non-leaf ancestor: the spot is empty
+        }
+    }
+}
+
+// One frontier step, one thread per (frontier cell, child slot): a child
+// adjacent to the leaf is a U leaf or the next frontier; one that is not is
+// a W cell (its parent, the frontier cell, is adjacent).
+__global__ void __launch_bounds__(kThreads)
+k_adapt_expand(LevelTab T, const uint64_t *fkey, const int32_t *flev, const int32_t *fq,
+               const int32_t *fl, const int32_t *fc, int64_t nf, ListOut o) {
+    const int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (g >= nf * 8) return;
+    const int64_t e = g / 8;
+    const int32_t q = fq[e];
+    const int l = fl[e];
+    const int32_t c = fc[e];
+    const int32_t ch = T.cb[l][c] + int32_t(g % 8);
+    if (ch >= T.ce[l][c]) return;
+    const int lc = l + 1;
+    if (cells_adjacent(lc, T.keys[lc][ch], flev[q], fkey[q], T.L)) {
+        if (T.leaf[lc][ch]) emit_u(o, q, T.flat[lc][ch]);
+        else emit_f(o, q, lc, ch);
+    } else {
+        emit_w(o, q, T.base[lc] + ch);
+    }
+}
+
+// after a sort: flag[i] = 1 where entry i differs from entry i - 1
+__global__ void __launch_bounds__(kThreads)
+k_unique_flags(const uint64_t *v, int64_t n, int32_t *flag) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || v[i] != v[i - 1]) ? 1 : 0;
+}
+
+// sorted (row << 32 | value) entries -> CSR: counts per row and the values
+__global__ void __launch_bounds__(kThreads)
+k_csr_fill(const uint64_t *v, int64_t n, const int32_t *flag, const int32_t *pos, int32_t *cnt,
+           int32_t *val) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n || (flag != nullptr && !flag[i])) return;
+    const int64_t j = flag != nullptr ? pos[i] : i;
+    val[j] = int32_t(uint32_t(v[i]));
+    atomicAdd(&cnt[int32_t(v[i] >> 32)], 1);
+}
+
+// global cell ids -> (level, cell)
+__global__ void __launch_bounds__(kThreads)
+k_split_gid(const int32_t *gid, int64_t n, LevelTab T, int32_t *lev, int32_t *cell) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = gid[i];
+    int l = 0;
+    while (l < T.L && T.base[l + 1] <= v) ++l;
+    lev[i] = l;
+    cell[i] = v - T.base[l];
+}
+
+// W entry (leaf q, cell g) -> X entry (cell g, leaf q)
+__global__ void __launch_bounds__(kThreads)
+k_transpose_pairs(const uint64_t *w, int64_t n, uint64_t *x) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) x[i] = (w[i] << 32) | (w[i] >> 32);
+}
+
+// per-level slice of a global CSR offset array, rebased to start at 0
+__global__ void __launch_bounds__(kThreads)
+k_rebase(const int32_t *goff, int32_t b, int32_t C, int32_t *off) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c <= C) off[c] = goff[b + c] - goff[b];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_nonempty_flags(const int32_t *off, int32_t C, int32_t *flag) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c < C) flag[c] = off[c + 1] > off[c] ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_compact_idx(const int32_t *flag, const int32_t *pos, int32_t C, int32_t *out) {
+    const int32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c < C && flag[c]) out[pos[c]] = c;
+}
+
 inline int grid(int64_t n) { return int(ceil_div(n, kThreads)); }
 
 // Cells of a level from a sorted key array: runs of equal key >> sh.
@@ -338,6 +566,288 @@ int32_t make_runs(const uint64_t *keys, int64_t n, int sh, int32_t total, LevelD
     return int32_t(C);
 }
 
+// Compact every level to the cells of the level-adaptive tree, drop the
+// trailing empty levels and gather the leaves of all levels into the leaf
+// table (by level, then cell).
+void adapt_levels(bbfmm_tree &t, int leaf_size, hipStream_t s) {
+    const int D = t.depth, L = D - 1;
+    std::vector<DBuf<int32_t>> keep(D), leaf(D), pos(D);
+    std::vector<int32_t> newC(D);
+    for (int l = 0; l < D; ++l) {
+        const LevelData &lv = t.lv[l];
+        keep[l].alloc(lv.C);
+        leaf[l].alloc(lv.C);
+        pos[l].alloc(lv.C);
+        k_adapt_flags<<<grid(lv.C), kThreads, 0, s>>>(lv.pb.p, lv.pe.p, lv.parent.p, lv.C,
+                                                      l == L ? 1 : 0, leaf_size,
+                                                      l ? keep[l - 1].p : nullptr,
+                                                      l ? leaf[l - 1].p : nullptr, keep[l].p,
+                                                      leaf[l].p);
+        BB_LAUNCH_CHECK();
+        newC[l] = int32_t(scan_exclusive(keep[l].p, pos[l].p, lv.C, s));
+    }
+    int D2 = 0;
+    while (D2 < D && newC[D2] > 0) ++D2;
+    for (int l = 0; l < D2; ++l) {
+        LevelData &lv = t.lv[l];
+        const int32_t C2 = newC[l];
+        DBuf<uint64_t> keys(C2);
+        DBuf<int32_t> pb(C2), pe(C2), parent(C2), cb(C2), ce(C2), isleaf(C2);
+        AdaptCompact a{};
+        a.keys = lv.keys.p;
+        a.pb = lv.pb.p;
+        a.pe = lv.pe.p;
+        a.parent = lv.parent.p;
+        a.cb = lv.cb.p;
+        a.ce = lv.ce.p;
+        a.leaf = leaf[l].p;
+        a.keep = keep[l].p;
+        a.pos = pos[l].p;
+        a.pos_up = l > 0 ? pos[l - 1].p : nullptr;
+        a.pos_down = l + 1 < D2 ? pos[l + 1].p : nullptr;
+        a.C = lv.C;
+        a.okeys = keys.p;
+        a.opb = pb.p;
+        a.ope = pe.p;
+        a.oparent = parent.p;
+        a.ocb = cb.p;
+        a.oce = ce.p;
+        a.oleaf = isleaf.p;
+        k_adapt_compact<<<grid(lv.C), kThreads, 0, s>>>(a);
+        BB_LAUNCH_CHECK();
+        BB_HIP(hipStreamSynchronize(s));
+        lv.C = C2;
+        lv.keys = std::move(keys);
+        lv.pb = std::move(pb);
+        lv.pe = std::move(pe);
+        lv.parent = std::move(parent);
+        lv.cb = std::move(cb);
+        lv.ce = std::move(ce);
+        lv.isleaf = std::move(isleaf);
+    }
+    for (int l = D2; l < D; ++l) t.lv[l] = LevelData();
+    t.depth = D2;
+
+    // the leaf table
+    std::vector<DBuf<int32_t>> rank(D2);
+    int32_t NL = 0;
+    for (int l = 0; l < D2; ++l) {
+        LevelData &lv = t.lv[l];
+        rank[l].alloc(lv.C);
+        lv.leaf0 = NL;
+        lv.nleaf = int32_t(scan_exclusive(lv.isleaf.p, rank[l].p, lv.C, s));
+        NL += lv.nleaf;
+    }
+    LevelData &F = t.fleaf;
+    F.C = NL;
+    F.keys.alloc(NL);
+    F.pb.alloc(NL);
+    F.pe.alloc(NL);
+    t.fl_level.alloc(NL);
+    t.fl_cell.alloc(NL);
+    for (int l = 0; l < D2; ++l) {
+        LevelData &lv = t.lv[l];
+        lv.flat.alloc(lv.C);
+        k_adapt_table<<<grid(lv.C), kThreads, 0, s>>>(lv.isleaf.p, rank[l].p, lv.C, l, lv.leaf0,
+                                                      lv.keys.p, lv.pb.p, lv.pe.p, lv.flat.p,
+                                                      F.keys.p, F.pb.p, F.pe.p, t.fl_level.p,
+                                                      t.fl_cell.p);
+        BB_LAUNCH_CHECK();
+    }
+    BB_HIP(hipStreamSynchronize(s));
+}
+
+// Sort (row << 32 | value) entries, optionally drop repeats, and write the
+// CSR (off: rows + 1, val: the values).  Returns the entry count.
+int64_t pairs_to_csr(DBuf<uint64_t> &v, int64_t n, int32_t rows, bool unique, DBuf<int32_t> &off,
+                     DBuf<int32_t> &val, hipStream_t s) {
+    int bits = 32;
+    while (bits < 63 && (int64_t(1) << (bits - 32)) <= rows) ++bits;
+    if (n > 0) {
+        DBuf<int32_t> dummy(n);
+        radix_sort_pairs(v.p, dummy.p, n, bits, s);
+    }
+    DBuf<int32_t> flag, pos;
+    int64_t m = n;
+    if (unique && n > 0) {
+        flag.alloc(n);
+        pos.alloc(n);
+        k_unique_flags<<<grid(n), kThreads, 0, s>>>(v.p, n, flag.p);
+        BB_LAUNCH_CHECK();
+        m = scan_exclusive(flag.p, pos.p, n, s);
+    }
+    DBuf<int32_t> cnt(int64_t(rows) + 1);
+    BB_HIP(hipMemsetAsync(cnt.p, 0, (size_t(rows) + 1) * sizeof(int32_t), s));
+    val.alloc(m);
+    if (n > 0) {
+        k_csr_fill<<<grid(n), kThreads, 0, s>>>(v.p, n, flag.p, pos.p, cnt.p, val.p);
+        BB_LAUNCH_CHECK();
+    }
+    off.alloc(int64_t(rows) + 1);
+    scan_exclusive(cnt.p, off.p, int64_t(rows) + 1, s);
+    BB_HIP(hipStreamSynchronize(s));
+    return m;
+}
+
+// U, W and X lists of the level-adaptive tree (see k_adapt_seed and
+// k_adapt_expand); also the near-field counts of the tree.
+void adapt_lists(bbfmm_tree &t, hipStream_t s) {
+    const int D = t.depth, L = D - 1;
+    const int32_t NL = t.fleaf.C;
+    LevelTab T{};
+    T.L = L;
+    T.base[0] = 0;
+    for (int l = 0; l < D; ++l) {
+        const LevelData &lv = t.lv[l];
+        T.keys[l] = lv.keys.p;
+        T.leaf[l] = lv.isleaf.p;
+        T.flat[l] = lv.flat.p;
+        T.cb[l] = lv.cb.p;
+        T.ce[l] = lv.ce.p;
+        T.C[l] = lv.C;
+        T.base[l + 1] = T.base[l] + lv.C;
+    }
+    const int32_t ncells = T.base[D];
+    DBuf<unsigned long long> cnt(3);
+    unsigned long long hc[3];
+    std::vector<DBuf<uint64_t>> uch, wch;
+    std::vector<int64_t> un, wn;
+    DBuf<int32_t> fq, fl, fc;
+    int64_t nf = 0;
+    // one list pass: count, allocate the appended chunks, fill
+    auto pass = [&](auto launch) {
+        BB_HIP(hipMemsetAsync(cnt.p, 0, sizeof(hc), s));
+        ListOut o{cnt.p, nullptr, nullptr, nullptr, nullptr, nullptr};
+        launch(o);
+        BB_HIP(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+        BB_HIP(hipStreamSynchronize(s));
+        DBuf<uint64_t> u(hc[0]), w(hc[2]);
+        DBuf<int32_t> q2(hc[1]), l2(hc[1]), c2(hc[1]);
+        BB_HIP(hipMemsetAsync(cnt.p, 0, sizeof(hc), s));
+        o.u = u.p;
+        o.fq = q2.p;
+        o.flev = l2.p;
+        o.fcell = c2.p;
+        o.w = w.p;
+        // a chunk the count found empty gets no buffer: its pointer stays null
+        // and the fill pass writes nothing there
+        launch(o);
+        BB_HIP(hipStreamSynchronize(s));
+        un.push_back(int64_t(hc[0]));
+        wn.push_back(int64_t(hc[2]));
+        uch.push_back(std::move(u));
+        wch.push_back(std::move(w));
+        fq = std::move(q2);
+        fl = std::move(l2);
+        fc = std::move(c2);
+        nf = int64_t(hc[1]);
+    };
+    if (NL > 0)
+        pass([&](const ListOut &o) {
+            k_adapt_seed<<<unsigned(ceil_div(int64_t(NL) * 27, kThreads)), kThreads, 0, s>>>(
+                T, t.fleaf.keys.p, t.fl_level.p, NL, o);
+            BB_LAUNCH_CHECK();
+        });
+    for (int step = 0; nf > 0; ++step) {
+        BB_INTERNAL(step <= L, "adaptive list frontier did not drain");
+        DBuf<int32_t> q0 = std::move(fq), l0 = std::move(fl), c0 = std::move(fc);
+        const int64_t n0 = nf;
+        pass([&](const ListOut &o) {
+            k_adapt_expand<<<unsigned(ceil_div(n0 * 8, kThreads)), kThreads, 0, s>>>(
+                T, t.fleaf.keys.p, t.fl_level.p, q0.p, l0.p, c0.p, n0, o);
+            BB_LAUNCH_CHECK();
+        });
+    }
+    auto gather = [&](std::vector<DBuf<uint64_t>> &ch, const std::vector<int64_t> &n,
+                      DBuf<uint64_t> &all) {
+        int64_t tot = 0;
+        for (int64_t v : n) tot += v;
+        all.alloc(tot);
+        int64_t o = 0;
+        for (size_t i = 0; i < ch.size(); ++i) {
+            if (n[i] > 0)
+                BB_HIP(hipMemcpyAsync(all.p + o, ch[i].p, n[i] * sizeof(uint64_t),
+                                      hipMemcpyDeviceToDevice, s));
+            o += n[i];
+        }
+        BB_HIP(hipStreamSynchronize(s));
+        ch.clear();
+        return tot;
+    };
+    DBuf<uint64_t> U, W;
+    const int64_t nu = gather(uch, un, U);
+    const int64_t nw = gather(wch, wn, W);
+    t.nbr_nnz = pairs_to_csr(U, nu, NL, true, t.nbr_off, t.nbr_idx, s);
+
+    // W: CSR over the leaf table, cells as (level, cell)
+    DBuf<uint64_t> X(nw);
+    if (nw > 0) {
+        k_transpose_pairs<<<grid(nw), kThreads, 0, s>>>(W.p, nw, X.p);
+        BB_LAUNCH_CHECK();
+    }
+    DBuf<int32_t> wg;
+    t.w_nnz = pairs_to_csr(W, nw, NL, false, t.w_off, wg, s);
+    t.w_level.alloc(t.w_nnz);
+    t.w_cell.alloc(t.w_nnz);
+    if (t.w_nnz > 0) {
+        k_split_gid<<<grid(t.w_nnz), kThreads, 0, s>>>(wg.p, t.w_nnz, T, t.w_level.p, t.w_cell.p);
+        BB_LAUNCH_CHECK();
+    }
+    // X: the transposed W pairs, CSR over all cells, then sliced per level
+    DBuf<int32_t> xoff, xval;
+    pairs_to_csr(X, nw, ncells, false, xoff, xval, s);
+    std::vector<int32_t> hxoff(size_t(ncells) + 1);
+    BB_HIP(hipMemcpyAsync(hxoff.data(), xoff.p, hxoff.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    BB_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l < D; ++l) {
+        LevelData &lv = t.lv[l];
+        const int32_t b = T.base[l];
+        lv.x_off.alloc(int64_t(lv.C) + 1);
+        k_rebase<<<grid(int64_t(lv.C) + 1), kThreads, 0, s>>>(xoff.p, b, lv.C, lv.x_off.p);
+        BB_LAUNCH_CHECK();
+        const int32_t nx = hxoff[size_t(b) + lv.C] - hxoff[b];
+        lv.x_leaf.alloc(nx);
+        if (nx > 0)
+            BB_HIP(hipMemcpyAsync(lv.x_leaf.p, xval.p + hxoff[b], nx * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+        DBuf<int32_t> flag(lv.C), pos(lv.C);
+        k_nonempty_flags<<<grid(lv.C), kThreads, 0, s>>>(lv.x_off.p, lv.C, flag.p);
+        BB_LAUNCH_CHECK();
+        lv.nx_cells = int32_t(scan_exclusive(flag.p, pos.p, lv.C, s));
+        lv.x_cells.alloc(lv.nx_cells);
+        if (lv.nx_cells > 0) {
+            k_compact_idx<<<grid(lv.C), kThreads, 0, s>>>(flag.p, pos.p, lv.C, lv.x_cells.p);
+            BB_LAUNCH_CHECK();
+        }
+        BB_HIP(hipStreamSynchronize(s));
+    }
+
+    // near-field sizes, from host copies of the leaf table and the U lists
+    std::vector<int32_t> pb(NL), pe(NL), off(size_t(NL) + 1), idx(size_t(t.nbr_nnz));
+    BB_HIP(hipMemcpyAsync(pb.data(), t.fleaf.pb.p, NL * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BB_HIP(hipMemcpyAsync(pe.data(), t.fleaf.pe.p, NL * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BB_HIP(hipMemcpyAsync(off.data(), t.nbr_off.p, off.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    if (t.nbr_nnz > 0)
+        BB_HIP(hipMemcpyAsync(idx.data(), t.nbr_idx.p, idx.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+    BB_HIP(hipStreamSynchronize(s));
+    int64_t near = 0;
+    int32_t most = 0;
+    for (int32_t q = 0; q < NL; ++q) {
+        int64_t src = 0;
+        for (int32_t e = off[q]; e < off[q + 1]; ++e) src += pe[idx[e]] - pb[idx[e]];
+        near += src * (pe[q] - pb[q]);
+        most = std::max(most, pe[q] - pb[q]);
+    }
+    t.near_pairs = near;
+    t.max_leaf = most;
+}
+
+void uniform_neighbors(bbfmm_tree &t, hipStream_t s);
+void build_m2l_lists(bbfmm_tree &t, hipStream_t s);
+
 }  // namespace
 
 bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params &p,
@@ -353,6 +863,8 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
                    (p.kernel_param > 0 && std::isfinite(p.kernel_param)),
                "kernel_param must be a positive finite length");
     BB_REQUIRE(p.fixed_depth >= 0 && p.fixed_depth <= kMaxLevels, "fixed_depth must be in [0, 22]");
+    BB_REQUIRE(p.adaptive == 0 || p.adaptive == 1, "adaptive must be 0 or 1");
+    if (p.adaptive) BB_REQUIRE(p.leaf_size >= 1, "leaf_size must be >= 1");
     if (p.fixed_depth == 0) {
         BB_REQUIRE(p.leaf_size >= 1, "leaf_size must be >= 1");
         BB_REQUIRE(p.max_depth >= 1 && p.max_depth <= kMaxLevels, "max_depth must be in [1, 22]");
@@ -457,7 +969,35 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
     k_fill_i32<<<1, kThreads, 0, s>>>(t.lv[0].parent.p, t.lv[0].C, -1);
     BB_LAUNCH_CHECK();
 
-    // ---- leaf neighbours
+    if (p.adaptive) {
+        t.adaptive = true;
+        adapt_levels(t, p.leaf_size, s);
+        adapt_lists(t, s);
+    } else {
+        uniform_neighbors(t, s);
+    }
+    build_m2l_lists(t, s);
+    // host copies of the leaf point ranges, from which plans make their
+    // near-field launch lists without reading the device
+    const LevelData &leaves = t.leaves();
+    t.leaf_pb_h.resize(size_t(leaves.C));
+    t.leaf_pe_h.resize(size_t(leaves.C));
+    BB_HIP(hipMemcpyAsync(t.leaf_pb_h.data(), leaves.pb.p, leaves.C * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    BB_HIP(hipMemcpyAsync(t.leaf_pe_h.data(), leaves.pe.p, leaves.C * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    BB_HIP(hipStreamSynchronize(s));
+    t.leaf_te_h = t.leaf_pe_h;
+    return tree.release();
+}
+
+namespace {
+
+// Leaf neighbour lists N(.) of the uniform tree, and its leaf table (the
+// leaf level).
+void uniform_neighbors(bbfmm_tree &t, hipStream_t s) {
+    const int L = t.leaf_level();
+    const LevelData &leaf = t.lv[L];
     DBuf<unsigned long long> npairs(1);
     DBuf<int32_t> maxleaf(1), cnt(leaf.C);
     BB_HIP(hipMemsetAsync(npairs.p, 0, sizeof(unsigned long long), s));
@@ -484,8 +1024,17 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
         BB_HIP(hipStreamSynchronize(s));
         t.near_pairs = int64_t(hp);
     }
+    t.fl_level.alloc(leaf.C);
+    t.fl_cell.alloc(leaf.C);
+    k_fill_i32<<<grid(leaf.C), kThreads, 0, s>>>(t.fl_level.p, leaf.C, L);
+    k_iota_i32<<<grid(leaf.C), kThreads, 0, s>>>(t.fl_cell.p, leaf.C);
+    BB_LAUNCH_CHECK();
+}
 
-    // ---- M2L structures on levels >= 2
+// Per level >= 2: the interaction table, the pairs grouped by transfer
+// vector and the cells grouped by octant (Definition 2.1's I(.)).
+void build_m2l_lists(bbfmm_tree &t, hipStream_t s) {
+    const int L = t.leaf_level();
     const TransferTables &tt = transfer_tables();
     std::vector<int32_t> htab(3 * kNumT + 8 * kSlots + 8 * kNumT);
     for (int i = 0; i < kNumT; ++i)
@@ -538,18 +1087,9 @@ bbfmm_tree *build_tree_impl(const float *pts, int64_t n, const bbfmm_tree_params
             BB_HIP(hipStreamSynchronize(s));
         }
     }
-    // host copies of the leaf point ranges, from which plans make their
-    // near-field launch lists without reading the device
-    t.leaf_pb_h.resize(size_t(leaf.C));
-    t.leaf_pe_h.resize(size_t(leaf.C));
-    BB_HIP(hipMemcpyAsync(t.leaf_pb_h.data(), leaf.pb.p, leaf.C * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, s));
-    BB_HIP(hipMemcpyAsync(t.leaf_pe_h.data(), leaf.pe.p, leaf.C * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, s));
-    BB_HIP(hipStreamSynchronize(s));
-    t.leaf_te_h = t.leaf_pe_h;
-    return tree.release();
 }
+
+}  // namespace
 
 // ------------------------------------------- separate target / source sets
 namespace {
@@ -577,6 +1117,7 @@ bbfmm_tree *build_tree_sets_impl(const float *targets, int64_t nt, const float *
     BB_REQUIRE(targets != nullptr && sources != nullptr, "targets / sources is NULL");
     BB_REQUIRE(nt >= 1 && ns >= 1, "need at least one target and one source");
     BB_REQUIRE(nt + ns < (int64_t(1) << 31), "targets + sources must be < 2^31");
+    BB_REQUIRE(p.adaptive == 0, "a level-adaptive tree takes one point set");
     std::unique_ptr<bbfmm_tree> tree;
     {
         DBuf<float> uni(size_t(nt + ns) * 3);

@@ -1,0 +1,222 @@
+"""Level-adaptive tree on the GPU against the oracle (Section 2.1 on adaptive
+subdivision): every tree array and the U/V/W/X lists bit for bit, then the
+matvec element by element (FP32 path: relative L2 <= 1e-5 against the FP64
+oracle over the same adaptive tree), the polynomial kernel against the direct
+sum, the 16-bit M2L forms, both near-field paths and schedules, and a large
+clustered cloud against the direct sum on sampled rows."""
+import numpy as np
+import pytest
+
+import synth
+from _helpers import assert_parity, run_plan
+from oracle import adaptive as oad, fmm as ofmm, operators as oops
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _two_scale(n, seed, r=1):
+    """A dense Gaussian blob (two thirds of the points) in a uniform
+    background: the adaptive tree has leaves on many levels."""
+    rng = np.random.default_rng(seed)
+    blob = rng.normal(0.3, 0.02, (2 * n // 3, 3))
+    bg = rng.uniform(0.0, 1.0, (n - 2 * n // 3, 3))
+    pts = np.concatenate([blob, bg]).astype(np.float32)
+    sig = rng.uniform(-1.0, 1.0, (n, r)).astype(np.float32)
+    return pts, sig
+
+
+def _gpu_tree(pts, kid, prm, n, **kw):
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    tp = torch.from_numpy(np.ascontiguousarray(pts, dtype=np.float32)).cuda()
+    return bbfmm.build_tree(tp, kid, prm, cheb_order=n, adaptive=True, **kw)
+
+
+def compare_adaptive(gt, at):
+    info = gt.info()
+    assert info.adaptive == 1
+    assert info.depth == at.depth
+    assert info.n_leaves == len(at.leaves)
+    assert np.array_equal(gt.export("perm"), at.perm)
+    for lvl in range(at.depth):
+        lv = at.levels[lvl]
+        assert info.cells[lvl] == len(lv.keys)
+        assert np.array_equal(gt.export("keys", lvl), lv.keys)
+        assert np.array_equal(gt.export("pb", lvl), lv.pb)
+        assert np.array_equal(gt.export("pe", lvl), lv.pe)
+        assert np.array_equal(gt.export("parent", lvl), lv.parent)
+        cb, ce = gt.export("cb", lvl), gt.export("ce", lvl)
+        inner = ~lv.leaf
+        assert np.array_equal(cb[inner], lv.cb[inner]) and np.array_equal(ce[inner], lv.ce[inner])
+        assert np.all(cb[lv.leaf] == -1) and np.all(ce[lv.leaf] == -1)
+    assert np.array_equal(gt.export("leaf_level"), at.leaves[:, 0])
+    assert np.array_equal(gt.export("leaf_cell"), at.leaves[:, 1])
+    flat = {(int(l), int(c)): q for q, (l, c) in enumerate(at.leaves)}
+    # U lists over the leaf table
+    off = np.zeros(len(at.leaves) + 1, np.int64)
+    off[1:] = np.cumsum([len(u) for u in at.U])
+    idx = np.array([flat[(int(l), int(c))] for u in at.U for l, c in u], np.int64)
+    assert np.array_equal(gt.export("nbr_off"), off)
+    assert np.array_equal(gt.export("nbr_idx"), idx)
+    # W lists
+    off[1:] = np.cumsum([len(w) for w in at.W])
+    assert info.w_entries == off[-1]
+    assert np.array_equal(gt.export("w_off"), off)
+    wl = np.concatenate([w[:, 0] for w in at.W]) if off[-1] else np.zeros(0, np.int64)
+    wc = np.concatenate([w[:, 1] for w in at.W]) if off[-1] else np.zeros(0, np.int64)
+    assert np.array_equal(gt.export("w_level"), wl)
+    assert np.array_equal(gt.export("w_cell"), wc)
+    # X lists, per level
+    for lvl in range(at.depth):
+        C = len(at.levels[lvl].keys)
+        rows = [at.X.get((lvl, c), np.zeros((0, 2), np.int64)) for c in range(C)]
+        xo = np.zeros(C + 1, np.int64)
+        xo[1:] = np.cumsum([len(x) for x in rows])
+        xl = np.array([flat[(int(l), int(c))] for x in rows for l, c in x], np.int64)
+        assert np.array_equal(gt.export("x_off", lvl), xo)
+        assert np.array_equal(gt.export("x_leaf", lvl), xl)
+    for lvl in range(2, at.depth):
+        pr = at.pairs[lvl]
+        assert info.pairs[lvl] == len(pr["t"])
+        assert np.array_equal(gt.export("pair_t", lvl), pr["t"])
+        assert np.array_equal(gt.export("pair_tgt", lvl), pr["tgt"])
+        assert np.array_equal(gt.export("pair_src", lvl), pr["src"])
+        assert np.array_equal(gt.export("pair_goff", lvl), pr["group_off"])
+    # near-field size over the U lists
+    pb = np.array([at.levels[l].pb[c] for l, c in at.leaves])
+    pe = np.array([at.levels[l].pe[c] for l, c in at.leaves])
+    near = sum(int(pe[q] - pb[q]) * int(sum(pe[flat[(int(l), int(c))]] - pb[flat[(int(l), int(c))]]
+                                            for l, c in at.U[q]))
+               for q in range(len(at.leaves)))
+    assert info.near_pairs == near
+    assert info.max_leaf_points == int((pe - pb).max())
+
+
+@pytest.mark.parametrize("case", ["two-scale", "clustered", "slab", "trimmed", "root", "dups"])
+def test_adaptive_tree_bit_exact(case):
+    if case == "two-scale":
+        pts, _ = _two_scale(3000, 11)
+        kw = dict(leaf_size=32, max_depth=8)
+    elif case == "clustered":
+        pts, _ = synth.random_cloud(20000, 12, kind="clustered")
+        kw = dict(leaf_size=64, max_depth=9)
+    elif case == "slab":
+        pts, _ = synth.random_cloud(5000, 13, kind="slab")
+        kw = dict(leaf_size=16, max_depth=9)
+    elif case == "trimmed":      # a fixed last level deeper than any split
+        pts, _ = synth.random_cloud(3000, 14)
+        kw = dict(leaf_size=500, fixed_depth=7)
+    elif case == "root":
+        pts, _ = synth.random_cloud(50, 15)
+        kw = dict(leaf_size=64, max_depth=6)
+    else:
+        pts = np.repeat(synth.random_cloud(100, 16)[0], 7, axis=0)
+        kw = dict(leaf_size=10, max_depth=8)
+    at = oad.build_adaptive_tree(pts, **kw)
+    compare_adaptive(_gpu_tree(pts, 0, 1.0, 4, **kw), at)
+    if case == "trimmed":
+        assert at.depth < 7
+    if case == "root":
+        assert at.depth == 1
+
+
+@pytest.mark.parametrize("kid,prm,n,r,eps,opts", [
+    (0, 1.0, 5, 1, 1e-7, {}),
+    (0, 1.0, 4, 2, 1e-6, {"overlap": 2}),
+    (1, 0.1, 4, 3, 1e-6, {"p2p_mfma": 2}),
+    (2, 0.2, 5, 1, 1e-6, {"overlap": 1, "p2p_mfma": 1}),
+    (3, 1.0, 5, 2, 1e-7, {"m2l_schedule": 1}),
+    (0, 1.0, 6, 17, 1e-6, {}),
+])
+def test_adaptive_matvec_matches_oracle(kid, prm, n, r, eps, opts):
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = _two_scale(4000, 20 + n + r, r=r)
+    kw = dict(leaf_size=32, max_depth=8)
+    gt = _gpu_tree(pts, kid, prm, n, **kw)
+    go = bbfmm.precompute_operators(gt, eps)
+    at = oad.build_adaptive_tree(pts, **kw)
+    oo = oops.precompute(at, kid, prm, n, eps)
+    for lvl in range(2, at.depth):
+        assert go.rank(lvl) == oo.levels[lvl].k
+    ref = oad.matvec(at, oo, pts, sig, kid, prm)
+    got = run_plan(gt, go, sig, **opts).cpu().numpy().astype(np.float64)
+    assert_parity(got, ref, TOL, f"adaptive kernel {kid} n {n} r {r} {opts}")
+    assert gt.info().w_entries > 0 and len(at.X) > 0
+
+
+def test_adaptive_polynomial_kernel_is_the_direct_sum():
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = _two_scale(3000, 31, r=2)
+    gt = _gpu_tree(pts, 100, 0.7, 4, leaf_size=32, max_depth=8)
+    go = bbfmm.precompute_operators(gt, 0.0)
+    got = run_plan(gt, go, sig).cpu().numpy().astype(np.float64)
+    assert_parity(got, ofmm.direct(pts, sig, 100, 0.7), 1e-5, "adaptive polynomial kernel")
+
+
+# The 16-bit M2L forms bound the error of each far-field product (split-BF16:
+# 3 * 2^-18 ~ 1.1e-5 relative; scaled FP16: 2 * 2^-11 ~ 1e-3), so the bar is
+# taken relative to the oracle's far field (everything but the U-list sums):
+# per column in L2, and element by element against the column's largest far
+# value.  With signed weights in a dense cluster a target's far field is a
+# sum of strongly cancelling contributions (the same far field with |sigma|
+# is 28 to 141 times larger in norm for this cloud), so the worst-case bound
+# is much looser; the terms' rounding errors average out, and the bar is 3x
+# the per-product bound.
+@pytest.mark.parametrize("prec,tol", [(1, 3.3e-5), (2, 3e-3)])
+def test_adaptive_16bit_m2l(prec, tol):
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = _two_scale(4000, 32, r=16)
+    kw = dict(leaf_size=32, max_depth=8)
+    gt = _gpu_tree(pts, 1, 0.1, 5, **kw)
+    go = bbfmm.precompute_operators(gt, 1e-6, prec)
+    at = oad.build_adaptive_tree(pts, **kw)
+    oo = oops.precompute(at, 1, 0.1, 5, 1e-6)
+    ref = oad.matvec(at, oo, pts, sig, 1, 0.1)
+    far = oad.matvec(at, oo, pts, sig, 1, 0.1, near=False)
+    for blk in (1, 2):
+        got = run_plan(gt, go, sig, m2l_block=blk).cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got))
+        l2 = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(far, axis=0)
+        elem = np.abs(got - ref).max(axis=0) / np.abs(far).max(axis=0)
+        print(f"adaptive precision {prec} m2l_block {blk}: relative to the far field "
+              f"L2 {l2.max():.2e}, element {elem.max():.2e}")
+        assert l2.max() < tol and elem.max() <= 10 * tol
+
+
+def test_adaptive_large_clustered_against_direct_sum():
+    """300k points in 64 tight clusters: the adaptive tree against the direct
+    sum on 2048 sampled rows, beside the uniform tree of the same depth."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    rng = np.random.default_rng(40)
+    pts = synth.clustered_points(rng, 300_000)
+    sig = rng.uniform(-1, 1, (len(pts), 1)).astype(np.float32)
+    rows = np.sort(rng.choice(len(pts), 2048, replace=False))
+    ex = ofmm.direct(pts, sig, 0, 1.0, rows=rows)
+    errs, cells = {}, {}
+    for adaptive in (False, True):
+        tp = torch.from_numpy(pts).cuda()
+        gt = bbfmm.build_tree(tp, 0, 1.0, cheb_order=5, leaf_size=64, max_depth=9,
+                              adaptive=adaptive)
+        go = bbfmm.precompute_operators(gt, 1e-7)
+        phi = bbfmm.matvec(gt, go, torch.from_numpy(sig).cuda())
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy().astype(np.float64)[rows]
+        errs[adaptive] = ofmm.rel_l2(got, ex)
+        info = gt.info()
+        cells[adaptive] = sum(info.cells[:info.depth])
+    print(f"300k clustered: rel err uniform {errs[False]:.2e} adaptive {errs[True]:.2e}; "
+          f"cells uniform {cells[False]} adaptive {cells[True]}")
+    assert errs[True] < 1e-4 and errs[True] < 3.0 * errs[False] + 1e-6
+    assert cells[True] < cells[False]
+
+
+def test_adaptive_rejects_separate_sets():
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, _ = synth.random_cloud(500, 3)
+    tp = torch.from_numpy(pts).cuda()
+    with pytest.raises(bbfmm.BBFMMError, match="one point set"):
+        bbfmm.build_tree(tp, 0, 1.0, cheb_order=4, sources=tp, adaptive=True)
