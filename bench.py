@@ -54,6 +54,15 @@ def measured_traffic(kernel: str, workload: str):
     return (ent["fetch_kib"] * rec["fetch_scale"] + ent["write_kib"] * rec["write_scale"]) * 1024.0
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden")
+
+
+def rel_l2(approx, exact) -> float:
+    """||approx - exact||_2 / ||exact||_2 over all entries."""
+    import numpy as np
+    return float(np.linalg.norm(approx - exact) / np.linalg.norm(exact))
+
+
 def flops_per_pair_p2p(kernel_id: int, r: int) -> int:
     """Flop convention for one kernel evaluation + accumulation: 3 sub,
     3 mul + 2 add for r^2, 1 for the kernel (rsqrt) = 9 for 1/r; exp(-r/a)
@@ -165,13 +174,14 @@ def fft_m2l_section(w, sig, steps: int = 20):
     import numpy as np
     import torch
 
-    from oracle import fmm as ofmm
     from paper_1903_02153_amd import bbfmm
     pts = torch.from_numpy(w.points).cuda()
     tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
                             leaf_size=w.leaf_size, max_depth=w.max_depth,
                             fixed_depth=w.fixed_depth)
-    exact = ofmm.direct(w.points, w.sigma, w.kernel_id, w.kernel_param, rows=w.sample_rows)
+    stored = np.load(os.path.join(GOLDEN, "bench_ref_uniform.npz"))
+    assert np.array_equal(stored["rows"], w.sample_rows)
+    exact = stored["direct"]
     out = {"workload": w.name, "order": w.order}
     for tag, prec in (("svd_fp32", bbfmm.M2L_FP32), ("fft_uniform", bbfmm.M2L_FFT)):
         ops = bbfmm.precompute_operators(tree, w.eps, prec)
@@ -190,46 +200,46 @@ def fft_m2l_section(w, sig, steps: int = 20):
                     "m2l_ms": round(st["m2l"] / ne, 4),
                     "up_ms": round((st["p2m"] + st["m2m"]) / ne, 4),
                     "down_ms": round(st["down"] / ne, 4),
-                    "rel_err_vs_direct": ofmm.rel_l2(got, exact)}
+                    "rel_err_vs_direct": rel_l2(got, exact)}
         plan.close()
         ops.close()
     return out
 
 
-def order_study(orders=range(2, 9)):
+def order_study():
     """Error against the direct sum per Chebyshev order (the error-versus-
     order study of the paper's accuracy section) on the small uniform
-    workload (4096 points, 1/r, 3 levels): the GPU FP32 matvec and the FP64
-    oracle bbFMM at each order, with SVD tolerance 1e-5 and without
-    compression."""
+    workload (4096 points, 1/r, 3 levels): the GPU FP32 matvec at each
+    order, with SVD tolerance 1e-5 and without compression, against the
+    stored direct sum and FP64 oracle bbFMM (tests/golden/make_bench_refs.py)."""
     import numpy as np
     import torch
 
     import synth
-    from oracle import fmm as ofmm, operators as oops, tree as otree
     from paper_1903_02153_amd import bbfmm
     w = synth.cfg_small()
-    exact = ofmm.direct(w.points, w.sigma, w.kernel_id, w.kernel_param)
-    ot = otree.build_tree(w.points, fixed_depth=w.fixed_depth)
+    stored = np.load(os.path.join(GOLDEN, "bench_ref_orders.npz"))
+    exact = stored["direct"]
+    orders = [int(v) for v in stored["orders"]]
+    epss = [float(v) for v in stored["eps"]]
     pts = torch.from_numpy(w.points).cuda()
     sig = torch.from_numpy(np.ascontiguousarray(w.sigma, dtype=np.float32)).cuda()
     if sig.dim() == 1:
         sig = sig[:, None].contiguous()
     out = []
-    for n in orders:
+    for i, n in enumerate(orders):
         tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=n,
                                 fixed_depth=w.fixed_depth)
-        for eps in (1e-5, 0.0):
+        for j, eps in enumerate(epss):
             ops = bbfmm.precompute_operators(tree, eps)
             got = bbfmm.matvec(tree, ops, sig)
             torch.cuda.synchronize()
             g = got.cpu().numpy().astype(np.float64)
-            oo = oops.precompute(ot, w.kernel_id, w.kernel_param, n, eps)
-            ref = ofmm.matvec(ot, oo, w.points, w.sigma, w.kernel_id, w.kernel_param)
+            ref = stored["bbfmm"][i, j]
             out.append({"n": n, "svd_eps": eps,
-                        "gpu_vs_direct": ofmm.rel_l2(g, exact),
-                        "gpu_vs_oracle": ofmm.rel_l2(g, ref),
-                        "oracle_vs_direct": ofmm.rel_l2(ref, exact)})
+                        "gpu_vs_direct": rel_l2(g, exact),
+                        "gpu_vs_oracle": rel_l2(g, ref),
+                        "oracle_vs_direct": rel_l2(ref, exact)})
             ops.close()
         tree.close()
     return {"workload": w.name, "N": w.n, "kernel": "1/r", "depth": w.fixed_depth,
@@ -258,8 +268,9 @@ def batched_variants(steps: int, warmup: int, tune: bool):
     two batched workloads: points x RHS/s of the single-RHS FP32 form, the
     r-column FP32 form and the r-column low-precision forms (HIP-graph
     replay), with each form's largest per-column relative difference from
-    the r-column FP32 result (whose own error against the FP64 oracle is
-    pinned by the full-size parity tests)."""
+    the r-column FP32 result and its largest per-column relative error
+    against the stored FP64 oracle bbFMM on the workload's 4096 sampled rows
+    (tests/golden/make_fullsize_refs.py)."""
     import numpy as np
     import torch
 
@@ -298,13 +309,25 @@ def batched_variants(steps: int, warmup: int, tune: bool):
             plan.close()
             return phi
 
-        run("fp32_r1", bbfmm.M2L_FP32, 1)
+        stored = np.load(os.path.join(GOLDEN, f"fullsize_ref_{w.name}.npz"))
+        assert np.array_equal(stored["rows"], w.sample_rows)
+        oref = stored["phi"].astype(np.float64)
+
+        def vs_oracle(phi, r):
+            got = phi.cpu().numpy().astype(np.float64)[w.sample_rows]
+            return float((np.linalg.norm(got - oref[:, :r], axis=0)
+                          / np.linalg.norm(oref[:, :r], axis=0)).max())
+
+        r1 = run("fp32_r1", bbfmm.M2L_FP32, 1)
+        rec["forms"]["fp32_r1"]["max_col_rel_err_vs_oracle"] = vs_oracle(r1, 1)
         ref = run(f"fp32_r{w.r}", bbfmm.M2L_FP32, w.r)
+        rec["forms"][f"fp32_r{w.r}"]["max_col_rel_err_vs_oracle"] = vs_oracle(ref, w.r)
         for prec in precs:
             tag = ("fp32", "bf16x3", "fp16s")[prec] + f"_r{w.r}"
             got = run(tag, prec, w.r)
             d = ((got - ref).norm(dim=0) / ref.norm(dim=0)).max().item()
             rec["forms"][tag]["max_col_rel_diff_vs_fp32"] = d
+            rec["forms"][tag]["max_col_rel_err_vs_oracle"] = vs_oracle(got, w.r)
             del got
         base = rec["forms"]["fp32_r1"]["points_rhs_per_s"]
         for f in rec["forms"].values():
@@ -312,6 +335,61 @@ def batched_variants(steps: int, warmup: int, tune: bool):
         out.append(rec)
         del ref, sig, pts, tree
         torch.cuda.empty_cache()
+    return out
+
+
+def adaptive_section(steps: int = 10):
+    """The level-adaptive tree (Section 2.1 on adaptive subdivision) on the
+    clustered 2M-point workload (64 tight clusters, exp(-r/0.1), n = 6,
+    r = 16, split-BF16 M2L, leaf size 64, at most 7 levels) beside the
+    uniform tree of the same depth rule: cells, near-field pairs, time per
+    product (HIP-graph replay) and the error against the stored direct sum on
+    1024 sampled rows (tests/golden/make_bench_refs.py)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1903_02153_amd import bbfmm
+    w = synth.cfg_clustered_2m()
+    stored = np.load(os.path.join(GOLDEN, "bench_ref_clustered.npz"))
+    rows = stored["rows"]
+    assert np.array_equal(rows, w.sample_rows[:len(rows)])
+    exact = stored["direct"]
+    pts = torch.from_numpy(w.points).cuda()
+    sig = torch.from_numpy(w.sigma).cuda()
+    out = {"workload": w.name, "precision": "bf16x3"}
+    for tag, adaptive in (("uniform", False), ("adaptive", True)):
+        t0 = time.perf_counter()
+        tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
+                                leaf_size=w.leaf_size, max_depth=w.max_depth,
+                                fixed_depth=w.fixed_depth, adaptive=adaptive)
+        torch.cuda.synchronize()
+        t_tree = time.perf_counter() - t0
+        ops = bbfmm.precompute_operators(tree, w.eps, w.precision)
+        phi = torch.empty_like(sig)
+        plan = bbfmm.Plan(tree, ops, w.r)
+        plan.set_graph(True)
+        lat = time_plan(plan, sig, phi, steps, 2)
+        plan.set_graph(False)
+        plan.set_timing(True)
+        plan.stage_times(reset=True)
+        for _ in range(3):
+            plan.execute(sig, phi)
+        torch.cuda.synchronize()
+        st, ne = plan.stage_times(reset=True)
+        info = tree.info()
+        got = phi.cpu().numpy().astype(np.float64)[rows]
+        med = float(np.median(lat))
+        out[tag] = {"cells": int(sum(info.cells[:info.depth])), "leaves": int(info.n_leaves),
+                    "depth": int(info.depth), "near_pairs": int(info.near_pairs),
+                    "w_entries": int(info.w_entries), "tree_build_s": round(t_tree, 3),
+                    "ms_median": round(med, 4), "points_rhs_per_s": w.n * w.r / (med * 1e-3),
+                    "stage_ms": {k: round(v / ne, 4) for k, v in st.items()},
+                    "max_col_rel_err_vs_direct": float(
+                        (np.linalg.norm(got - exact, axis=0) / np.linalg.norm(exact, axis=0)).max())}
+        plan.close()
+        ops.close()
+        tree.close()
     return out
 
 
@@ -603,6 +681,8 @@ def main() -> int:
     if args.workload == "uniform-1M" and not args.no_extras:
         out["order_study"] = order_study()
         progress("error per order done")
+        out["adaptive_tree"] = adaptive_section()
+        progress("adaptive tree done")
         out["m2l_fft"] = fft_m2l_section(w, sig)
         progress("FFT M2L variant done")
     if not args.no_cpu_baseline:
