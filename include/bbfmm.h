@@ -358,7 +358,8 @@ bbfmm_status bbfmm_plan_create(const bbfmm_tree *tree, const bbfmm_ops *ops,
 /* Launch-shape choices of a plan; 0 selects the built-in heuristic. */
 typedef struct {
     int32_t m2l_split;      /* workgroups sharing one M2L tile's 189 slots, 1..8   */
-    int32_t m2l_min_waves;  /* heuristic target of M2L workgroups per CU, 1..16   */
+    int32_t m2l_min_waves;  /* heuristic target of M2L workgroups per CU, 1..16  */
+                            /* (0 = 16; the split doubles up to 8 to reach it)   */
     int32_t p2p_max_split;  /* cap on sub-lanes per P2P target, 1..64 (power of 2) */
     int32_t p2p_mfma;       /* near field + L2P: 1 per-lane FMA kernel, 2 on MFMA  */
                             /* (kernel values as the A operand); 0 picks by r     */
@@ -387,6 +388,11 @@ typedef struct {
     int32_t m2l_rtile;      /* parent blocks: right-hand sides per workgroup, 16, */
                             /* 32 or 64 (0: 16 up to r = 16, 32 up to 47, else   */
                             /* 64)                                               */
+    int32_t m2l_xcd;        /* tile M2L: 1 = each XCD runs every slot split of a  */
+                            /* contiguous run of tiles; 2 = each split pinned to  */
+                            /* 8 / m2l_split XCDs, so a split's operators stay in */
+                            /* their L2s (needs m2l_split dividing 8); 0 = 2 when */
+                            /* it applies                                        */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a
@@ -458,7 +464,8 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  *   reps        1..100.
  *   best        out: the chosen options (m2l_split, p2p_mfma,
  *               p2p_max_split, overlap, p2p_waves, m2l_occupancy,
- *               m2l_layout, m2l_schedule, m2l_block and m2l_rtile explicit).
+ *               m2l_layout, m2l_schedule, m2l_block, m2l_rtile and m2l_xcd
+ *               explicit).
  *   best_ms     out (may be NULL): its median milliseconds per product.
  * Allocates and frees one plan workspace per candidate; synchronizes
  * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.

@@ -480,7 +480,7 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 cur = c;
             }
         };
-        for (int split = 1; split <= 4; ++split) {
+        for (int split : {1, 2, 3, 4, 8}) {
             bbfmm_plan_options c = cur;
             c.m2l_split = split;
             consider(c);
@@ -513,6 +513,11 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
         if (o->precision == BBFMM_M2L_FP32) {
             bbfmm_plan_options c = cur;
             c.m2l_layout = 2;
+            consider(c);
+        }
+        for (int xc = 1; xc <= 2; ++xc) {
+            bbfmm_plan_options c = cur;
+            c.m2l_xcd = xc;
             consider(c);
         }
         if (cur.overlap == 2)

@@ -141,7 +141,8 @@ struct LevelData {
     DBuf<int32_t> pb, pe, parent, cb, ce;
     // M2L structures, levels >= 2
     DBuf<int32_t> itab;             // [C][189]: source cell per slot, -1 if none
-    DBuf<int32_t> oct_cells;        // cells grouped by octant (stable)
+    DBuf<int32_t> oct_cells;        // cells grouped by octant, then by interaction-slot
+                                    // pattern, Morton order within a group
     int32_t oct_off[9] = {0};       // group boundaries in oct_cells
     int64_t npairs = 0;
     DBuf<int32_t> pair_t, pair_tgt, pair_src, pair_goff;

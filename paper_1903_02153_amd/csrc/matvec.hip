@@ -165,15 +165,9 @@ k_gather_sigma(const float *sigma, const int32_t *perm, int64_t n, int r, int ld
 
 // ----------------------------------------------------- up / down ----
 // Node rows are padded from m = n^3 to mp (a multiple of 16) with zeros so
-// that the compression GEMMs can read them with 16-byte loads.  All up /
-// down interpolation kernels are one wave per (cell, right-hand side) and
-// are compiled per order N, so node index arithmetic is by constants.
-
-template <int N>
-struct NodeIdx {
-    static constexpr int m = N * N * N;
-    static constexpr int Q = (m + 63) / 64;     // node slots per lane
-};
+// that the compression GEMMs can read them with 16-byte loads.  The up /
+// down interpolation kernels are compiled per order N, so node index
+// arithmetic is by constants.
 
 // P2M: M[leaf][c][node] = sum_p Lx_i1(p) Ly_i2(p) Lz_i3(p) sigma_p[c]   (grid:
 // ceil(leaves / G) x r).  The wave holds G = 64 / n^2 leaves, one per group
@@ -359,141 +353,137 @@ k_p2m_mfma(const float *xs, const float *ys, const float *zs, const int32_t *pb,
     }
 }
 
-// One child -> parent translation (trans = false) or parent -> child
-// (trans = true) of an n^3 block held in LDS `A`, as three n x n mode
-// products; the result is returned in registers (node slots of the lane).
+// ---------------------------------------------- M2M / L2L by pencils ----
+// The translation between a cell and a child is the tensor product
+// T_z (x) T_y (x) T_x of three n x n matrices (the 1D interpolation of the
+// child's nodes, Section 2.3).  A group of n^2 lanes holds one n^3 block of
+// one column as n^2 pencils of n values along one axis; a mode product along
+// the pencil axis is n^2 register FMAs per lane with the matrix entries
+// uniform across the wave (scalar operands), and two transposes through LDS
+// turn the pencils to the next axes (z, then y, then x).  A wave takes
+// G = 64 / n^2 columns of one parent.
 template <int N>
-__device__ inline void mode3(float *A, float *B, const float (*Ts)[N][N], int o, bool trans,
-                             const int *i1, const int *i2, const int *i3, float *out) {
-    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
-    const int lane = threadIdx.x;
-    const int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+struct Pencil {
+    static constexpr int NP = N * N, G = 64 / NP, m = N * N * N;
+};
+
+// w[i] = sum_j T[o][i][j] v[j]  (trans: T[o][j][i])
+template <int N, bool TRANS>
+__device__ inline void mode1(const ChebConst &cc, int o, const float *v, float *w) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (lane + 64 * q < m) {
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-                s += (trans ? Ts[ox][j][i1[q]] : Ts[ox][i1[q]][j]) * A[(i3[q] * N + i2[q]) * N + j];
-            B[lane + 64 * q] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (lane + 64 * q < m) {
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-                s += (trans ? Ts[oy][j][i2[q]] : Ts[oy][i2[q]][j]) * B[(i3[q] * N + j) * N + i1[q]];
-            A[lane + 64 * q] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int i = 0; i < N; ++i) {
         float s = 0.f;
-        if (lane + 64 * q < m) {
 #pragma unroll
-            for (int j = 0; j < N; ++j)
-                s += (trans ? Ts[oz][j][i3[q]] : Ts[oz][i3[q]][j]) * A[(j * N + i2[q]) * N + i1[q]];
-        }
-        out[q] = s;
+        for (int j = 0; j < N; ++j) s = __fmaf_rn(TRANS ? cc.T[o][j][i] : cc.T[o][i][j], v[j], s);
+        w[i] = s;
     }
 }
 
-template <int N>
-__device__ inline void load_T(const ChebConst &cc, float (*Ts)[N][N]) {
-    for (int e = threadIdx.x; e < 2 * N * N; e += 64) {
-        const int o = e / (N * N), i = (e / N) % N, j = e % N;
-        Ts[o][i][j] = cc.T[o][i][j];
+// One child translation of a block held as z-pencils (lane p = i1 + N i2
+// holds i3 = 0..N-1); returns x-pencils (lane p = i2 + N i3 holds i1).
+// buf: this group's N^3 floats of LDS.
+template <int N, bool TRANS>
+__device__ inline void translate3(const ChebConst &cc, int oct, const float *vz, float *buf,
+                                  int p, bool on, float *out) {
+    const int ox = oct & 1, oy = (oct >> 1) & 1, oz = (oct >> 2) & 1;
+    float w[N], u[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) u[k] = 0.f;       // lanes outside the groups stay at 0
+    mode1<N, TRANS>(cc, oz, vz, w);                 // along z
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) buf[p + N * N * k] = w[k];
     }
+    __syncthreads();
+    const int a1 = p % N, a3 = p / N;               // y-pencils: lane (i1, i3)
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) u[k] = buf[a1 + N * k + N * N * a3];
+    }
+    __syncthreads();
+    mode1<N, TRANS>(cc, oy, u, w);                  // along y
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) buf[a1 + N * k + N * N * a3] = w[k];
+    }
+    __syncthreads();
+    if (on) {                                       // x-pencils: lane (i2, i3)
+#pragma unroll
+        for (int k = 0; k < N; ++k) u[k] = buf[k + N * p];
+    }
+    __syncthreads();
+    mode1<N, TRANS>(cc, ox, u, out);                // along x
 }
 
-// M2M: M[P][c] = sum over children of (T (x) T (x) T) M[child][c]   (grid: parents x r).
-// The (at most 8) children's coefficients are all requested before the
-// first is used, so the wave waits for memory once; the translations then
-// run child by child from LDS and are summed in child order.
+// M2M: M[P][c] = sum over the children of (T (x) T (x) T) M[child][c]
+// (grid: parents x column groups).  Every child's pencils are loaded before
+// the first translation; children are summed in child order.  A cell
+// without children (a leaf above the last level of an adaptive tree) is
+// left to P2M.
 template <int N>
 __global__ void __launch_bounds__(64)
-k_m2m(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Mc, ChebConst cc,
-      int r, int mp, float *M) {
-    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
-    __shared__ float Ts[2][N][N];
-    __shared__ float Cs[8][64 * Q], B[64 * Q];
-    const int lane = threadIdx.x;
-    const int P = blockIdx.x, c = blockIdx.y;
-    float acc[Q], t[Q];
-    int i1[Q], i2[Q], i3[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = lane + 64 * q;
-        acc[q] = 0.f;
-        i1[q] = i % N;
-        i2[q] = (i / N) % N;
-        i3[q] = (i / (N * N)) % N;
-    }
+k_m2m_pen(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Mc,
+          ChebConst cc, int r, int mp, float *M) {
+    using PN = Pencil<N>;
+    __shared__ float bufs[PN::G][PN::m];
+    const int lane = threadIdx.x, g = lane / PN::NP, p = lane % PN::NP;
+    const int P = blockIdx.x, c = blockIdx.y * PN::G + g;
+    const bool on = g < PN::G && c < r;
     const int c0 = cb[P], nc = min(ce[P] - c0, 8);
-    if (nc <= 0) return;        // a leaf above the last level: P2M writes its coefficients
-    float v[8][Q];
+    if (nc <= 0) return;
+    float *buf = bufs[on ? g : 0];
+    float v[8][N];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = lane + 64 * q;
-            v[k][q] = (k < nc && i < m) ? Mc[(int64_t(c0 + k) * r + c) * mp + i] : 0.f;
-        }
-    load_T<N>(cc, Ts);
+        for (int j = 0; j < N; ++j)
+            v[k][j] = (on && k < nc) ? Mc[(int64_t(c0 + k) * r + c) * mp + p + PN::NP * j] : 0.f;
+    float acc[N];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int j = 0; j < N; ++j) acc[j] = 0.f;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) Cs[k][lane + 64 * q] = v[k][q];
-    __syncthreads();
-    for (int k = 0; k < nc; ++k) {
-        const int o = int(ckeys[c0 + k] & 7);
-        mode3<N>(Cs[k], B, Ts, o, false, i1, i2, i3, t);
+    for (int k = 0; k < 8; ++k) {
+        if (k >= nc) break;
+        float t[N];
+        translate3<N, false>(cc, int(ckeys[c0 + k] & 7), v[k], buf, p, on, t);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] += t[q];
-        __syncthreads();       // B is rewritten by the next child's first mode product
+        for (int j = 0; j < N; ++j) acc[j] += t[j];
     }
-    float *out = M + (int64_t(P) * r + c) * mp;
+    if (on) {
+        float *out = M + (int64_t(P) * r + c) * mp;
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-        if (lane + 64 * q < m) out[lane + 64 * q] = acc[q];
-    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
+        for (int j = 0; j < N; ++j) out[j + N * p] = acc[j];
+        for (int i = PN::m + p; i < mp; i += PN::NP) out[i] = 0.f;
+    }
 }
 
-// L2L: F[cell][c] = (T^T (x) T^T (x) T^T) F[parent][c]   (grid: cells x r)
+// L2L: F[child][c] = (T^T (x) T^T (x) T^T) F[P][c] for every child of P
+// (grid: parents x column groups); the parent's pencils are loaded once.
 template <int N>
 __global__ void __launch_bounds__(64)
-k_l2l(const int32_t *parent, const uint64_t *keys, const float *Fp, ChebConst cc, int r, int mp,
-      float *F) {
-    constexpr int m = NodeIdx<N>::m, Q = NodeIdx<N>::Q;
-    __shared__ float Ts[2][N][N];
-    __shared__ float A[64 * Q], B[64 * Q];
-    const int lane = threadIdx.x;
-    const int a = blockIdx.x, c = blockIdx.y;
-    load_T<N>(cc, Ts);
-    int i1[Q], i2[Q], i3[Q];
+k_l2l_pen(const int32_t *cb, const int32_t *ce, const uint64_t *ckeys, const float *Fp,
+          ChebConst cc, int r, int mp, float *F) {
+    using PN = Pencil<N>;
+    __shared__ float bufs[PN::G][PN::m];
+    const int lane = threadIdx.x, g = lane / PN::NP, p = lane % PN::NP;
+    const int P = blockIdx.x, c = blockIdx.y * PN::G + g;
+    const bool on = g < PN::G && c < r;
+    const int c0 = cb[P], nc = min(ce[P] - c0, 8);
+    if (nc <= 0) return;
+    float *buf = bufs[on ? g : 0];
+    float v[N];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = lane + 64 * q;
-        i1[q] = i % N;
-        i2[q] = (i / N) % N;
-        i3[q] = (i / (N * N)) % N;
+    for (int j = 0; j < N; ++j) v[j] = on ? Fp[(int64_t(P) * r + c) * mp + p + PN::NP * j] : 0.f;
+    for (int k = 0; k < nc; ++k) {
+        float t[N];
+        translate3<N, true>(cc, int(ckeys[c0 + k] & 7), v, buf, p, on, t);
+        if (on) {
+            float *out = F + (int64_t(c0 + k) * r + c) * mp;
+#pragma unroll
+            for (int j = 0; j < N; ++j) out[j + N * p] = t[j];
+            for (int i = PN::m + p; i < mp; i += PN::NP) out[i] = 0.f;
+        }
     }
-    const float *src = Fp + (int64_t(parent[a]) * r + c) * mp;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-        if (lane + 64 * q < m) A[lane + 64 * q] = src[lane + 64 * q];
-    __syncthreads();
-    float t[Q];
-    mode3<N>(A, B, Ts, int(keys[a] & 7), true, i1, i2, i3, t);
-    float *out = F + (int64_t(a) * r + c) * mp;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-        if (lane + 64 * q < m) out[lane + 64 * q] = t[q];
-    for (int i = m + lane; i < mp; i += 64) out[i] = 0.f;
 }
 
 // Y[R][N] = alpha X[R][K] Bt[N][K]^T + beta Y with FP32 MFMA 16x16x4, where
@@ -665,6 +655,8 @@ struct M2LArgs {
     int r, rc, tpt;
     int nsplit;                 // the 189 slots are split over this many workgroups
     int tile0;                  // first tile of this launch
+    int ntiles;                 // tiles of this launch
+    int xsplit;                 // splits pinned to XCDs (m2l_block_tile)
 };
 
 // Block index -> tile so that each XCD (blocks are dealt round-robin over
@@ -674,6 +666,27 @@ __device__ inline int xcd_tile(int bid, int nblocks) {
     const int xcd = bid & 7, idx = bid >> 3;
     const int full = nblocks >> 3, rem = nblocks & 7;
     return xcd * full + min(xcd, rem) + idx;
+}
+
+// Block index -> (tile, slot split).  xsplit = 0: every XCD runs all splits
+// of a contiguous run of tiles (xcd_tile).  xsplit = 1: XCD x runs split
+// x % nsplit only (nsplit divides 8), and the 8 / nsplit XCDs of a split
+// take contiguous runs of its tiles, so the operators of a split's slots
+// (a 1 / nsplit share of the level's) are what its L2s hold.  The launch
+// then has 8 ceil(ntiles nsplit / 8) blocks; false for the few past the end.
+__device__ inline bool m2l_block_tile(int bid, int nblocks, int ntiles, int nsplit, int xsplit,
+                                      int &tile, int &split) {
+    if (!xsplit) {
+        const int vb = xcd_tile(bid, nblocks);
+        split = vb % nsplit;
+        tile = vb / nsplit;
+        return true;
+    }
+    const int x = bid & 7, idx = bid >> 3;
+    const int G = 8 / nsplit, per = (ntiles + G - 1) / G;
+    split = x % nsplit;
+    tile = (x / nsplit) * per + idx;
+    return tile < ntiles;
 }
 
 // Software-pipelined M2L.  A step is (slot j, K chunk kc of 64).  While the
@@ -704,9 +717,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     __shared__ uint8_t sl[kSlots];
     __shared__ int16_t st[kSlots];
-    const int vb = xcd_tile(blockIdx.x, gridDim.x);
-    const int split = vb % g.nsplit;
-    const int tix = g.tile0 + vb / g.nsplit;
+    int tl, split;
+    if (!m2l_block_tile(blockIdx.x, gridDim.x, g.ntiles, g.nsplit, g.xsplit, tl, split)) return;
+    const int tix = g.tile0 + tl;
     const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevel &L = g.lv[tile.x];
     const int o = tile.y, start = tile.z, cnt = tile.w;
@@ -930,6 +943,8 @@ struct M2LArgsLP {
     int r, rc, tpt;
     int nsplit;
     int tile0;
+    int ntiles;
+    int xsplit;
 };
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -948,9 +963,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
     __shared__ int16_t st[kSlots];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int vb = xcd_tile(blockIdx.x, gridDim.x);
-    const int split = vb % g.nsplit;
-    const int tix = g.tile0 + vb / g.nsplit;
+    int tl, split;
+    if (!m2l_block_tile(blockIdx.x, gridDim.x, g.ntiles, g.nsplit, g.xsplit, tl, split)) return;
+    const int tix = g.tile0 + tl;
     const int4 tile = reinterpret_cast<const int4 *>(g.tiles)[tix];
     const M2LLevelLP &L = g.lv[tile.x];
     const int o = tile.y, start = tile.z, cnt = tile.w;
@@ -2098,6 +2113,7 @@ struct Plan {
     // per-level M2L schedule: the upward chain on `up`, one event per level
     bool m2l_early = false;
     bool m2l_block = false;             // 16-bit M2L by parent blocks (k_m2l_blk), no slot split
+    bool m2l_xsplit = false;            // tile M2L: slot splits pinned to XCDs
     int m2l_cb = 4;                     // its 16-column blocks per workgroup (r-tile / 16)
     hipStream_t up = nullptr;
     hipEvent_t lev_ev[kMaxLevels] = {};
@@ -2165,6 +2181,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.m2l_block >= 0 && op.m2l_block <= 2, "m2l_block must be 0, 1 or 2");
     BB_REQUIRE(op.m2l_rtile == 0 || op.m2l_rtile == 16 || op.m2l_rtile == 32 || op.m2l_rtile == 64,
                "m2l_rtile must be 0, 16, 32 or 64");
+    BB_REQUIRE(op.m2l_xcd >= 0 && op.m2l_xcd <= 2, "m2l_xcd must be 0, 1 or 2");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -2219,10 +2236,12 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             }
         }
         ws += p->M[lvl].bytes() + p->F[lvl].bytes();
-        // M2L tiles: runs of up to tpt cells of one octant (Morton order
-        // within the octant), interleaved over the octants run by run, so
-        // that consecutive tiles -- which the launch deals to one XCD --
-        // cover one region of space and share their sources in that L2
+        // M2L tiles: runs of up to tpt cells of one octant (grouped by the
+        // pattern of slots that hold a source, so that a tile's targets
+        // share their visited slots; Morton order within a group),
+        // interleaved over the octants run by run, so that consecutive tiles
+        // -- which the launch deals to one XCD -- cover one region of space
+        // and share their sources in that L2
         p->tile_off[lvl] = int(tl.size() / 4);
         const int *oo = t->lv[lvl].oct_off;
         int nrun = 0;
@@ -2251,10 +2270,12 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     } else if (op.m2l_split > 0) {
         p->nsplit = op.m2l_split;
     } else {
-        const int target = op.m2l_min_waves > 0 ? op.m2l_min_waves : 4;
+        const int target = op.m2l_min_waves > 0 ? op.m2l_min_waves : 16;
         const int64_t wgs = int64_t(p->ntiles) * ceil_div(p->max_kp, 64) * ceil_div(r, p->rc_m2l);
-        while (p->nsplit < 4 && wgs * p->nsplit < int64_t(target) * 256) p->nsplit *= 2;
+        while (p->nsplit < 8 && wgs * p->nsplit < int64_t(target) * 256) p->nsplit *= 2;
     }
+    // slot splits pinned to XCDs where the split count divides the 8 XCDs
+    p->m2l_xsplit = !p->m2l_block && 8 % p->nsplit == 0 && op.m2l_xcd != 1;
     for (int lvl = 2; lvl <= L && o->precision != BBFMM_M2L_FFT; ++lvl) {
         const int64_t C = t->lv[lvl].C;
         p->Fh[lvl].alloc(int64_t(p->nsplit) * C * r * o->lv[lvl].set->kp);
@@ -2381,6 +2402,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_schedule = p->m2l_early ? 2 : 1;
     out->m2l_block = p->m2l_block ? 2 : 1;
     out->m2l_rtile = 16 * p->m2l_cb;
+    out->m2l_xcd = p->m2l_xsplit ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -2773,10 +2795,9 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
     };
     auto m2m = [&](int lvl, hipStream_t st) {
         const LevelData &lv = t.lv[lvl], &ch = t.lv[lvl + 1];
-        dim3 g(lv.C, r);
         switch (n) {
-#define BB_M2M(NN) case NN: k_m2m<NN><<<g, 64, 0, st>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p, \
-            o.cheb, r, mp, p.M[lvl].p); break;
+#define BB_M2M(NN) case NN: k_m2m_pen<NN><<<dim3(unsigned(lv.C), unsigned(ceil_div(r, Pencil<NN>::G))), \
+            64, 0, st>>>(lv.cb.p, lv.ce.p, ch.keys.p, p.M[lvl + 1].p, o.cheb, r, mp, p.M[lvl].p); break;
         BB_M2M(2) BB_M2M(3) BB_M2M(4) BB_M2M(5) BB_M2M(6) BB_M2M(7) BB_M2M(8)
 #undef BB_M2M
         }
@@ -2825,8 +2846,9 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         if (t1 == t0) return;
         int kpmax = 0;
         for (int lvl = lo; lvl <= hi; ++lvl) kpmax = std::max(kpmax, o.lv[lvl].set->kp);
-        dim3 gr(unsigned((t1 - t0) * p.nsplit), unsigned(ceil_div(kpmax, 64)),
-                unsigned(ceil_div(r, p.rc_m2l)));
+        const int ntl = t1 - t0;
+        const int64_t nblk = p.m2l_xsplit ? 8 * ceil_div(ntl, 8 / p.nsplit) : int64_t(ntl) * p.nsplit;
+        dim3 gr(unsigned(nblk), unsigned(ceil_div(kpmax, 64)), unsigned(ceil_div(r, p.rc_m2l)));
         if (o.precision != BBFMM_M2L_FP32) {
             M2LArgsLP g{};
             for (int lvl = lo; lvl <= hi; ++lvl) {
@@ -2844,6 +2866,8 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             g.tpt = p.tpt;
             g.nsplit = p.nsplit;
             g.tile0 = t0;
+            g.ntiles = ntl;
+            g.xsplit = p.m2l_xsplit ? 1 : 0;
             if (o.precision == BBFMM_M2L_BF16X3)
                 k_m2l_lp<BBFMM_M2L_BF16X3><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
             else
@@ -2863,6 +2887,8 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             g.tpt = p.tpt;
             g.nsplit = p.nsplit;
             g.tile0 = t0;
+            g.ntiles = ntl;
+            g.xsplit = p.m2l_xsplit ? 1 : 0;
             if (p.m2l_layout == 2)
                 k_m2l<2><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
             else
@@ -2906,10 +2932,10 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         const LevelData &lv = t.lv[lvl];
         const OpSet &set = *o.lv[lvl].set;
         if (lvl > 2) {
-            dim3 g(lv.C, r);
+            const LevelData &pa = t.lv[lvl - 1];
             switch (n) {
-#define BB_L2L(NN) case NN: k_l2l<NN><<<g, 64, 0, s>>>(lv.parent.p, lv.keys.p, p.F[lvl - 1].p, \
-                o.cheb, r, mp, p.F[lvl].p); break;
+#define BB_L2L(NN) case NN: k_l2l_pen<NN><<<dim3(unsigned(pa.C), unsigned(ceil_div(r, Pencil<NN>::G))), \
+                64, 0, s>>>(pa.cb.p, pa.ce.p, lv.keys.p, p.F[lvl - 1].p, o.cheb, r, mp, p.F[lvl].p); break;
             BB_L2L(2) BB_L2L(3) BB_L2L(4) BB_L2L(5) BB_L2L(6) BB_L2L(7) BB_L2L(8)
 #undef BB_L2L
             }

@@ -312,11 +312,28 @@ k_octant_flags(const uint64_t *keys, int32_t C, int32_t *flag) {
     flag[g] = int(keys[g % C] & 7) == o ? 1 : 0;
 }
 
+// Sort key of a cell for the M2L tiles: its octant in the top 3 bits, then
+// a 61-bit hash of which of its 189 interaction slots hold a source.  Cells
+// of one octant with the same slot pattern (the interior, or one stretch of
+// the boundary) get equal keys, so a stable sort keeps them together in
+// Morton order and a tile's visited slots are those of all its targets.
 __global__ void __launch_bounds__(kThreads)
-k_octant_fill(int32_t C, const int32_t *flag, const int32_t *pos, int32_t *cells) {
-    int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (g >= int64_t(C) * 8 || !flag[g]) return;
-    cells[pos[g]] = int32_t(g % C);
+k_tile_order_keys(const uint64_t *keys, const int32_t *itab, int32_t C, uint64_t *okey,
+                  int32_t *idx) {
+    const int32_t a = blockIdx.x * kThreads + threadIdx.x;
+    if (a >= C) return;
+    uint64_t h = 0xcbf29ce484222325ull;           // FNV-1a over the slot words
+    const int32_t *row = itab + int64_t(a) * kSlots;
+    for (int w = 0; w < (kSlots + 31) / 32; ++w) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32 && 32 * w + b < kSlots; ++b) bits |= uint32_t(row[32 * w + b] >= 0) << b;
+        for (int k = 0; k < 4; ++k) {
+            h ^= (bits >> (8 * k)) & 0xffu;
+            h *= 0x100000001b3ull;
+        }
+    }
+    okey[a] = (uint64_t(keys[a] & 7) << 61) | (h >> 3);
+    idx[a] = a;
 }
 
 // ------------------------------------------- level-adaptive tree
@@ -1079,8 +1096,11 @@ void build_m2l_lists(bbfmm_tree &t, hipStream_t s) {
             const int64_t tot = scan_exclusive(flag.p, pos.p, C * 8, s);
             BB_INTERNAL(tot == C, "octant grouping lost cells");
             lv.oct_cells.alloc(C);
-            k_octant_fill<<<grid(C * 8), kThreads, 0, s>>>(lv.C, flag.p, pos.p, lv.oct_cells.p);
+            DBuf<uint64_t> okey(C);
+            k_tile_order_keys<<<grid(C), kThreads, 0, s>>>(lv.keys.p, lv.itab.p, lv.C, okey.p,
+                                                           lv.oct_cells.p);
             BB_LAUNCH_CHECK();
+            radix_sort_pairs(okey.p, lv.oct_cells.p, C, 64, s);
             k_group_offsets<<<1, 64, 0, s>>>(pos.p, lv.C, 8, lv.C, off.p);
             BB_LAUNCH_CHECK();
             BB_HIP(hipMemcpyAsync(lv.oct_off, off.p, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, s));

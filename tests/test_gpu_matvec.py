@@ -204,21 +204,31 @@ def test_mixed_precision_m2l(prec, tol, kid, prm, n, kind, r):
                                               (2, 0.1, 4, "slab", 70)])
 def test_m2l_wave_layouts(kid, prm, n, kind, r):
     """The FP32 M2L with waves of 16 rows x 64 columns and of 32 x 32 (rank
-    rows past a partial row group masked) against the oracle and each
-    other: the same products in the same order per output, so equal bit for
-    bit."""
+    rows past a partial row group masked), with the slot splits dealt to
+    every XCD or pinned to XCDs (two splits pin, three do not), against the
+    oracle and each other: the same products in the same order per output,
+    so equal bit for bit."""
     import torch
     from paper_1903_02153_amd import bbfmm
     pts, sig = synth.random_cloud(20000, 110 + n, r=r, kind=kind)
     gt, go, ot, oo = _both(pts, sig, kid, prm, n, 1e-5, fixed_depth=5)
     ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
     ts = torch.from_numpy(sig).cuda()
-    outs = []
+    outs = {}
     for layout in (1, 2):
-        got = run_plan(gt, go, ts, m2l_layout=layout, m2l_split=2).cpu().numpy().astype(np.float64)
-        assert_parity(got, ref, TOL, f"M2L wave layout {layout}")
-        outs.append(got)
-    assert np.array_equal(outs[0], outs[1])
+        for xcd in (1, 2):
+            for split in (2, 3):
+                got = run_plan(gt, go, ts, m2l_layout=layout, m2l_split=split,
+                               m2l_xcd=xcd).cpu().numpy().astype(np.float64)
+                assert_parity(got, ref, TOL, f"M2L wave layout {layout} xcd {xcd} split {split}")
+                outs[(layout, xcd, split)] = got
+    # where a product lands does not depend on the block -> (tile, split) mapping
+    for layout in (1, 2):
+        for split in (2, 3):
+            assert np.array_equal(outs[(layout, 1, split)], outs[(layout, 2, split)])
+    for xcd in (1, 2):
+        for split in (2, 3):
+            assert np.array_equal(outs[(1, xcd, split)], outs[(2, xcd, split)])
 
 
 @pytest.mark.parametrize("r", [1, 4, 20, 40, 70])
