@@ -393,6 +393,12 @@ typedef struct {
                             /* 8 / m2l_split XCDs, so a split's operators stay in */
                             /* their L2s (needs m2l_split dividing 8); 0 = 2 when */
                             /* it applies                                        */
+    int32_t leaf_fused;     /* 2: P2M, compression and M2M of the leaf level in   */
+                            /* one kernel per (parent, 16 right-hand sides): the  */
+                            /* leaves' full coefficients never reach HBM; 1: the */
+                            /* three stages as separate kernels; 0 = 1.  Applies  */
+                            /* to uniform trees of at least four levels with the */
+                            /* Chebyshev/SVD M2L (else the stages stay separate) */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a
@@ -464,8 +470,8 @@ bbfmm_status bbfmm_plan_stage_times(bbfmm_plan *plan, double *ms, int64_t *execu
  *   reps        1..100.
  *   best        out: the chosen options (m2l_split, p2p_mfma,
  *               p2p_max_split, overlap, p2p_waves, m2l_occupancy,
- *               m2l_layout, m2l_schedule, m2l_block, m2l_rtile and m2l_xcd
- *               explicit).
+ *               m2l_layout, m2l_schedule, m2l_block, m2l_rtile, m2l_xcd and
+ *               leaf_fused explicit).
  *   best_ms     out (may be NULL): its median milliseconds per product.
  * Allocates and frees one plan workspace per candidate; synchronizes
  * `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.

@@ -520,6 +520,12 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
             c.m2l_xcd = xc;
             consider(c);
         }
+        if (r >= 4)
+            for (int lf = 1; lf <= 2; ++lf) {
+                bbfmm_plan_options c = cur;
+                c.leaf_fused = lf;
+                consider(c);
+            }
         if (cur.overlap == 2)
             for (int occ : {3, 2}) {
                 bbfmm_plan_options c = cur;

@@ -595,6 +595,267 @@ k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *B
     }
 }
 
+// ------------------------------------------- fused leaf upward pass ----
+// P2M, compression and M2M of the leaf level in one kernel (Section 2.3,
+// upward pass; Section 2.5: the right-hand sides as the columns of matrix
+// products).  A workgroup takes one parent cell and 16 right-hand sides.
+// For each child leaf in turn it
+//   A. forms M = S^T sigma (n^3 x 16) on FP32 MFMA into LDS (as k_p2m_mfma:
+//      wave w owns the 16-node row blocks w, w + 4, ...);
+//   B. compresses it, M^ = V^T M (kp x 16) on FP32 MFMA with V^T read from
+//      global memory (wave w owns the rank row blocks w, w + 4, ...), and
+//      writes M^ in the M2L operand format (as k_gemm_nt's epilogues);
+//   C. adds its translation to the parent's coefficients, held as pencils
+//      in registers (as k_m2m_pen; a thread owns up to four (column,
+//      pencil) pairs).
+// The leaves' full coefficients never reach HBM; the parent's are written
+// once.  Per output the sums run in the same order as in the separate
+// kernels except that M feeds the compression from LDS.
+struct LeafUpArgs {
+    const float *xs, *ys, *zs;
+    const int32_t *sb, *pe;          // leaf source ranges (tree order)
+    const uint64_t *keys;            // leaf keys
+    const int32_t *pcb, *pce;        // children of each parent (level L-1)
+    const float *sig_s;
+    int ld, r, mp, kp, nchunk;
+    const float *VT;                 // kp x mp: V^T of the leaf level
+    float *Mh;                       // FP32 operands [leaf][r][kp]
+    uint16_t *Mh16, *Ml16;           // 16-bit operands [leaf][r][kp]
+    float *Msinv;                    // fp16: inverse scales [leaf][r][nchunk]
+    float *Mpar;                     // parent coefficients [parent][r][mp]
+};
+
+template <int N, int OUT>
+__global__ void __launch_bounds__(kThreads)
+k_leaf_up(LeafUpArgs a, Geo geo, ChebConst cc) {
+    constexpr int m = N * N * N, NP = N * N;
+    constexpr int MPAD = ((m + 15) / 16) * 16;    // == mp
+    constexpr int NRBT = MPAD / 16;               // node row blocks
+    constexpr int RBQ = (NRBT + 3) / 4;           // ... per wave
+    constexpr int MS = 17;                        // LDS row stride of M (16 columns + pad)
+    constexpr int PC = 64;                        // points per staging chunk
+    constexpr int TPT = (16 * NP + kThreads - 1) / kThreads;   // pencils per thread
+    constexpr int STAGE = PC * 3 * N + PC * 16;   // floats: Lagrange values + sigma
+    constexpr int SCR = 16 * m;                   // floats: pencil transposes
+    __shared__ float Ms[MPAD * MS];
+    __shared__ float pool[STAGE > SCR ? STAGE : SCR];
+    __shared__ float cmax[4][16];
+    float (*lv)[3][N] = reinterpret_cast<float (*)[3][N]>(pool);
+    float *ss = pool + PC * 3 * N;                // [PC][16]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int P = blockIdx.x, col0 = blockIdx.y * 16;
+    const int c0 = a.pcb[P], nc = a.pce[P] - c0;
+    const int r = a.r, kp = a.kp, nrb = kp / 16;
+    // node decomposition of this lane's P2M rows
+    int n1[RBQ], n2[RBQ], n3[RBQ];
+    float nw[RBQ];
+#pragma unroll
+    for (int q = 0; q < RBQ; ++q) {
+        const int node = 16 * (wave + 4 * q) + (lane & 15);
+        const int nd = node < m ? node : 0;
+        nw[q] = node < m ? 1.f : 0.f;
+        n1[q] = nd % N;
+        n2[q] = (nd / N) % N;
+        n3[q] = nd / NP;
+    }
+    float par[TPT][N];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u)
+#pragma unroll
+        for (int k = 0; k < N; ++k) par[u][k] = 0.f;
+
+    for (int ci = 0; ci < nc; ++ci) {
+        const int c = c0 + ci;
+        const uint64_t key = a.keys[c];
+        // ---- A: P2M into Ms
+        float chi[3], clo[3];
+        for (int d = 0; d < 3; ++d) center_pair(geo.lo[d], compact3(key >> d), geo.h, chi[d], clo[d]);
+        v4f acc[RBQ];
+#pragma unroll
+        for (int q = 0; q < RBQ; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int b = a.sb[c], e = a.pe[c];
+        for (int p0 = b; p0 < e; p0 += PC) {
+            const int np = min(PC, e - p0), npad = (np + 3) & ~3;
+            __syncthreads();                      // previous chunk (or Ms / pool users) done
+            if (tid < PC) {
+                if (tid < np) {
+                    const float p3[3] = {a.xs[p0 + tid], a.ys[p0 + tid], a.zs[p0 + tid]};
+                    for (int d = 0; d < 3; ++d) {
+                        float l[kMaxOrder];
+                        lagrange(cc, local_coord(p3[d], chi[d], clo[d], geo.inv_h), l);
+#pragma unroll
+                        for (int k = 0; k < N; ++k) lv[tid][d][k] = l[k];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+#pragma unroll
+                        for (int k = 0; k < N; ++k) lv[tid][d][k] = 0.f;
+                }
+            }
+            for (int g = tid; g < PC * 16; g += kThreads) {
+                const int pp = g / 16, j = g % 16;
+                ss[g] = (pp < np && col0 + j < r) ? a.sig_s[int64_t(p0 + pp) * a.ld + col0 + j] : 0.f;
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < npad; k0 += 4) {
+                const int pp = k0 + (lane >> 4);
+                const float bv = ss[pp * 16 + (lane & 15)];
+#pragma unroll
+                for (int q = 0; q < RBQ; ++q) {
+                    if (wave + 4 * q >= NRBT) break;
+                    const float av = lv[pp][0][n1[q]] * lv[pp][1][n2[q]] * lv[pp][2][n3[q]] * nw[q];
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();                          // pool free; Ms readers of the last child done
+        // D[i][j] in lane j + 16 (i / 4), register i % 4
+#pragma unroll
+        for (int q = 0; q < RBQ; ++q) {
+            if (wave + 4 * q >= NRBT) break;
+            const int node0 = 16 * (wave + 4 * q) + 4 * (lane >> 4);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ms[(node0 + v) * MS + (lane & 15)] = acc[q][v];
+        }
+        __syncthreads();
+        // ---- B: compression V^T M from Ms.  D[i = rank][j = column] of a
+        // row block sits in lane j + 16 (i / 4), register i % 4.
+        // (the operator rows of GB 16-node steps are requested together; two
+        // accumulators interleave the dependent MFMA chain)
+        auto compress_block = [&](int rb) -> v4f {
+            constexpr int NK = MPAD / 16, GB = 4;
+            v4f d0 = v4f{0.f, 0.f, 0.f, 0.f}, d1 = d0;
+            const float *vrow = a.VT + int64_t(rb * 16 + (lane & 15)) * a.mp + 4 * (lane >> 4);
+            const float *mcol = Ms + 4 * (lane >> 4) * MS + (lane & 15);
+#pragma unroll
+            for (int g0 = 0; g0 < NK; g0 += GB) {
+                float4 av[GB];
+#pragma unroll
+                for (int u = 0; u < GB; ++u)
+                    if (g0 + u < NK) av[u] = *reinterpret_cast<const float4 *>(vrow + 16 * (g0 + u));
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    if (g0 + u >= NK) break;
+                    const float *mrow = mcol + 16 * (g0 + u) * MS;
+                    v4f &d = (u & 1) ? d1 : d0;
+                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].x, mrow[0], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].y, mrow[MS], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].z, mrow[2 * MS], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u].w, mrow[3 * MS], d, 0, 0, 0);
+                }
+            }
+            return d0 + d1;
+        };
+        const int col = col0 + (lane & 15);
+        const int64_t orow = int64_t(c) * r + col;     // output row (leaf, column)
+        if constexpr (OUT != kOutF16S) {
+            for (int rb = wave; rb < nrb; rb += 4) {
+                const v4f d = compress_block(rb);
+                const int k4 = rb * 16 + 4 * (lane >> 4);
+                if (col >= r) continue;
+                if constexpr (OUT == kOutF32) {
+                    *reinterpret_cast<float4 *>(a.Mh + orow * kp + k4) = make_float4(d[0], d[1], d[2], d[3]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint16_t h = to_bf16(d[v]);
+                        a.Mh16[orow * kp + k4 + v] = h;
+                        a.Ml16[orow * kp + k4 + v] = to_bf16(d[v] - from_bf16(h));
+                    }
+                }
+            }
+        } else {
+            // one power-of-two scale per (column, 64-rank chunk), max |x| 2^e in
+            // [2^14, 2^15): the chunk's four row blocks are waves 0..3
+            for (int ch = 0; ch < a.nchunk; ++ch) {
+                const int rb = 4 * ch + wave;
+                const v4f d = rb < nrb ? compress_block(rb) : v4f{0.f, 0.f, 0.f, 0.f};
+                float mx = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
+                mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+                mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+                if (lane < 16) cmax[wave][lane] = mx;
+                __syncthreads();
+                mx = fmaxf(fmaxf(cmax[0][lane & 15], cmax[1][lane & 15]),
+                           fmaxf(cmax[2][lane & 15], cmax[3][lane & 15]));
+                const int e = mx > 0.f ? max(-126, min(126, 14 - ilogbf(mx))) : 0;
+                if (rb < nrb && col < r) {
+                    const int k4 = rb * 16 + 4 * (lane >> 4);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a.Mh16[orow * kp + k4 + v] = to_f16(ldexpf(d[v], e));
+                }
+                if (wave == 0 && lane < 16 && col < r) a.Msinv[orow * a.nchunk + ch] = ldexpf(1.f, -e);
+                __syncthreads();                  // cmax read before the next chunk writes it
+            }
+        }
+        __syncthreads();                          // Ms complete for C; pool free
+        // ---- C: translate into the parent (pencils; child octant uniform)
+        const int oct = int(key & 7);
+        float w[TPT][N];
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+            const bool on = task < 16 * NP;
+            float v[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = on ? Ms[(pnc + NP * k) * MS + j] : 0.f;
+            mode1<N, false>(cc, (oct >> 2) & 1, v, w[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+            if (task < 16 * NP)
+#pragma unroll
+                for (int k = 0; k < N; ++k) pool[j * m + pnc + NP * k] = w[u][k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+            const int a1 = pnc % N, a3 = pnc / N;
+            float v[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = task < 16 * NP ? pool[j * m + a1 + N * k + NP * a3] : 0.f;
+            mode1<N, false>(cc, (oct >> 1) & 1, v, w[u]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+            const int a1 = pnc % N, a3 = pnc / N;
+            if (task < 16 * NP)
+#pragma unroll
+                for (int k = 0; k < N; ++k) pool[j * m + a1 + N * k + NP * a3] = w[u][k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+            float v[N], t[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = task < 16 * NP ? pool[j * m + k + N * pnc] : 0.f;
+            mode1<N, false>(cc, oct & 1, v, t);
+#pragma unroll
+            for (int k = 0; k < N; ++k) par[u][k] += t[k];
+        }
+    }
+    // ---- the parent's coefficients (x-pencils: node k + N pencil)
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int task = tid + kThreads * u, j = task / NP, pnc = task % NP;
+        if (task < 16 * NP && col0 + j < r) {
+            float *out = a.Mpar + (int64_t(P) * r + col0 + j) * a.mp;
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k + N * pnc] = par[u][k];
+        }
+    }
+    for (int g = tid; g < 16 * (a.mp - m); g += kThreads) {
+        const int j = g / (a.mp - m);
+        if (col0 + j < r) a.Mpar[(int64_t(P) * r + col0 + j) * a.mp + m + g % (a.mp - m)] = 0.f;
+    }
+}
+
 // --------------------------------------------------------------- M2L ----
 // One workgroup = one tile of up to 64 columns (target, rhs) of targets that
 // share an octant, times 64 rows of the compressed rank.  For every slot
@@ -2114,6 +2375,7 @@ struct Plan {
     bool m2l_early = false;
     bool m2l_block = false;             // 16-bit M2L by parent blocks (k_m2l_blk), no slot split
     bool m2l_xsplit = false;            // tile M2L: slot splits pinned to XCDs
+    bool leaf_fused = false;            // P2M + compression + M2M of the leaf level fused
     int m2l_cb = 4;                     // its 16-column blocks per workgroup (r-tile / 16)
     hipStream_t up = nullptr;
     hipEvent_t lev_ev[kMaxLevels] = {};
@@ -2182,6 +2444,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.m2l_rtile == 0 || op.m2l_rtile == 16 || op.m2l_rtile == 32 || op.m2l_rtile == 64,
                "m2l_rtile must be 0, 16, 32 or 64");
     BB_REQUIRE(op.m2l_xcd >= 0 && op.m2l_xcd <= 2, "m2l_xcd must be 0, 1 or 2");
+    BB_REQUIRE(op.leaf_fused >= 0 && op.leaf_fused <= 2, "leaf_fused must be 0, 1 or 2");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -2208,12 +2471,16 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     p->ld_s = p->p2p_mfma ? int(16 * p->ncb_p2p * ceil_div(r, 16 * p->ncb_p2p)) : int(r);
     p->sig_s.alloc(t->n * p->ld_s);
     int64_t ws = p->sig_s.bytes();
+    // the fused leaf pass needs a parent level with expansions (L >= 3)
+    // (off by default: on the batched workloads the separate kernels are
+    // faster; the autotuner measures both)
+    p->leaf_fused = !t->adaptive && L >= 3 && o->precision != BBFMM_M2L_FFT && op.leaf_fused == 2;
     std::vector<int32_t> tl;
     for (int lvl = 2; lvl <= L; ++lvl) {
         const int64_t C = t->lv[lvl].C;
         const int kp = o->lv[lvl].set->kp;
         p->max_kp = std::max(p->max_kp, kp);
-        p->M[lvl].alloc(C * r * mp);
+        if (!(p->leaf_fused && lvl == L)) p->M[lvl].alloc(C * r * mp);   // fused: leaf M stays on chip
         p->F[lvl].alloc(C * r * mp);
         if (o->precision == BBFMM_M2L_FFT) {
             const int64_t Q = fft_freqs(o->n);
@@ -2403,6 +2670,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_block = p->m2l_block ? 2 : 1;
     out->m2l_rtile = 16 * p->m2l_cb;
     out->m2l_xcd = p->m2l_xsplit ? 2 : 1;
+    out->leaf_fused = p->leaf_fused ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -2711,7 +2979,44 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         BB_HIP(hipEventRecord(p.join, p.side));
     }
     mark(BBFMM_STAGE_P2M);
-    if (L >= 2 && t.adaptive) {
+    if (p.leaf_fused) {
+        // P2M, compression and M2M of the leaf level (k_leaf_up)
+        const OpSet &set = *o.lv[L].set;
+        LeafUpArgs la{};
+        la.xs = t.xs.p;
+        la.ys = t.ys.p;
+        la.zs = t.zs.p;
+        la.sb = t.src_begin();
+        la.pe = t.lv[L].pe.p;
+        la.keys = t.lv[L].keys.p;
+        la.pcb = t.lv[L - 1].cb.p;
+        la.pce = t.lv[L - 1].ce.p;
+        la.sig_s = p.sig_s.p;
+        la.ld = p.ld_s;
+        la.r = r;
+        la.mp = mp;
+        la.kp = set.kp;
+        la.nchunk = int(ceil_div(set.kp, 64));
+        la.VT = set.VT32.p;
+        la.Mh = p.Mh[L].p;
+        la.Mh16 = p.Mh16[L].p;
+        la.Ml16 = p.Ml16[L].p;
+        la.Msinv = p.Msinv[L].p;
+        la.Mpar = p.M[L - 1].p;
+        dim3 g(unsigned(t.lv[L - 1].C), unsigned(ceil_div(r, 16)));
+#define BB_LU(NN)                                                                                   \
+        case NN:                                                                                    \
+            if (o.precision == BBFMM_M2L_FP32)                                                      \
+                k_leaf_up<NN, kOutF32><<<g, kThreads, 0, s>>>(la, geo, o.cheb);                     \
+            else if (o.precision == BBFMM_M2L_BF16X3)                                               \
+                k_leaf_up<NN, kOutBF16X3><<<g, kThreads, 0, s>>>(la, geo, o.cheb);                  \
+            else                                                                                    \
+                k_leaf_up<NN, kOutF16S><<<g, kThreads, 0, s>>>(la, geo, o.cheb);                    \
+            break;
+        switch (n) { BB_LU(2) BB_LU(3) BB_LU(4) BB_LU(5) BB_LU(6) BB_LU(7) BB_LU(8) }
+#undef BB_LU
+        BB_LAUNCH_CHECK();
+    } else if (L >= 2 && t.adaptive) {
         // leaves of every level >= 2 (M2M skips them)
         const LevelData &fl = t.leaves();
         for (int lvl = 2; lvl <= L; ++lvl) {
@@ -2896,11 +3201,12 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         }
         BB_LAUNCH_CHECK();
     };
-    if (L >= 2) compress(L, s);
+    // the fused leaf pass already compressed level L and formed level L-1
+    if (L >= 2 && !p.leaf_fused) compress(L, s);
     if (!p.m2l_early) {
         mark(BBFMM_STAGE_M2M);
         for (int lvl = L - 1; lvl >= 2; --lvl) {
-            m2m(lvl, s);
+            if (!(p.leaf_fused && lvl == L - 1)) m2m(lvl, s);
             compress(lvl, s);
         }
         mark(BBFMM_STAGE_M2L);
@@ -2915,7 +3221,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         BB_HIP(hipStreamWaitEvent(p.up, p.lev_ev[L], 0));
         if (ev) BB_HIP(hipEventRecord(ev[kEvUpBeg], p.up));
         for (int lvl = L - 1; lvl >= 2; --lvl) {
-            m2m(lvl, p.up);
+            if (!(p.leaf_fused && lvl == L - 1)) m2m(lvl, p.up);
             compress(lvl, p.up);
             BB_HIP(hipEventRecord(p.lev_ev[lvl], p.up));
         }

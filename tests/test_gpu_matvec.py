@@ -274,11 +274,12 @@ def test_autotune_options_are_valid_and_exact(r):
     for key in ("device_buffers", "device_bytes", "plans", "events"):
         assert after[key] == before[key], (key, before, after)
     assert ms > 0
-    assert 1 <= opts["m2l_split"] <= 4 and opts["p2p_mfma"] in (1, 2)
+    assert opts["m2l_split"] in (1, 2, 3, 4, 8) and opts["p2p_mfma"] in (1, 2)
     assert opts["p2p_max_split"] in (4, 8, 16) and opts["overlap"] in (1, 2)
     assert opts["p2p_waves"] in (0, 512, 1024, 2048, 4096)
     assert opts["m2l_occupancy"] in (0, 2, 3) and opts["m2l_layout"] in (1, 2)
     assert opts["m2l_schedule"] in (1, 2)
+    assert opts["m2l_xcd"] in (1, 2) and opts["leaf_fused"] in (1, 2)
     phi = run_plan(gt, go, ts, **opts)
     ref = ofmm.matvec(ot, oo, pts, sig, 0, 1.0)
     assert_parity(phi.cpu().numpy(), ref, TOL, f"autotuned r {r} {opts}")
@@ -364,6 +365,8 @@ def test_graph_replay_matches_eager():
 
 @pytest.mark.parametrize("r,opts", [(1, dict(p2p_mfma=1)), (3, dict(p2p_mfma=1, overlap=1)),
                                     (5, dict(p2p_mfma=2)), (20, dict(p2p_mfma=2)),
+                                    (20, dict(p2p_mfma=2, leaf_fused=1)),
+                                    (5, dict(p2p_mfma=1, leaf_fused=2)),
                                     (2, dict(p2p_mfma=1, overlap=2))])
 def test_separate_target_and_source_sets(r, opts):
     """eq. (1) with distinct targets and sources: one tree over both sets
@@ -475,3 +478,32 @@ def test_block_m2l_rtiles_agree(prec):
     oo = oops.precompute(ot, 2, 0.08, 5, 1e-5)
     ref = ofmm.matvec(ot, oo, pts, sig, 2, 0.08)
     assert_parity(outs[0], ref, TOL if prec == 1 else 1e-3, f"block M2L r-tiles precision {prec}")
+
+
+# P2M, compression and M2M of the leaf level fused into one kernel (the
+# leaves' full coefficients stay on chip) against the oracle, beside the
+# separate kernels, for the three M2L operand formats, ragged column counts
+# (r not a multiple of 16) and ranks past 64 (several 64-rank scale chunks).
+@pytest.mark.parametrize("prec,tol,kid,prm,n,kind,r,eps", [
+    (0, TOL, 0, 1.0, 5, "uniform", 16, 1e-5),
+    (0, TOL, 1, 0.2, 6, "clustered", 21, 1e-7),
+    (1, TOL, 2, 0.1, 7, "slab", 40, 1e-5),
+    (2, 1e-3, 2, 0.1, 7, "slab", 64, 1e-5),
+    (2, 1e-3, 1, 0.3, 4, "uniform", 7, 1e-6),
+    (0, TOL, 100, 0.7, 4, "uniform", 3, 0.0),
+])
+def test_fused_leaf_pass(prec, tol, kid, prm, n, kind, r, eps):
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(15000, 300 + n + r, r=r, kind=kind)
+    gt = gpu_tree(pts, kid, prm, n, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, eps, prec)
+    ot = oracle_tree(pts, fixed_depth=5)
+    oo = oops.precompute(ot, kid, prm, n, eps)
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    outs = {}
+    for lf in (1, 2):
+        got = run_plan(gt, go, sig, leaf_fused=lf).cpu().numpy().astype(np.float64)
+        assert_parity(got, ref, tol, f"precision {prec} n {n} r {r} leaf_fused {lf}")
+        outs[lf] = got
+    # the same arithmetic per output up to the summation order of M into V^T M
+    assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < tol
