@@ -899,13 +899,13 @@ __device__ inline int tile_slot_list(const uint32_t *mask, int jlo, int jhi, con
 }
 
 struct M2LLevel {
-    const float *Mh;
+    const float *Mh;            // [C + 1][r][kp]: the extra cell C is all zeros
     float *Fh;                  // nsplit partial results, each [C][r][kp]
     const float *C32;
     const int32_t *itab;
     const int32_t *oct_cells;
     int kp;
-    int64_t rows;               // C r: rows of one partial result
+    int64_t rows;               // C r: rows of one partial result (the zero cell is rows / r)
 };
 
 struct M2LArgs {
@@ -965,7 +965,11 @@ __device__ inline bool m2l_block_tile(int bid, int nblocks, int ntiles, int nspl
 // on how targets are grouped into tiles.  The last K chunk of a rank that
 // is not a multiple of 64 issues only its nonzero 16-deep MFMA blocks, and
 // waves whose 16 rows lie past the rank issue no MFMAs.
-template <int RW>
+// FULL: every level of the launch has a rank padded to a whole 64-row
+// group and every tile column is a right-hand side (r a multiple of the
+// column tile), so no load needs a mask: a missing source reads the zero
+// cell, and the per-element mask multiplies are gone.
+template <int RW, bool FULL>
 __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     static_assert(RW == 4 || RW == 2, "row waves");
     constexpr int RB = 4 / RW;          // 16-row blocks per wave
@@ -1034,22 +1038,31 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     // Loads are issued unconditionally from clamped in-bounds addresses and
     // masked afterwards: no branches, so the compiler never has to drain the
     // prefetches before the MFMAs of the current step.
-    auto load_b = [&](int j, int kc, float4 *breg) {
+    const int zc = int(L.rows / r);                      // the zero cell
+    auto load_b = [&](int j, int kc, float4 (&breg)[4]) {
         const int lim = min(64, kp - kc * 64) / 4;   // float4 per column in this chunk
         const int32_t *sj = srcs[j % 3];
         int sc[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) sc[i] = sj[btl[i]];
+        if constexpr (FULL) {
+            (void)lim;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const bool ok = sc[i] >= 0 && boff[i] >= 0 && bq[i] < lim;
-            const float w = ok ? 1.f : 0.f;      // Mh is finite: 0 * v == 0
-            const float4 v = *reinterpret_cast<const float4 *>(
-                Mh + (ok ? int64_t(sc[i]) * r * kp + boff[i] + kc * 64 : 0));
-            breg[i] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
+            for (int i = 0; i < 4; ++i)
+                breg[i] = *reinterpret_cast<const float4 *>(
+                    Mh + int64_t(sc[i] >= 0 ? sc[i] : zc) * r * kp + boff[i] + kc * 64);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = sc[i] >= 0 && boff[i] >= 0 && bq[i] < lim;
+                const float w = ok ? 1.f : 0.f;      // Mh is finite: 0 * v == 0
+                const float4 v = *reinterpret_cast<const float4 *>(
+                    Mh + (ok ? int64_t(sc[i]) * r * kp + boff[i] + kc * 64 : 0));
+                breg[i] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
+            }
         }
     };
-    auto store_b = [&](int buf, const float4 *breg) {
+    auto store_b = [&](int buf, const float4 (&breg)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + i * kThreads;
@@ -1061,18 +1074,27 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
 #pragma unroll
     for (int b = 0; b < RB; ++b)
         arow[b] = int64_t(rok[b] ? rowb + 16 * b + (lane & 15) : 0) * kp + 4 * (lane >> 4);
-    auto load_a = [&](int j, int kc, float4 *areg) {      // areg[b * 4 + kb]
+    auto load_a = [&](int j, int kc, float4 (&areg)[4 * RB]) {      // areg[b * 4 + kb]
         const int nkb = min(64, kp - kc * 64) / 16;
         const float *A = L.C32 + int64_t(st[j]) * kp * kp + kc * 64;
+        if constexpr (FULL) {
+            (void)nkb;
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
+            for (int b = 0; b < RB; ++b)
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const bool ok = rok[b] && kb < nkb;    // wave-uniform
-                const float w = ok ? 1.f : 0.f;        // C32 is finite: 0 * v == 0
-                const float4 v = *reinterpret_cast<const float4 *>(A + arow[b] + (ok ? 16 * kb : 0));
-                areg[b * 4 + kb] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
-            }
+                for (int kb = 0; kb < 4; ++kb)
+                    areg[b * 4 + kb] = *reinterpret_cast<const float4 *>(A + arow[b] + 16 * kb);
+        } else {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const bool ok = rok[b] && kb < nkb;    // wave-uniform
+                    const float w = ok ? 1.f : 0.f;        // C32 is finite: 0 * v == 0
+                    const float4 v = *reinterpret_cast<const float4 *>(A + arow[b] + (ok ? 16 * kb : 0));
+                    areg[b * 4 + kb] = make_float4(v.x * w, v.y * w, v.z * w, v.w * w);
+                }
+        }
     };
 
     v4f acc[RB][CB];
@@ -1080,7 +1102,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     for (int b = 0; b < RB; ++b)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[b][cb] = v4f{0.f, 0.f, 0.f, 0.f};
-    float4 breg[4], a0[4 * RB], a1[4 * RB];
+    float4 a0[4 * RB], a1[4 * RB];
     int32_t itab_next = -1;
     int j = jbeg, kc = 0;
     // One step: prefetch step s+1 (sources into breg, C_t rows into anxt,
@@ -1088,11 +1110,12 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     // publish the prefetch.  Every prefetching step issues the same nine
     // unconditional loads per thread, so the compiler's wait counts stay
     // exact and the MFMAs never wait on the loads of the step they overlap.
-    auto step = [&](auto more_c, int s, const float4 *acur, float4 *anxt) {
+    auto step = [&](auto more_c, int s, const float4 (&acur)[4 * RB], float4 (&anxt)[4 * RB]) {
         constexpr bool MORE = decltype(more_c)::value;
         int j1 = j, kc1 = kc + 1;
         if (kc1 == nkc) { kc1 = 0; ++j1; }
         const bool new_slot = MORE && kc1 == 0 && j + 3 < jend;
+        float4 breg[4];                  // this step's prefetch of the next sources
         if constexpr (MORE) {
             load_b(j1, kc1, breg);
             load_a(j1, kc1, anxt);
@@ -1103,7 +1126,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
         // MFMA block: the 16-deep K blocks of this chunk that hold nonzero
         // rank (the zero-padded tail of a rank is skipped); waves whose rows
         // lie past the rank skip it entirely.  Both conditions are uniform.
-        const int nkb = active ? min(64, kp - kc * 64) / 16 : 0;
+        const int nkb = FULL ? 4 : (active ? min(64, kp - kc * 64) / 16 : 0);
         const float *B = Bs[s & 1] + (colb + (lane & 15)) * ldb + 4 * (lane >> 4);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
@@ -1144,6 +1167,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l(M2LArgs g) {
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
     if (nsteps > 0) {                    // uniform: no slot of this split has a source -> zeros
+        float4 breg[4];
         load_b(jbeg, 0, breg);
         store_b(0, breg);
         load_a(jbeg, 0, a0);
@@ -2489,7 +2513,9 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             ws += p->Mc[lvl].bytes() + p->Fc[lvl].bytes() + p->M[lvl].bytes() + p->F[lvl].bytes();
             continue;            // no compressed operands, no M2L tiles
         } else if (o->precision == BBFMM_M2L_FP32) {
-            p->Mh[lvl].alloc(C * r * kp);
+            // one zero cell past the last: the M2L's missing sources read it
+            p->Mh[lvl].alloc((C + 1) * r * kp);
+            BB_HIP(hipMemsetAsync(p->Mh[lvl].p + C * r * kp, 0, size_t(r) * kp * sizeof(float), setup));
             ws += p->Mh[lvl].bytes();
         } else {
             p->Mh16[lvl].alloc(C * r * kp);
@@ -2618,8 +2644,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         // CU (160 KiB of LDS each), leaving registers to a concurrent kernel
         hipFuncAttributes fa{};
         if (o->precision == BBFMM_M2L_FP32)
-            BB_HIP(hipFuncGetAttributes(&fa, op.m2l_layout == 2 ? reinterpret_cast<const void *>(k_m2l<2>)
-                                                              : reinterpret_cast<const void *>(k_m2l<4>)));
+            BB_HIP(hipFuncGetAttributes(&fa, op.m2l_layout == 2 ? reinterpret_cast<const void *>(k_m2l<2, false>)
+                                                              : reinterpret_cast<const void *>(k_m2l<4, false>)));
         else if (o->precision == BBFMM_M2L_BF16X3)
             BB_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_m2l_lp<BBFMM_M2L_BF16X3>)));
         else
@@ -3194,10 +3220,15 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             g.tile0 = t0;
             g.ntiles = ntl;
             g.xsplit = p.m2l_xsplit ? 1 : 0;
-            if (p.m2l_layout == 2)
-                k_m2l<2><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
-            else
-                k_m2l<4><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+            bool full = r % p.rc_m2l == 0;
+            for (int lvl = lo; lvl <= hi; ++lvl) full = full && o.lv[lvl].set->kp % 64 == 0;
+            if (p.m2l_layout == 2) {
+                if (full) k_m2l<2, true><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+                else k_m2l<2, false><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+            } else {
+                if (full) k_m2l<4, true><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+                else k_m2l<4, false><<<gr, kThreads, p.m2l_pad_lds, st>>>(g);
+            }
         }
         BB_LAUNCH_CHECK();
     };
