@@ -542,54 +542,73 @@ k_gemm_nt(const float *X, int64_t ldx, int nsum, int64_t xstride, const float *B
         for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4[cb].w, acc[cb], 0, 0, 0);
     }
     if constexpr (OUT == kOutF32) {
+        // through LDS, so that each row of the wave's 16 x 64 tile is read
+        // (beta) and written as 256 contiguous bytes
+        __shared__ float tile[4][16][64 + 4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            if (!bok[cb]) continue;
-            const int col = col0 + cb * 16 + (lane & 15);
+        for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = row0 + 4 * (lane >> 4) + v;
-                if (row < R) {
-                    float *y = Y + row * ldy + col;
-                    *y = alpha * acc[cb][v] + (beta != 0.f ? beta * *y : 0.f);
-                }
+            for (int v = 0; v < 4; ++v) tile[wave][4 * (lane >> 4) + v][cb * 16 + (lane & 15)] = acc[cb][v];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int idx = it * 64 + lane, rr = idx >> 4, q = idx & 15;
+            const int64_t row = row0 + rr;
+            const int col = col0 + 4 * q;
+            if (row >= R || col >= Ncol) continue;
+            const float4 d = *reinterpret_cast<const float4 *>(&tile[wave][rr][4 * q]);
+            float4 *y = reinterpret_cast<float4 *>(Y + row * ldy + col);
+            float4 o = make_float4(alpha * d.x, alpha * d.y, alpha * d.z, alpha * d.w);
+            if (beta != 0.f) {
+                const float4 old = *y;
+                o = make_float4(o.x + beta * old.x, o.y + beta * old.y, o.z + beta * old.z, o.w + beta * old.w);
             }
-        }
-    } else if constexpr (OUT == kOutBF16X3) {
-        // x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            if (!bok[cb]) continue;
-            const int col = col0 + cb * 16 + (lane & 15);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = row0 + 4 * (lane >> 4) + v;
-                if (row < R) {
-                    const float x = alpha * acc[cb][v];
-                    const uint16_t h = to_bf16(x);
-                    Yh[row * ldy + col] = h;
-                    Yl[row * ldy + col] = to_bf16(x - from_bf16(h));
-                }
-            }
+            *y = o;
         }
     } else {
-        // one power-of-two scale per (row, 64-column chunk): max |x| 2^e in [2^14, 2^15)
+        // 16-bit outputs, converted in registers and written through LDS so
+        // that each row of the wave's 16 x 64 tile leaves as 128 contiguous
+        // bytes per plane.  BF16x3: x = hi + lo with hi = bf16(x), lo =
+        // bf16(x - hi).  Scaled FP16: one power-of-two scale per (row,
+        // 64-column chunk), max |x| 2^e in [2^14, 2^15).
+        constexpr int NPL = OUT == kOutBF16X3 ? 2 : 1;
+        __shared__ uint16_t tile16[NPL][4][16][64 + 8];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            float mx = 0.f;
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) mx = fmaxf(mx, bok[cb] ? fabsf(alpha * acc[cb][v]) : 0.f);
-            for (int msk = 1; msk < 16; msk <<= 1) mx = fmaxf(mx, __shfl_xor(mx, msk, 64));
-            const int e = mx > 0.f ? max(-126, min(126, 14 - ilogbf(mx))) : 0;
-            const int64_t row = row0 + 4 * (lane >> 4) + v;
-            if (row < R) {
+            const int rr = 4 * (lane >> 4) + v;
+            if constexpr (OUT == kOutBF16X3) {
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
-                    if (!bok[cb]) continue;
-                    const int col = col0 + cb * 16 + (lane & 15);
-                    Yh[row * ldy + col] = to_f16(ldexpf(alpha * acc[cb][v], e));
+                    const float x = alpha * acc[cb][v];
+                    const uint16_t h = to_bf16(x);
+                    tile16[0][wave][rr][cb * 16 + (lane & 15)] = h;
+                    tile16[NPL - 1][wave][rr][cb * 16 + (lane & 15)] = to_bf16(x - from_bf16(h));
                 }
-                if ((lane & 15) == 0) Sinv[row * nchunk + blockIdx.y] = ldexpf(1.f, -e);
+            } else {
+                float mx = 0.f;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) mx = fmaxf(mx, bok[cb] ? fabsf(alpha * acc[cb][v]) : 0.f);
+                for (int msk = 1; msk < 16; msk <<= 1) mx = fmaxf(mx, __shfl_xor(mx, msk, 64));
+                const int e = mx > 0.f ? max(-126, min(126, 14 - ilogbf(mx))) : 0;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    tile16[0][wave][rr][cb * 16 + (lane & 15)] = to_f16(ldexpf(alpha * acc[cb][v], e));
+                const int64_t row = row0 + rr;
+                if (row < R && (lane & 15) == 0) Sinv[row * nchunk + blockIdx.y] = ldexpf(1.f, -e);
+            }
+        }
+        __syncthreads();
+        // 16 rows x 8 pieces of 8 halves per plane: two pieces per lane
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = it * 64 + lane, rr = idx >> 3, q = idx & 7;
+            const int64_t row = row0 + rr;
+            const int col = col0 + 8 * q;
+            if (row >= R || col >= Ncol) continue;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                uint16_t *dst = (pl == 0 ? Yh : Yl) + row * ldy + col;
+                *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(&tile16[pl][wave][rr][8 * q]);
             }
         }
     }
