@@ -18,13 +18,16 @@
 // used first when the budget needs room.
 //
 // Batch invariance: every plan the server makes splits the M2L slot range
-// over the same kServeSplit workgroups and runs the near field on MFMA for
-// every R.  With those fixed, the arithmetic of one right-hand side does
-// not depend on the batch width R or on the other columns (P2M/M2M/L2L run
-// one wave per (cell, column), the (de)compression GEMMs, the M2L and the
-// MFMA near field accumulate each column in a fixed order), so a request's
-// phi is bit-identical to a lone plan execution with m2l_split = kServeSplit
-// and p2p_mfma = 2, whatever batch it ran in.
+// over the same kServeSplit workgroups and, from R = 2 on, runs the near
+// field on MFMA (a batch of width 1 -- one request with r = 1 -- takes the
+// per-lane near field, the faster one for a single column).  With those
+// fixed, the arithmetic of one right-hand side does not depend on the batch
+// width R >= 2 or on the other columns (P2M/M2M/L2L work per (cell,
+// column), the (de)compression GEMMs, the M2L and the MFMA near field
+// accumulate each column in a fixed order), so a request's phi is
+// bit-identical to a lone plan execution with m2l_split = kServeSplit and
+// p2p_mfma = 2 whatever batch of width >= 2 it ran in, and to one with
+// p2p_mfma = 1 when it ran alone at R = 1.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -216,7 +219,7 @@ struct Server {
         const Model &m = models[mdl];
         bbfmm_plan_options opt{};
         opt.m2l_split = kServeSplit;
-        opt.p2p_mfma = 2;
+        opt.p2p_mfma = R == 1 ? 1 : 2;
         struct PlanDel {
             void operator()(Plan *q) const { plan_destroy(q); }
         };
@@ -312,7 +315,10 @@ struct Server {
         while (!stop) {
             retire();
             bool progressed = false;
-            if (!pending.empty()) {
+            int pick = -1;
+            for (size_t k = 0; k < slots.size(); ++k)
+                if (!slots[k].busy) { pick = int(k); break; }
+            if (!pending.empty() && pick >= 0) {
                 // batch: the oldest request and later ones of the same model
                 const int mdl = pending.front()->model;
                 std::vector<Request *> batch;
@@ -325,10 +331,7 @@ struct Server {
                 }
                 int R = 1;
                 while (R < tot) R *= 2;
-                int pick = -1;
-                for (size_t k = 0; k < slots.size(); ++k)
-                    if (!slots[k].busy) { pick = int(k); break; }
-                if (pick >= 0) {
+                if (!batch.empty()) {
                     bool ok = false;
                     try {
                         ok = launch(size_t(pick), batch, R);
@@ -475,7 +478,7 @@ bbfmm_status bbfmm_server_wait(bbfmm_server *sv, uint64_t request_id, bbfmm_requ
         }
         const bbfmm_status st = rq->status;
         const std::string err = rq->error;
-        s.requests.erase(it);
+        s.requests.erase(request_id);      // `it` may be stale: submits rehash the map
         if (st != BBFMM_OK) fail(st, "%s", err.c_str());
         return BBFMM_OK;
     } catch (const Exception &e) {

@@ -46,17 +46,19 @@ def test_mix_equals_alone_and_batches():
     stats = [srv.wait(rid) for _, _, _, rid in reqs]
     torch.cuda.synchronize()
     # Batch invariance: with the M2L slot split and the near-field path fixed
-    # (the server uses split 2 and the MFMA near field), a column's
+    # (the server uses split 2, the MFMA near field for batches of width
+    # >= 2 and the per-lane one for a lone r = 1 request), a column's
     # arithmetic does not depend on the batch, so every request equals a
     # lone plan execution bit for bit.
     lone = {}
     for (m, sig, phi, _), st in zip(reqs, stats):
         t, o = models[m][:2]
         r = sig.shape[1]
-        if (m, r) not in lone:
-            lone[(m, r)] = bbfmm.Plan(t, o, r, m2l_split=2, p2p_mfma=2)
+        path = 1 if st["batch_r"] == 1 else 2
+        if (m, r, path) not in lone:
+            lone[(m, r, path)] = bbfmm.Plan(t, o, r, m2l_split=2, p2p_mfma=path)
         alone = torch.empty_like(sig)
-        lone[(m, r)].execute(sig, alone)
+        lone[(m, r, path)].execute(sig, alone)
         torch.cuda.synchronize()
         assert torch.equal(phi, alone), (m, r, st["batch_r"])
         assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
