@@ -399,6 +399,13 @@ typedef struct {
                             /* three stages as separate kernels; 0 = 1.  Applies  */
                             /* to uniform trees of at least four levels with the */
                             /* Chebyshev/SVD M2L (else the stages stay separate) */
+    int32_t p2p_pack;       /* per-lane near field, one right-hand side, on the  */
+                            /* overlapped schedule: 2 = each wave holds 1, 2 or 4 */
+                            /* targets per lane and any number S <= 16 of        */
+                            /* sub-lanes per target, picked per leaf so that the */
+                            /* leaf's targets fill the 64 lanes; 1 = power-of-two */
+                            /* sub-lanes, one target per lane; 0 = 2 where it     */
+                            /* applies                                           */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a
@@ -415,6 +422,10 @@ bbfmm_status bbfmm_plan_execute(bbfmm_plan *plan, const float *sigma,
                                 float *phi, void *stream);
 /* Bytes of device workspace the plan holds. */
 bbfmm_status bbfmm_plan_workspace_bytes(const bbfmm_plan *plan, int64_t *bytes);
+/* The launch shapes the plan runs with, every heuristic choice made
+ * explicit (out, host).  p2p_max_split and m2l_min_waves echo what was
+ * asked (0 = default). */
+bbfmm_status bbfmm_plan_get_options(const bbfmm_plan *plan, bbfmm_plan_options *out);
 
 /* Stages of one matvec, in execution order (Section 2.3).  Each stage is
  * one kernel launch except M2M and DOWN, which launch once per level. */

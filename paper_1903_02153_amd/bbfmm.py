@@ -77,7 +77,7 @@ class PlanOptions(ctypes.Structure):
                 ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32),
                 ("m2l_schedule", ctypes.c_int32), ("m2l_block", ctypes.c_int32),
                 ("m2l_rtile", ctypes.c_int32), ("m2l_xcd", ctypes.c_int32),
-                ("leaf_fused", ctypes.c_int32)]
+                ("leaf_fused", ctypes.c_int32), ("p2p_pack", ctypes.c_int32)]
 
 
 class RuntimeCounters(ctypes.Structure):
@@ -171,6 +171,7 @@ SIGNATURES = {
     "bbfmm_get_runtime_counters": (_I32, [ctypes.POINTER(RuntimeCounters)]),
     "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
     "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
+    "bbfmm_plan_get_options": (_I32, [_VP, ctypes.POINTER(PlanOptions)]),
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
     "bbfmm_plan_set_graph": (_I32, [_VP, _I32]),
     "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
@@ -313,7 +314,8 @@ class Plan:
 
     def __init__(self, tree: Tree, ops: Ops, r: int, allocator=None, stream=None, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
-        m2l_occupancy, m2l_layout, m2l_schedule, m2l_block, m2l_rtile, m2l_xcd, leaf_fused (0 = heuristic).  allocator: a TorchAllocator
+        m2l_occupancy, m2l_layout, m2l_schedule, m2l_block, m2l_rtile, m2l_xcd, leaf_fused,
+        p2p_pack (0 = heuristic).  allocator: a TorchAllocator
         (None = the operators'); stream: where the set-up is enqueued."""
         h = _VP()
         opt = PlanOptions()
@@ -328,6 +330,12 @@ class Plan:
         self.tree, self.ops, self.r = tree, ops, int(r)
         info = tree.info()
         self.n_in, self.n_out = info.n_sources, info.n_targets
+
+    def resolved_options(self) -> dict:
+        """The launch shapes this plan runs with (heuristic choices explicit)."""
+        o = PlanOptions()
+        _check(lib().bbfmm_plan_get_options(self._h, ctypes.byref(o)))
+        return {name: getattr(o, name) for name, _ in PlanOptions._fields_}
 
     def workspace_bytes(self) -> int:
         b = _I64(0)
@@ -386,7 +394,8 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
             "p2p_waves": best.p2p_waves, "m2l_occupancy": best.m2l_occupancy,
             "m2l_layout": best.m2l_layout, "m2l_schedule": best.m2l_schedule,
             "m2l_block": best.m2l_block, "m2l_rtile": best.m2l_rtile,
-            "m2l_xcd": best.m2l_xcd, "leaf_fused": best.leaf_fused}, ms.value
+            "m2l_xcd": best.m2l_xcd, "leaf_fused": best.leaf_fused,
+            "p2p_pack": best.p2p_pack}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,

@@ -148,6 +148,7 @@ using namespace bbfmm;
 
 struct bbfmm_plan {
     Plan *impl = nullptr;
+    bbfmm_plan_options asked{};        // the options the plan was created with
     ~bbfmm_plan() { plan_destroy(impl); }
 };
 
@@ -379,6 +380,7 @@ bbfmm_status bbfmm_plan_create_ex(const bbfmm_tree *t, const bbfmm_ops *o, int64
         MemScope scope(allocator ? allocator : (o ? &o->hook : nullptr), s);
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());
         p->impl = plan_create_impl(t, o, r, opt, s);
+        if (opt) p->asked = *opt;
         *out = p.release();
     });
 }
@@ -392,6 +394,14 @@ bbfmm_status bbfmm_plan_execute(bbfmm_plan *p, const float *sigma, float *phi, v
     return guarded([&] {
         BB_REQUIRE(p != nullptr, "plan is NULL");
         plan_execute_impl(p->impl, sigma, phi, static_cast<hipStream_t>(stream));
+    });
+}
+
+bbfmm_status bbfmm_plan_get_options(const bbfmm_plan *p, bbfmm_plan_options *out) {
+    return guarded([&] {
+        BB_REQUIRE(p != nullptr && out != nullptr, "plan / out is NULL");
+        *out = p->asked;
+        plan_resolved_options(p->impl, out);
     });
 }
 
@@ -502,6 +512,13 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
             c.overlap = ov;
             consider(c);
         }
+        if (r == 1 && cur.p2p_mfma != 2)
+            for (int pk = 1; pk <= 2; ++pk) {
+                bbfmm_plan_options c = cur;
+                c.p2p_mfma = 1;
+                c.p2p_pack = pk;
+                consider(c);
+            }
         if (cur.overlap == 2 && cur.p2p_mfma != 2)
             for (int nw : {512, 1024, 2048, 4096}) {
                 bbfmm_plan_options c = cur;

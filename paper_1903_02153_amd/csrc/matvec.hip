@@ -1922,6 +1922,166 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf,
     }
 }
 
+// ----------------------------------------- packed per-lane P2P ----
+// One right-hand side.  A work item (leaf a, first target t0, S, tpl, G)
+// holds G groups of tpl consecutive targets; lane l serves group l / S as
+// sub-lane l mod S, so that any leaf size fills the wave: S need not be a
+// power of two and each lane evaluates tpl targets against every record it
+// reads (the record is loaded once from LDS for all of them).  Sub-lane s
+// takes records s, s + S, ... of each LDS pass, stored contiguously for it;
+// a pass holds a multiple of the loop step U S (U = 8 records per step for
+// one target per lane, 4 otherwise; zero records pad it; they have sigma =
+// 0 and a finite kernel value).  The S partial sums of a target are added in sub-lane order
+// through LDS, so results are reproducible.  No L2P: the plan uses it on
+// the overlapped schedule, where the far field is added after the join.
+constexpr int kPackCap = 512;                 // records per LDS pass, at most
+
+template <int KID, int TPL>
+__device__ inline void p2p_pack_item(const float *xs, const float *ys, const float *zs,
+                                     const int32_t *sb_leaf, const int32_t *pe, const int32_t *te,
+                                     const int32_t *nbr_off, const int32_t *nbr_idx,
+                                     const int32_t *perm, const float *sig_s, int ld, float cs,
+                                     int a, int t0, int S, int G, float4 *sp, int32_t *nb_end,
+                                     int32_t *nb_src, float *red, float *phi) {
+    constexpr int KS = kPackCap / 64;
+    const int lane = threadIdx.x;
+    const int g = lane / S, sub = lane - g * S;
+    const int tend = te[a];
+    float x[TPL], y[TPL], z[TPL], acc[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int i = t0 + g * TPL + k;
+        const bool ok = g < G && i < tend;
+        x[k] = ok ? xs[i] * cs : 0.f;
+        y[k] = ok ? ys[i] * cs : 0.f;
+        z[k] = ok ? zs[i] * cs : 0.f;
+        acc[k] = 0.f;
+    }
+    float acc1 = 0.f;                          // second chain of the single-target form
+    constexpr int U = TPL == 1 ? 8 : 4;        // records per sub-lane per loop step
+    const int step = U * S;
+    const int pass = kPackCap / step * step;   // records per pass: whole loop steps
+    const int rcp = (65536 + S - 1) / S;       // e / S = (e rcp) >> 16 for e < 600, S <= 16
+    const int q0 = nbr_off[a], q1 = nbr_off[a + 1];
+    for (int qc = q0; qc < q1; qc += 64) {
+        int sb = 0, cnt = 0;
+        if (qc + lane < q1) {
+            const int b = nbr_idx[qc + lane];
+            sb = sb_leaf[b];
+            cnt = pe[b] - sb;
+        }
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int tv = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += tv;
+        }
+        const int total = __shfl(inc, 63, 64);
+        __syncthreads();                       // the previous chunk's table is consumed
+        nb_end[lane] = inc;
+        nb_src[lane] = sb - (inc - cnt);       // record e of this neighbour is point nb_src + e
+        for (int base = 0; base < total; base += pass) {
+            const int n = min(pass, total - base);
+            __syncthreads();                   // table visible, previous pass consumed
+            // record e of the pass goes to row e mod S, column e / S of an
+            // S x (M + 1) table (M = npad / S): each sub-lane then reads its
+            // records at consecutive addresses, and the odd row pitch keeps
+            // the S rows' reads on different banks.  Staged in two halves
+            // (fewer registers live beside the targets' accumulators).
+            const int npad = (n + step - 1) / step * step;   // <= pass <= kPackCap
+            const int M = npad / S;
+            constexpr int KH = KS / 2;
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                int src[KH];
+#pragma unroll
+                for (int k = 0; k < KH; ++k) {
+                    const int e = base + lane + 64 * (h * KH + k);
+                    int j = 0;
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (nb_end[j + st - 1] <= e) j += st;
+                    src[k] = e < base + n ? nb_src[min(j, 63)] + e : -1;
+                }
+                float4 rec[KH];
+#pragma unroll
+                for (int k = 0; k < KH; ++k) {
+                    const int q = max(src[k], 0);
+                    rec[k] = make_float4(xs[q], ys[q], zs[q], sig_s[int64_t(q) * ld]);
+                }
+#pragma unroll
+                for (int k = 0; k < KH; ++k) {
+                    const int e = lane + 64 * (h * KH + k);
+                    if (e < npad) {
+                        const int col = (e * rcp) >> 16, row = e - col * S;
+                        const float w = src[k] >= 0 ? 1.f : 0.f, wc = w * cs;
+                        sp[row * (M + 1) + col] =
+                            make_float4(rec[k].x * wc, rec[k].y * wc, rec[k].z * wc, rec[k].w * w);
+                    }
+                }
+            }
+            __syncthreads();
+            const float4 *mine = sp + sub * (M + 1);
+            for (int u = 0; u < M; u += U) {
+#pragma unroll
+                for (int v = 0; v < U; ++v) {
+                    const float4 q = mine[u + v];
+#pragma unroll
+                    for (int k = 0; k < TPL; ++k) {
+                        const float kv = kernel_eval<KID>(x[k] - q.x, y[k] - q.y, z[k] - q.z);
+                        if (TPL == 1 && (v & 1)) acc1 += kv * q.w;
+                        else acc[k] += kv * q.w;
+                    }
+                }
+            }
+        }
+    }
+    acc[0] += acc1;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) red[k * 64 + lane] = acc[k];
+    __syncthreads();
+    if (g < G && sub == 0) {
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+            const int i = t0 + g * TPL + k;
+            if (i < tend) {
+                float sum = 0.f;
+                for (int j = 0; j < S; ++j) sum += red[k * 64 + lane + j];
+                phi[perm[i]] = sum;
+            }
+        }
+    }
+    __syncthreads();                           // LDS of this item is consumed
+}
+
+template <int KID>
+__global__ void __launch_bounds__(64)
+k_p2p_pack(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf, const int32_t *pe,
+           const int32_t *te, const int32_t *nbr_off, const int32_t *nbr_idx, const int32_t *perm,
+           const int32_t *work, int nwork, const float *sig_s, int ld, float cs, float *phi) {
+    __shared__ float4 sp[kPackCap + 16];        // S rows of pitch npad / S + 1
+    __shared__ int32_t nb_end[64], nb_src[64];
+    __shared__ float red[4 * 64];
+    for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const int a = work[3 * item], t0 = work[3 * item + 1], code = work[3 * item + 2];
+        const int S = code & 31, tpl = (code >> 5) & 7, G = code >> 8;
+        switch (tpl) {
+        case 1:
+            p2p_pack_item<KID, 1>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
+                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+            break;
+        case 2:
+            p2p_pack_item<KID, 2>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
+                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+            break;
+        default:
+            p2p_pack_item<KID, 4>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
+                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+            break;
+        }
+    }
+}
+
 // -------------------------------------------- L2P + P2P on MFMA ----
 // For a block of right-hand sides the near field is a product,
 // phi[i][c] += sum_j K(x_i, y_j) sigma[j][c].  One wave takes up to 64
@@ -2419,6 +2579,7 @@ struct Plan {
     bool m2l_block = false;             // 16-bit M2L by parent blocks (k_m2l_blk), no slot split
     bool m2l_xsplit = false;            // tile M2L: slot splits pinned to XCDs
     bool leaf_fused = false;            // P2M + compression + M2M of the leaf level fused
+    bool p2p_pack = false;              // per-lane near field with packed targets (k_p2p_pack)
     int m2l_cb = 4;                     // its 16-column blocks per workgroup (r-tile / 16)
     hipStream_t up = nullptr;
     hipEvent_t lev_ev[kMaxLevels] = {};
@@ -2488,6 +2649,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                "m2l_rtile must be 0, 16, 32 or 64");
     BB_REQUIRE(op.m2l_xcd >= 0 && op.m2l_xcd <= 2, "m2l_xcd must be 0, 1 or 2");
     BB_REQUIRE(op.leaf_fused >= 0 && op.leaf_fused <= 2, "leaf_fused must be 0, 1 or 2");
+    BB_REQUIRE(op.p2p_pack >= 0 && op.p2p_pack <= 2, "p2p_pack must be 0, 1 or 2");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -2608,6 +2770,11 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         BB_LAUNCH_CHECK();
         ws += p->tiles.bytes() + p->masks.bytes();
     }
+    // overlapped near field: by default with the per-lane near field (whose
+    // VALU work complements the MFMA-bound far field); needs a far field
+    p->overlap = !transient && L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
+    // packed per-lane near field: one right-hand side, no fused L2P
+    p->p2p_pack = !p->p2p_mfma && r == 1 && (p->overlap || t->adaptive) && op.p2p_pack != 1;
     if (p->p2p_mfma) {
         // MFMA near field: one wave per (leaf, up to 64 consecutive
         // targets), grouped by the number of 16-row blocks they need
@@ -2625,6 +2792,48 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         }
         p->mfma_off[4] = int(w.size() / 2);
         p->nwork = int(w.size() / 2);
+        p->work.alloc(w.size());
+        BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              setup));
+    } else if (p->p2p_pack) {
+        // packed work items (leaf, first target, S | tpl << 5 | G << 8): G
+        // groups of tpl consecutive targets, S sub-lanes each, G S <= 64;
+        // per leaf the (tpl, S) that keeps most lanes busy (largest
+        // count S / (64 tpl)); on ties fewer targets per lane, then fewer
+        // sub-lanes (measured the faster order).  Leaves of
+        // more than 64 targets are cut into ceil(count / 64) near-equal
+        // pieces, one wave each, so that dense leaves keep as many waves in
+        // flight as one target per lane would.
+        const LevelData &leaf = t->leaves();
+        const std::vector<int32_t> &hb = t->leaf_pb_h, &he = t->leaf_te_h;
+        const int cap = op.p2p_max_split > 0 ? std::min(op.p2p_max_split, 16) : 16;
+        std::vector<int32_t> &w = p->h_work;
+        for (int a = 0; a < leaf.C; ++a) {
+            const int total = he[a] - hb[a];
+            const int pieces = (total + 63) / 64;
+            for (int q = 0, s0 = hb[a]; q < pieces; ++q) {
+                const int cnt = total / pieces + (q < total % pieces ? 1 : 0);
+                int best_t = 4, best_s = 1;
+                double best = -1.0;
+                for (int tpl : {1, 2, 4})
+                    for (int S = 1; S <= cap; ++S) {
+                        const int G = (cnt + tpl - 1) / tpl;
+                        if (G * S > 64) break;
+                        const double eff = double(cnt) * S / (64.0 * tpl);
+                        if (eff > best + 1e-12) {
+                            best = eff;
+                            best_t = tpl;
+                            best_s = S;
+                        }
+                    }
+                const int G = (cnt + best_t - 1) / best_t;
+                w.push_back(a);
+                w.push_back(s0);
+                w.push_back(best_s | (best_t << 5) | (G << 8));
+                s0 += cnt;
+            }
+        }
+        p->nwork = int(w.size() / 3);
         p->work.alloc(w.size());
         BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                               setup));
@@ -2652,9 +2861,6 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                               setup));
     }
-    // overlapped near field: by default with the per-lane near field (whose
-    // VALU work complements the MFMA-bound far field); needs a far field
-    p->overlap = !transient && L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
     p->p2p_waves = op.p2p_waves;
     p->m2l_occupancy = op.m2l_occupancy;
     p->m2l_layout = op.m2l_layout == 2 ? 2 : 1;
@@ -2716,6 +2922,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_rtile = 16 * p->m2l_cb;
     out->m2l_xcd = p->m2l_xsplit ? 2 : 1;
     out->leaf_fused = p->leaf_fused ? 2 : 1;
+    out->p2p_pack = p->p2p_pack ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -2791,6 +2998,15 @@ void launch_p2p(const Plan &p, const float *FL, const Geo &geo, float *phi, hipS
         return;
     }
     const int nwg = p.p2p_waves > 0 ? std::min(p.p2p_waves, p.nwork) : p.nwork;
+    if (p.p2p_pack) {
+        BB_INTERNAL(FL == nullptr && p.r == 1, "the packed near field takes one column and no L2P");
+        if (nwg == 0) return;
+        k_p2p_pack<KID><<<nwg, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p,
+                                           t.tgt_end(), t.nbr_off.p, t.nbr_idx.p, t.perm.p,
+                                           p.work.p, p.nwork, p.sig_s.p, p.ld_s, cs, phi);
+        BB_LAUNCH_CHECK();
+        return;
+    }
     dim3 g(unsigned(nwg), unsigned(ceil_div(p.r, p.rc_p2p)));
 #define BB_P2P(RCV)                                                                          \
     k_p2p<KID, RCV><<<g, 64, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, t.src_begin(), leaf.pe.p,        \

@@ -124,6 +124,7 @@ def test_adaptive_tree_bit_exact(case):
 
 @pytest.mark.parametrize("kid,prm,n,r,eps,opts", [
     (0, 1.0, 5, 1, 1e-7, {}),
+    (0, 1.0, 5, 1, 1e-7, {"p2p_pack": 1}),
     (0, 1.0, 4, 2, 1e-6, {"overlap": 2}),
     (1, 0.1, 4, 3, 1e-6, {"p2p_mfma": 2}),
     (2, 0.2, 5, 1, 1e-6, {"overlap": 1, "p2p_mfma": 1}),

@@ -251,6 +251,43 @@ def test_near_field_paths_agree(r):
     assert ofmm.rel_l2_cols(outs[0], outs[1]).max() < TOL
 
 
+@pytest.mark.parametrize("nn,kind,kid,prm,n,depth,cap", [
+    (20000, "uniform", 0, 1.0, 5, 4, 16),      # ~40 points per leaf: 2 or 4 targets per lane
+    (30000, "uniform", 1, 0.2, 4, 5, 16),      # ~15 per leaf: one target, up to 4 sub-lanes
+    (20000, "clustered", 0, 1.0, 4, 3, 16),    # leaves of hundreds: whole waves of 256 targets
+    (12000, "slab", 2, 0.05, 5, 4, 4),         # sub-lanes capped at 4
+    (15000, "clustered", 3, 1.0, 4, 4, 1),     # one sub-lane per target
+])
+def test_packed_near_field(nn, kind, kid, prm, n, depth, cap):
+    """The per-lane near field with packed targets (1, 2 or 4 targets per
+    lane, any sub-lane count) against the oracle and the power-of-two
+    per-lane form, on the overlapped schedule; repeated products are
+    bit-identical (fixed reduction order)."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(nn, 300 + depth, r=1, kind=kind)
+    gt, go, ot, oo = _both(pts, sig, kid, prm, n, 1e-5, fixed_depth=depth)
+    ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
+    ts = torch.from_numpy(sig).cuda()
+    outs = {}
+    for pack in (1, 2):
+        plan = bbfmm.Plan(gt, go, 1, p2p_mfma=1, overlap=2, p2p_pack=pack, p2p_max_split=cap)
+        assert plan.resolved_options()["p2p_pack"] == pack
+        phi = torch.empty_like(ts)
+        plan.execute(ts, phi)
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy().astype(np.float64)
+        assert_parity(got, ref, TOL, f"{kind} kernel {kid} depth {depth} p2p_pack {pack}")
+        outs[pack] = got
+        if pack == 2:
+            again = torch.empty_like(ts)
+            plan.execute(ts, again)
+            torch.cuda.synchronize()
+            assert torch.equal(phi, again)
+        plan.close()
+    assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
+
+
 @pytest.mark.parametrize("r", [1, 6])
 def test_autotune_options_are_valid_and_exact(r):
     """The autotuner returns explicit, valid options whose plan meets the
@@ -363,7 +400,8 @@ def test_graph_replay_matches_eager():
     assert torch.equal(out2, ref)
 
 
-@pytest.mark.parametrize("r,opts", [(1, dict(p2p_mfma=1)), (3, dict(p2p_mfma=1, overlap=1)),
+@pytest.mark.parametrize("r,opts", [(1, dict(p2p_mfma=1)), (1, dict(p2p_mfma=1, p2p_pack=1)),
+                                    (3, dict(p2p_mfma=1, overlap=1)),
                                     (5, dict(p2p_mfma=2)), (20, dict(p2p_mfma=2)),
                                     (20, dict(p2p_mfma=2, leaf_fused=1)),
                                     (5, dict(p2p_mfma=1, leaf_fused=2)),
