@@ -406,6 +406,9 @@ typedef struct {
                             /* leaf's targets fill the 64 lanes; 1 = power-of-two */
                             /* sub-lanes, one target per lane; 0 = 2 where it     */
                             /* applies                                           */
+    int32_t m2l_mfma;       /* 16-bit parent-block M2L: 1 = 16x16x32 MFMAs, 2 =  */
+                            /* 32x32x16 (with an r-tile of 32 or 64; 32 rank rows */
+                            /* per workgroup); 0 = 1                             */
 } bbfmm_plan_options;
 
 /* plan_create with explicit launch shapes (NULL options = defaults), a

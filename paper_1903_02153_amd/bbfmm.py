@@ -77,7 +77,8 @@ class PlanOptions(ctypes.Structure):
                 ("m2l_occupancy", ctypes.c_int32), ("m2l_layout", ctypes.c_int32),
                 ("m2l_schedule", ctypes.c_int32), ("m2l_block", ctypes.c_int32),
                 ("m2l_rtile", ctypes.c_int32), ("m2l_xcd", ctypes.c_int32),
-                ("leaf_fused", ctypes.c_int32), ("p2p_pack", ctypes.c_int32)]
+                ("leaf_fused", ctypes.c_int32), ("p2p_pack", ctypes.c_int32),
+                ("m2l_mfma", ctypes.c_int32)]
 
 
 class RuntimeCounters(ctypes.Structure):
@@ -315,7 +316,7 @@ class Plan:
     def __init__(self, tree: Tree, ops: Ops, r: int, allocator=None, stream=None, **options):
         """options: m2l_split, m2l_min_waves, p2p_max_split, p2p_mfma, overlap, p2p_waves,
         m2l_occupancy, m2l_layout, m2l_schedule, m2l_block, m2l_rtile, m2l_xcd, leaf_fused,
-        p2p_pack (0 = heuristic).  allocator: a TorchAllocator
+        p2p_pack, m2l_mfma (0 = heuristic).  allocator: a TorchAllocator
         (None = the operators'); stream: where the set-up is enqueued."""
         h = _VP()
         opt = PlanOptions()
@@ -395,7 +396,7 @@ def autotune(tree: Tree, ops: Ops, sigma, phi=None, reps: int = 5, stream=None):
             "m2l_layout": best.m2l_layout, "m2l_schedule": best.m2l_schedule,
             "m2l_block": best.m2l_block, "m2l_rtile": best.m2l_rtile,
             "m2l_xcd": best.m2l_xcd, "leaf_fused": best.leaf_fused,
-            "p2p_pack": best.p2p_pack}, ms.value
+            "p2p_pack": best.p2p_pack, "m2l_mfma": best.m2l_mfma}, ms.value
 
 
 def build_tree(points, kernel_id: int = K_INV_R, kernel_param: float = 1.0,

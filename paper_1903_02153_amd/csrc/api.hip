@@ -570,6 +570,14 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.m2l_rtile = rt;
                 consider(c);
             }
+        if ((o->precision == BBFMM_M2L_BF16X3 || o->precision == BBFMM_M2L_FP16_SCALED) &&
+            cur.m2l_block != 1 && r >= 32)
+            for (int mf = 1; mf <= 2; ++mf) {
+                bbfmm_plan_options c = cur;
+                c.m2l_block = 2;
+                c.m2l_mfma = mf;
+                consider(c);
+            }
         // make every choice explicit: what the heuristic picked for the zeros
         MemScope scope(&o->hook, s);
         std::unique_ptr<bbfmm_plan> p(new bbfmm_plan());

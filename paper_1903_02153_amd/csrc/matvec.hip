@@ -1253,6 +1253,7 @@ struct M2LArgsLP {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 template <int PREC>
 __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
@@ -1474,7 +1475,10 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_lp(M2LArgsLP g) {
 // 32-rank chunk and serve all children that see them (about seven on a full
 // grid), while the operator rows C_t come from L2 (316 operators per
 // level).  Wave w owns children 2w and 2w+1: RB 16-row blocks of the rank
-// times CB 16-column blocks of right-hand sides for each.  The sum over the
+// times CB 16-column blocks of right-hand sides for each, as 16x16x32
+// MFMAs; with W32 (RB = 2, CB = 2 or 4) the same 32 rows x 16 CB columns
+// are 32x32x16 MFMAs instead (half as many instructions, each operand
+// fragment serving twice the outputs).  The sum over the
 // halo is complete inside the workgroup (one partial result).  The loads of
 // the next step -- the staged source chunk and the wave's operator rows --
 // are issued before the MFMAs of the current one.
@@ -1501,9 +1505,11 @@ __device__ inline int t_compact(int tx, int ty, int tz) {
     return code - inner;
 }
 
-template <int PREC, int RB, int CB>
+template <int PREC, int RB, int CB, bool W32>
 __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
+    static_assert(!W32 || (RB == 2 && (CB == 2 || CB == 4)), "32x32 blocks: 32 rows, 32 or 64 columns");
     constexpr bool X3 = PREC == BBFMM_M2L_BF16X3;
+    constexpr int C32 = W32 ? CB / 2 : 1;       // 32-column blocks (W32)
     constexpr int COLS = 16 * CB;
     constexpr int ldb = 32 + 8;                 // 80-byte column rows (32 ranks + pad)
     constexpr int PPC = X3 ? 8 : 4;             // 16-byte pieces per column (hi + lo for X3)
@@ -1605,15 +1611,24 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
     };
 
     v4f acc[2][RB][CB];
+    v16f acc32[2][C32];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < 2; ++u) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[u][rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c2 = 0; c2 < C32; ++c2)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc32[u][c2][e] = 0.f;
+    }
     const int nsteps = nh * nkc;
-    // operator rows of this wave's two children for one step (ks = 32-deep
-    // block of the 64-rank chunk), prefetched one step ahead like the sources
+    // operator rows of this wave's two children for one step, prefetched one
+    // step ahead like the sources: 16x16x32 -- RB 16-row blocks, lane holds
+    // row (lane & 15), ranks 8 (lane >> 4) .. + 7 of the 32-rank chunk;
+    // W32 -- two 16-deep halves ks (in the rb slot), lane holds row
+    // (lane & 31), ranks 16 ks + 8 (lane >> 5) .. + 7
     constexpr int NP = X3 ? 2 : 1;
     uint4 acur[2][RB][NP], anxt[2][RB][NP];
     float ccur[2] = {0.f, 0.f}, cnxt[2] = {0.f, 0.f};
@@ -1626,10 +1641,11 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
             const bool valid = (hm >> i) & 1u;                  // wave-uniform
             const int ti = valid ? int(htix[h][i]) : 0;
             if constexpr (!X3) cv[u] = valid ? g.Cinv[ti] : 0.f;
-            const int64_t cbase = int64_t(ti) * kp * kp + kc * 32 + 8 * (lane >> 4);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const int row = row0 + rb * 16 + (lane & 15);
+                const int64_t cbase = int64_t(ti) * kp * kp + kc * 32 +
+                                      (W32 ? 16 * rb + 8 * (lane >> 5) : 8 * (lane >> 4));
+                const int row = W32 ? row0 + (lane & 31) : row0 + rb * 16 + (lane & 15);
                 const bool ok = valid && row < kp;
                 const int64_t o = ok ? cbase + int64_t(row) * kp : 0;
                 const uint32_t w = ok ? 0xffffffffu : 0u;
@@ -1661,6 +1677,48 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
         const int h = s / nkc;
         const unsigned hm = hmask[h];
         const uint4 *Bh = Bstore[s & 1][0];
+        if constexpr (W32) {
+            const int b32 = ((lane & 31) * ldb + 8 * (lane >> 5)) / 8;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = 2 * wave + u;
+                if (!((hm >> i) & 1u)) continue;                // wave-uniform
+                v16f part[C32];
+                if constexpr (!X3) {
+#pragma unroll
+                    for (int c2 = 0; c2 < C32; ++c2)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) part[c2][e] = 0.f;
+                }
+#pragma unroll
+                for (int c2 = 0; c2 < C32; ++c2)
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks) {
+                        const int bi = b32 + (c2 * 32 * ldb + 16 * ks) / 8;
+                        if constexpr (X3) {
+                            const v8bf bh = __builtin_bit_cast(v8bf, Bh[bi]);
+                            const v8bf bl = __builtin_bit_cast(v8bf, Bstore[s & 1][1][bi]);
+                            const v8bf a_h = __builtin_bit_cast(v8bf, acur[u][ks][0]);
+                            const v8bf a_l = __builtin_bit_cast(v8bf, acur[u][ks][NP - 1]);
+                            acc32[u][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, bh, acc32[u][c2], 0, 0, 0);
+                            acc32[u][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, bl, acc32[u][c2], 0, 0, 0);
+                            acc32[u][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, bh, acc32[u][c2], 0, 0, 0);
+                        } else {
+                            part[c2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(v8h, acur[u][ks][0]), __builtin_bit_cast(v8h, Bh[bi]),
+                                part[c2], 0, 0, 0);
+                        }
+                    }
+                if constexpr (!X3) {
+#pragma unroll
+                    for (int c2 = 0; c2 < C32; ++c2) {
+                        const float f = Bsc[s & 1][c2 * 32 + (lane & 31)] * ccur[u];
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) acc32[u][c2][e] += part[c2][e] * f;
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int i = 2 * wave + u;
@@ -1715,6 +1773,27 @@ __global__ void __launch_bounds__(kThreads, 2) k_m2l_blk(M2LBlockArgs g) {
                     for (int q = 0; q < NP; ++q) acur[u][rb][q] = anxt[u][rb][q];
             }
         }
+    }
+    if constexpr (W32) {
+        // 32x32 accumulator: element 4 q + e is row 8 q + 4 (lane >> 5) + e,
+        // column lane & 31 of the block
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = 2 * wave + u;
+            if (i >= nchild) continue;
+#pragma unroll
+            for (int c2 = 0; c2 < C32; ++c2) {
+                const int c = rhs0 + c2 * 32 + (lane & 31);
+                if (c >= r) continue;
+                float *dst = g.Fh + (int64_t(c0 + i) * r + c) * kp + row0 + 4 * (lane >> 5);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<float4 *>(dst + 8 * q) =
+                        make_float4(acc32[u][c2][4 * q], acc32[u][c2][4 * q + 1], acc32[u][c2][4 * q + 2],
+                                    acc32[u][c2][4 * q + 3]);
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -2580,6 +2659,7 @@ struct Plan {
     bool m2l_xsplit = false;            // tile M2L: slot splits pinned to XCDs
     bool leaf_fused = false;            // P2M + compression + M2M of the leaf level fused
     bool p2p_pack = false;              // per-lane near field with packed targets (k_p2p_pack)
+    bool m2l_w32 = false;               // block M2L on 32x32x16 MFMAs (r-tile >= 32)
     int m2l_cb = 4;                     // its 16-column blocks per workgroup (r-tile / 16)
     hipStream_t up = nullptr;
     hipEvent_t lev_ev[kMaxLevels] = {};
@@ -2650,6 +2730,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     BB_REQUIRE(op.m2l_xcd >= 0 && op.m2l_xcd <= 2, "m2l_xcd must be 0, 1 or 2");
     BB_REQUIRE(op.leaf_fused >= 0 && op.leaf_fused <= 2, "leaf_fused must be 0, 1 or 2");
     BB_REQUIRE(op.p2p_pack >= 0 && op.p2p_pack <= 2, "p2p_pack must be 0, 1 or 2");
+    BB_REQUIRE(op.m2l_mfma >= 0 && op.m2l_mfma <= 2, "m2l_mfma must be 0, 1 or 2");
     BB_REQUIRE(t != nullptr && o != nullptr, "tree or ops is NULL");
     BB_REQUIRE(o->tree == t, "operators were built for another tree");
     BB_REQUIRE(r >= 1 && r <= 4096, "r must be in [1, 4096]");
@@ -2738,6 +2819,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                    (op.m2l_block == 0 ? r >= 16 : op.m2l_block == 2);
     // r-tile of the parent-block kernel: 16, 32 or 64 columns per workgroup
     p->m2l_cb = op.m2l_rtile > 0 ? op.m2l_rtile / 16 : (r >= 48 ? 4 : (r > 16 ? 2 : 1));
+    // MFMA shape of the parent-block kernel: 32x32x16 needs an r-tile of 32 or 64
+    p->m2l_w32 = p->m2l_block && p->m2l_cb >= 2 && op.m2l_mfma == 2;
     // split the slots until the launch has about m2l_min_waves workgroups per CU
     if (p->m2l_block) {
         p->nsplit = 1;                  // each block sums its whole halo
@@ -2923,6 +3006,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_xcd = p->m2l_xsplit ? 2 : 1;
     out->leaf_fused = p->leaf_fused ? 2 : 1;
     out->p2p_pack = p->p2p_pack ? 2 : 1;
+    out->m2l_mfma = p->m2l_w32 ? 2 : 1;
     if (out->p2p_max_split == 0) out->p2p_max_split = 16;   // the per-lane kernel's default cap
 }
 void plan_destroy(Plan *p) { delete p; }
@@ -3380,17 +3464,20 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
                                set.Cinv.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p, t.lv[lvl - 1].cb.p,
                                t.lv[lvl - 1].ce.p, t.tables.p + 3 * kNumT + 8 * kSlots, kp, r};
                 const int CBv = p.m2l_cb;
-                const int RBv = (kp <= 32 || CBv == 4 ||
+                const bool w32 = p.m2l_w32 && CBv >= 2;   // 32x32x16 MFMAs: 32 rows
+                const int RBv = (w32 || kp <= 32 || CBv == 4 ||
                                  (CBv == 2 && o.precision == BBFMM_M2L_BF16X3)) ? 2 : 4;
                 dim3 gr(unsigned(t.lv[lvl - 1].C), unsigned(ceil_div(kp, 16 * RBv)),
                         unsigned(ceil_div(r, 16 * CBv)));
-#define BB_BLK(PR, RBc, CBc) k_m2l_blk<PR, RBc, CBc><<<gr, kThreads, p.m2l_pad_lds, st>>>(g)
+#define BB_BLK(PR, RBc, CBc, W) k_m2l_blk<PR, RBc, CBc, W><<<gr, kThreads, p.m2l_pad_lds, st>>>(g)
 #define BB_BLK_P(PR)                                                                          \
-                if (RBv == 2 && CBv == 1) BB_BLK(PR, 2, 1);                                   \
-                else if (RBv == 2 && CBv == 2) BB_BLK(PR, 2, 2);                              \
-                else if (RBv == 2) BB_BLK(PR, 2, 4);                                          \
-                else if (CBv == 1) BB_BLK(PR, 4, 1);                                          \
-                else BB_BLK(PR, 4, 2);
+                if (w32 && CBv == 2) BB_BLK(PR, 2, 2, true);                                  \
+                else if (w32) BB_BLK(PR, 2, 4, true);                                         \
+                else if (RBv == 2 && CBv == 1) BB_BLK(PR, 2, 1, false);                       \
+                else if (RBv == 2 && CBv == 2) BB_BLK(PR, 2, 2, false);                       \
+                else if (RBv == 2) BB_BLK(PR, 2, 4, false);                                   \
+                else if (CBv == 1) BB_BLK(PR, 4, 1, false);                                   \
+                else BB_BLK(PR, 4, 2, false);
                 if (o.precision == BBFMM_M2L_BF16X3) {
                     BB_BLK_P(BBFMM_M2L_BF16X3)
                 } else {

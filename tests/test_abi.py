@@ -89,7 +89,8 @@ def test_allocator_hook_checked_and_counters_without_gpu():
                                          ("p2p_waves", -5), ("m2l_occupancy", 5),
                                          ("m2l_layout", 3), ("m2l_schedule", 3),
                                          ("m2l_block", -1), ("m2l_rtile", 48),
-                                         ("m2l_xcd", 3), ("leaf_fused", 3), ("p2p_pack", -1)])
+                                         ("m2l_xcd", 3), ("leaf_fused", 3), ("p2p_pack", -1),
+                                         ("m2l_mfma", 3)])
 def test_plan_options_validated_without_gpu(field, value):
     """Every launch-shape option is range-checked before any handle or
     device memory is touched; the message names the option."""

@@ -518,6 +518,38 @@ def test_block_m2l_rtiles_agree(prec):
     assert_parity(outs[0], ref, TOL if prec == 1 else 1e-3, f"block M2L r-tiles precision {prec}")
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_block_m2l_mfma_shapes(prec):
+    """The parent-block 16-bit M2L on 32x32x16 MFMAs (r-tiles of 32 and 64
+    columns, partial last tile at r = 40) against the oracle and the
+    16x16x32 form; the two r-tiles of the 32x32 form sum each column in the
+    same order, so they agree bit for bit."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(15000, 261, r=40, kind="slab")
+    gt = gpu_tree(pts, bbfmm.K_GAUSS, 0.08, 5, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5, prec)
+    ts = torch.from_numpy(sig).cuda()
+    outs = {}
+    for mf, rt in ((1, 32), (2, 32), (2, 64)):
+        plan = bbfmm.Plan(gt, go, 40, m2l_block=2, m2l_rtile=rt, m2l_mfma=mf)
+        assert plan.resolved_options()["m2l_mfma"] == mf
+        phi = torch.empty_like(ts)
+        plan.execute(ts, phi)
+        torch.cuda.synchronize()
+        plan.close()
+        outs[(mf, rt)] = phi.cpu().numpy()
+    assert np.array_equal(outs[(2, 32)], outs[(2, 64)])
+    ot = oracle_tree(pts, fixed_depth=5)
+    oo = oops.precompute(ot, 2, 0.08, 5, 1e-5)
+    ref = ofmm.matvec(ot, oo, pts, sig, 2, 0.08)
+    tol = TOL if prec == 1 else 1e-3
+    for key, got in outs.items():
+        assert_parity(got, ref, tol, f"block M2L precision {prec} mfma/r-tile {key}")
+    d = ofmm.rel_l2_cols(outs[(2, 32)].astype(np.float64), outs[(1, 32)].astype(np.float64)).max()
+    assert d < (TOL if prec == 1 else 1e-4), d
+
+
 # P2M, compression and M2M of the leaf level fused into one kernel (the
 # leaves' full coefficients stay on chip) against the oracle, beside the
 # separate kernels, for the three M2L operand formats, ragged column counts
