@@ -519,10 +519,9 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.p2p_pack = pk;
                 consider(c);
             }
-        if (cur.overlap == 2 && cur.p2p_mfma != 2)
+        if (cur.overlap != 1 && cur.p2p_mfma != 2)
             for (int nw : {512, 1024, 2048, 4096}) {
                 bbfmm_plan_options c = cur;
-                c.overlap = 2;
                 c.p2p_mfma = 1;
                 c.p2p_waves = nw;
                 consider(c);
@@ -543,10 +542,9 @@ bbfmm_status bbfmm_plan_autotune(const bbfmm_tree *t, const bbfmm_ops *o, int64_
                 c.leaf_fused = lf;
                 consider(c);
             }
-        if (cur.overlap == 2)
+        if (cur.overlap != 1)
             for (int occ : {3, 2}) {
                 bbfmm_plan_options c = cur;
-                c.overlap = 2;
                 c.m2l_occupancy = occ;
                 consider(c);
             }

@@ -2020,12 +2020,12 @@ __device__ inline void p2p_pack_item(const float *xs, const float *ys, const flo
                                      const int32_t *sb_leaf, const int32_t *pe, const int32_t *te,
                                      const int32_t *nbr_off, const int32_t *nbr_idx,
                                      const int32_t *perm, const float *sig_s, int ld, float cs,
-                                     int a, int t0, int S, int G, float4 *sp, int32_t *nb_end,
-                                     int32_t *nb_src, float *red, float *phi) {
+                                     int a, int t0, int cnt_t, int S, int G, float4 *sp,
+                                     int32_t *nb_end, int32_t *nb_src, float *red, float *phi) {
     constexpr int KS = kPackCap / 64;
     const int lane = threadIdx.x;
     const int g = lane / S, sub = lane - g * S;
-    const int tend = te[a];
+    const int tend = min(te[a], t0 + cnt_t);   // this item's targets only (a leaf may have several)
     float x[TPL], y[TPL], z[TPL], acc[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -2143,19 +2143,19 @@ k_p2p_pack(const float *xs, const float *ys, const float *zs, const int32_t *sb_
     __shared__ float red[4 * 64];
     for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
         const int a = work[3 * item], t0 = work[3 * item + 1], code = work[3 * item + 2];
-        const int S = code & 31, tpl = (code >> 5) & 7, G = code >> 8;
+        const int S = code & 31, tpl = (code >> 5) & 7, G = (code >> 8) & 127, cnt = code >> 15;
         switch (tpl) {
         case 1:
             p2p_pack_item<KID, 1>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
-                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+                                  a, t0, cnt, S, G, sp, nb_end, nb_src, red, phi);
             break;
         case 2:
             p2p_pack_item<KID, 2>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
-                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+                                  a, t0, cnt, S, G, sp, nb_end, nb_src, red, phi);
             break;
         default:
             p2p_pack_item<KID, 4>(xs, ys, zs, sb_leaf, pe, te, nbr_off, nbr_idx, perm, sig_s, ld, cs,
-                                  a, t0, S, G, sp, nb_end, nb_src, red, phi);
+                                  a, t0, cnt, S, G, sp, nb_end, nb_src, red, phi);
             break;
         }
     }
@@ -2879,7 +2879,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         BB_HIP(hipMemcpyAsync(p->work.p, w.data(), w.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                               setup));
     } else if (p->p2p_pack) {
-        // packed work items (leaf, first target, S | tpl << 5 | G << 8): G
+        // packed work items (leaf, first target, S | tpl << 5 | G << 8 |
+        // count << 15) for `count` consecutive targets of the leaf: G
         // groups of tpl consecutive targets, S sub-lanes each, G S <= 64;
         // per leaf the (tpl, S) that keeps most lanes busy (largest
         // count S / (64 tpl)); on ties fewer targets per lane, then fewer
@@ -2912,7 +2913,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
                 const int G = (cnt + best_t - 1) / best_t;
                 w.push_back(a);
                 w.push_back(s0);
-                w.push_back(best_s | (best_t << 5) | (G << 8));
+                w.push_back(best_s | (best_t << 5) | (G << 8) | (cnt << 15));
                 s0 += cnt;
             }
         }

@@ -261,8 +261,8 @@ def test_near_field_paths_agree(r):
 def test_packed_near_field(nn, kind, kid, prm, n, depth, cap):
     """The per-lane near field with packed targets (1, 2 or 4 targets per
     lane, any sub-lane count) against the oracle and the power-of-two
-    per-lane form, on the overlapped schedule; repeated products are
-    bit-identical (fixed reduction order)."""
+    per-lane form, on the overlapped schedule; repeated products, eager
+    and as graph replays, are bit-identical."""
     import torch
     from paper_1903_02153_amd import bbfmm
     pts, sig = synth.random_cloud(nn, 300 + depth, r=1, kind=kind)
@@ -280,10 +280,15 @@ def test_packed_near_field(nn, kind, kid, prm, n, depth, cap):
         assert_parity(got, ref, TOL, f"{kind} kernel {kid} depth {depth} p2p_pack {pack}")
         outs[pack] = got
         if pack == 2:
-            again = torch.empty_like(ts)
-            plan.execute(ts, again)
-            torch.cuda.synchronize()
-            assert torch.equal(phi, again)
+            # every target is written by exactly one work item, in a fixed
+            # order: repeated products, eager and replayed, are identical
+            # (leaves of more than 64 targets are cut into several items)
+            for graph in (False, False, True, True, True):
+                plan.set_graph(graph)
+                again = torch.full_like(ts, float("nan"))
+                plan.execute(ts, again)
+                torch.cuda.synchronize()
+                assert torch.equal(phi, again), graph
         plan.close()
     assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
 
