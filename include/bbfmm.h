@@ -399,13 +399,14 @@ typedef struct {
                             /* three stages as separate kernels; 0 = 1.  Applies  */
                             /* to uniform trees of at least four levels with the */
                             /* Chebyshev/SVD M2L (else the stages stay separate) */
-    int32_t p2p_pack;       /* per-lane near field, one right-hand side, on the  */
-                            /* overlapped schedule: 2 = each wave holds 1, 2 or 4 */
-                            /* targets per lane and any number S <= 16 of        */
-                            /* sub-lanes per target, picked per leaf so that the */
-                            /* leaf's targets fill the 64 lanes; 1 = power-of-two */
-                            /* sub-lanes, one target per lane; 0 = 2 where it     */
-                            /* applies                                           */
+    int32_t p2p_pack;       /* per-lane near field, one right-hand side: 2 =     */
+                            /* each wave holds 1, 2 or 4 targets per lane and    */
+                            /* any number S <= 16 of sub-lanes per target,       */
+                            /* picked per leaf so that the leaf's targets fill   */
+                            /* the 64 lanes, and L2P runs as its own kernel;     */
+                            /* 1 = power-of-two sub-lanes, one target per lane   */
+                            /* (L2P fused on the one-stream schedule); 0 = 2     */
+                            /* where it applies                                  */
     int32_t m2l_mfma;       /* 16-bit parent-block M2L: 1 = 16x16x32 MFMAs, 2 =  */
                             /* 32x32x16 (with an r-tile of 32 or 64; 32 rank rows */
                             /* per workgroup); 0 = 1                             */

@@ -2010,9 +2010,9 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf,
 // takes records s, s + S, ... of each LDS pass, stored contiguously for it;
 // a pass holds a multiple of the loop step U S (U = 8 records per step for
 // one target per lane, 4 otherwise; zero records pad it; they have sigma =
-// 0 and a finite kernel value).  The S partial sums of a target are added in sub-lane order
-// through LDS, so results are reproducible.  No L2P: the plan uses it on
-// the overlapped schedule, where the far field is added after the join.
+// 0 and a finite kernel value).  The S partial sums of a target are added
+// in sub-lane order through LDS, so results are reproducible.  The kernel
+// writes the near field only; k_l2p adds the far field after it.
 constexpr int kPackCap = 512;                 // records per LDS pass, at most
 
 template <int KID, int TPL>
@@ -2856,8 +2856,9 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     // overlapped near field: by default with the per-lane near field (whose
     // VALU work complements the MFMA-bound far field); needs a far field
     p->overlap = !transient && L >= 2 && (op.overlap == 0 ? !p->p2p_mfma : op.overlap == 2);
-    // packed per-lane near field: one right-hand side, no fused L2P
-    p->p2p_pack = !p->p2p_mfma && r == 1 && (p->overlap || t->adaptive) && op.p2p_pack != 1;
+    // packed per-lane near field: one right-hand side; the far field is
+    // then added by its own L2P kernel on either schedule
+    p->p2p_pack = !p->p2p_mfma && r == 1 && op.p2p_pack != 1;
     if (p->p2p_mfma) {
         // MFMA near field: one wave per (leaf, up to 64 consecutive
         // targets), grouped by the number of 16-row blocks they need
@@ -2962,15 +2963,17 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
         const size_t per_wg = size_t(160 * 1024) / size_t(op.m2l_occupancy) - 512;
         p->m2l_pad_lds = per_wg > fa.sharedSizeBytes ? per_wg - fa.sharedSizeBytes : 0;
     }
+    // a separate L2P kernel (k_l2p) after the near field: on the overlapped
+    // schedule and with the packed near field (adaptive trees: k_leaf_far)
+    if (!t->adaptive && L >= 2 && (p->overlap || p->p2p_pack)) {
+        const LevelData &leaf = t->lv[L];
+        p->pleaf.alloc(t->n);
+        ws += p->pleaf.bytes();
+        k_point_leaf<<<grid(leaf.C), kThreads, 0, setup>>>(leaf.pb.p, leaf.pe.p, leaf.C,
+                                                           p->pleaf.p);
+        BB_LAUNCH_CHECK();
+    }
     if (p->overlap) {
-        if (!t->adaptive) {         // k_l2p after the join (adaptive trees: k_leaf_far)
-            const LevelData &leaf = t->lv[L];
-            p->pleaf.alloc(t->n);
-            ws += p->pleaf.bytes();
-            k_point_leaf<<<grid(leaf.C), kThreads, 0, setup>>>(leaf.pb.p, leaf.pe.p, leaf.C,
-                                                               p->pleaf.p);
-            BB_LAUNCH_CHECK();
-        }
         p->side = acquire_side_stream();
         p->fork = make_event(hipEventDisableTiming);
         p->join = make_event(hipEventDisableTiming);
@@ -3656,17 +3659,23 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             near_field(nullptr, s);
         }
         if (L >= 2) leaf_far(p, geo, phi, s);
-    } else if (p.overlap) {
-        BB_HIP(hipStreamWaitEvent(s, p.join, 0));
-        if (ev) BB_HIP(hipEventRecord(ev[kEvJoined], s));
-        const LevelData &leaf = t.lv[L];
-        switch (n) {
-#define BB_L2P(NN) case NN: k_l2p<NN><<<grid(t.n), kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, p.pleaf.p, \
-            leaf.keys.p, t.perm.p, t.n, t.n_out(), r, FL, mp, geo, o.cheb, phi); break;
-        BB_L2P(2) BB_L2P(3) BB_L2P(4) BB_L2P(5) BB_L2P(6) BB_L2P(7) BB_L2P(8)
-#undef BB_L2P
+    } else if (p.overlap || p.p2p_pack) {
+        if (p.overlap) {
+            BB_HIP(hipStreamWaitEvent(s, p.join, 0));
+            if (ev) BB_HIP(hipEventRecord(ev[kEvJoined], s));
+        } else {
+            near_field(nullptr, s);
         }
-        BB_LAUNCH_CHECK();
+        if (FL != nullptr) {
+            const LevelData &leaf = t.lv[L];
+            switch (n) {
+#define BB_L2P(NN) case NN: k_l2p<NN><<<grid(t.n), kThreads, 0, s>>>(t.xs.p, t.ys.p, t.zs.p, p.pleaf.p, \
+                leaf.keys.p, t.perm.p, t.n, t.n_out(), r, FL, mp, geo, o.cheb, phi); break;
+            BB_L2P(2) BB_L2P(3) BB_L2P(4) BB_L2P(5) BB_L2P(6) BB_L2P(7) BB_L2P(8)
+#undef BB_L2P
+            }
+            BB_LAUNCH_CHECK();
+        }
     } else {
         near_field(FL, s);
     }

@@ -291,6 +291,9 @@ def test_packed_near_field(nn, kind, kid, prm, n, depth, cap):
                 assert torch.equal(phi, again), graph
         plan.close()
     assert ofmm.rel_l2_cols(outs[1], outs[2]).max() < TOL
+    # the one-stream schedule: packed near field, then the far field's L2P
+    got = run_plan(gt, go, ts, p2p_mfma=1, overlap=1, p2p_pack=2, p2p_max_split=cap)
+    assert_parity(got.cpu().numpy(), ref, TOL, f"{kind} kernel {kid} one stream, packed")
 
 
 @pytest.mark.parametrize("r", [1, 6])
