@@ -558,6 +558,26 @@ typedef struct {
 bbfmm_status bbfmm_server_get_stats(bbfmm_server *server, bbfmm_server_stats *out);
 
 /*
+ * Dense products of the randomized eigendecomposition built on the matvec
+ * (Section 4, the geostatistics application: with l right-hand sides the
+ * range basis is N x l).  Device pointers, row-major, FP32 inputs, FP64
+ * accumulation, asynchronous on `stream`; the summation order is fixed, so
+ * results do not depend on the launch.
+ *   bbfmm_dense_atb: C (m x m, FP64) = A^T B for A, B (n x m, FP32).  Uses a
+ *     workspace of ceil(n / 4096) m^2 doubles from `allocator` (NULL =
+ *     hipMalloc), released before the call returns (stream-ordered with a
+ *     hook).
+ *   bbfmm_dense_ab: C (n x k, FP32) = A R for A (n x m, FP32) and R (m x k,
+ *     FP64).
+ * Errors: INVALID_ARG (NULL or host pointers, n < 1, m or k outside
+ * [1, 1024]), OUT_OF_MEMORY, HIP.
+ */
+bbfmm_status bbfmm_dense_atb(const float *A, const float *B, int64_t n, int32_t m, double *C,
+                             const bbfmm_allocator *allocator, void *stream);
+bbfmm_status bbfmm_dense_ab(const float *A, int64_t n, int32_t m, const double *R, int32_t k,
+                            float *C, void *stream);
+
+/*
  * Live resources of the library in this process (all out, host): device
  * buffers and bytes it holds (from hooks or hipMalloc), plans, the streams
  * and events it created and has not destroyed (side streams are kept for

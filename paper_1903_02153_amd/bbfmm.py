@@ -173,6 +173,8 @@ SIGNATURES = {
     "bbfmm_plan_execute": (_I32, [_VP, _VP, _VP, _VP]),
     "bbfmm_plan_workspace_bytes": (_I32, [_VP, ctypes.POINTER(_I64)]),
     "bbfmm_plan_get_options": (_I32, [_VP, ctypes.POINTER(PlanOptions)]),
+    "bbfmm_dense_atb": (_I32, [_VP, _VP, _I64, _I32, _VP, _VP, _VP]),
+    "bbfmm_dense_ab": (_I32, [_VP, _I64, _I32, _VP, _I32, _VP, _VP]),
     "bbfmm_plan_set_timing": (_I32, [_VP, _I32]),
     "bbfmm_plan_set_graph": (_I32, [_VP, _I32]),
     "bbfmm_plan_stage_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
@@ -229,6 +231,36 @@ def _device_f32(t, name: str, shape: Optional[Sequence[int]] = None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     return t
+
+
+def dense_atb(A, B, allocator="torch", stream=None):
+    """A^T B (m x m, float64 CUDA tensor) for A, B of shape (n, m), float32
+    on the GPU, with FP64 accumulation in a fixed order (bbfmm_dense_atb)."""
+    import torch
+    _device_f32(A, "A")
+    _device_f32(B, "B", tuple(A.shape))
+    n, m = A.shape
+    C = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    hook = torch_allocator() if allocator == "torch" else allocator
+    _check(lib().bbfmm_dense_atb(A.data_ptr(), B.data_ptr(), n, m, C.data_ptr(), _hook_arg(hook),
+                                 _stream_handle(stream)))
+    return C
+
+
+def dense_ab(A, R, stream=None):
+    """A R (n x k, float32 CUDA tensor) for A (n, m) float32 and R (m, k)
+    float64, both on the GPU, with FP64 accumulation (bbfmm_dense_ab)."""
+    import torch
+    _device_f32(A, "A")
+    if not isinstance(R, torch.Tensor) or not R.is_cuda or R.dtype != torch.float64 \
+            or not R.is_contiguous() or R.dim() != 2 or R.shape[0] != A.shape[1]:
+        raise TypeError("R must be a contiguous float64 CUDA tensor with A.shape[1] rows")
+    n, m = A.shape
+    k = R.shape[1]
+    C = torch.empty((n, k), dtype=torch.float32, device=A.device)
+    _check(lib().bbfmm_dense_ab(A.data_ptr(), n, m, R.data_ptr(), k, C.data_ptr(),
+                                _stream_handle(stream)))
+    return C
 
 
 def runtime_counters() -> dict:

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "primitives.hip", "tree_build.hip", "precompute.hip", "matvec.hip",
-           "server.hip", "static_matvec.hip", "fft_m2l.hip"]
+           "server.hip", "static_matvec.hip", "fft_m2l.hip", "dense.hip"]
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]

@@ -65,6 +65,24 @@ def test_invalid_arguments_rejected_without_gpu():
     lib.bbfmm_plan_free(None)
 
 
+def test_dense_products_reject_invalid_arguments_without_gpu():
+    """The dense products of the eigendecomposition check sizes and
+    pointers before touching the device."""
+    lib = bbfmm.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bbfmm_dense_atb(None, fake, 10, 4, fake, None, None) == 1
+    assert b"NULL" in lib.bbfmm_last_error()
+    assert lib.bbfmm_dense_atb(fake, fake, 0, 4, fake, None, None) == 1
+    assert lib.bbfmm_dense_atb(fake, fake, 10, 0, fake, None, None) == 1
+    assert lib.bbfmm_dense_atb(fake, fake, 10, 1025, fake, None, None) == 1
+    assert b"m must be" in lib.bbfmm_last_error()
+    assert lib.bbfmm_dense_atb(fake, fake, 10, 4, fake, None, None) == 1   # not device memory
+    assert b"device" in lib.bbfmm_last_error()
+    assert lib.bbfmm_dense_ab(fake, 10, 4, None, 3, fake, None) == 1
+    assert lib.bbfmm_dense_ab(fake, 10, 4, fake, 0, fake, None) == 1
+    assert lib.bbfmm_dense_ab(fake, -1, 4, fake, 3, fake, None) == 1
+
+
 def test_allocator_hook_checked_and_counters_without_gpu():
     """An allocator hook needs both functions; the runtime counters are
     readable without a GPU and start with nothing live."""

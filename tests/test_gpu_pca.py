@@ -24,6 +24,31 @@ def _exact_randomized(pts, omega, k):
     return np.sort(lam)[::-1][:k]
 
 
+@pytest.mark.parametrize("n,m,k", [(10_000, 37, 5), (9_001, 120, 120), (4097, 1, 16)])
+def test_dense_products_against_numpy(n, m, k):
+    """bbfmm_dense_atb (A^T B, FP64 accumulation over n rows in 4096-row
+    chunks, ragged last chunk) and bbfmm_dense_ab (A R, FP32 out) against
+    NumPy in FP64 on the same FP32 inputs; repeated calls are identical."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    rng = np.random.default_rng(n + m)
+    A = rng.standard_normal((n, m)).astype(np.float32)
+    B = rng.standard_normal((n, m)).astype(np.float32)
+    R = rng.standard_normal((m, k))
+    tA, tB, tR = (torch.from_numpy(x).cuda() for x in (A, B, R))
+    C = bbfmm.dense_atb(tA, tB)
+    C2 = bbfmm.dense_atb(tA, tB)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
+    ref = A.astype(np.float64).T @ B.astype(np.float64)
+    # products of FP32 values are exact in FP64: only the FP64 summation order differs
+    assert np.abs(C.cpu().numpy() - ref).max() <= 1e-12 * np.abs(A).max() * np.abs(B).max() * n
+    D = bbfmm.dense_ab(tA, tR).cpu().numpy()
+    ref = A.astype(np.float64) @ R
+    # one FP32 rounding of an FP64 sum
+    assert np.all(np.abs(D - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-12 * np.abs(R).max() * m)
+
+
 def test_randomized_eigenvalues_match_exact_products():
     import torch
     from paper_1903_02153_amd import bbfmm, pca
