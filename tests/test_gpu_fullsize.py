@@ -10,8 +10,8 @@ The tree is compared bit for bit.  phi is compared with the FP64 oracle bbFMM
 (same tree, order and SVD tolerance) on 4096 sampled rows and every column,
 per column (relative L2) and per element, for the workload's own M2L
 precision with the launch shapes the autotuner picks (as the benchmark runs
-it), for split-BF16x3 on the slab, and for the FP32 path with the built-in
-heuristic.  The oracle values of all columns are stored in
+it), for the other 16-bit format (split-BF16x3 on the slab, scaled FP16 on the
+clusters), and for the FP32 path with the built-in heuristic.  The oracle values of all columns are stored in
 tests/golden/fullsize_ref_*.npz (written by make_fullsize_refs.py, which
 calls only the oracle); here the oracle recomputes the last column and it
 must equal the stored one before the file is used."""
@@ -60,14 +60,15 @@ def workload(request):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("which", ["own-autotuned", "bf16x3-autotuned", "fp32"])
+@pytest.mark.parametrize("which", ["own-autotuned", "other16-autotuned", "fp32"])
 def test_full_size_batched(workload, which):
+    """other16: the 16-bit M2L format that is not the workload's own
+    (split-BF16x3 on the slab, scaled FP16 on the clusters)."""
     from paper_1903_02153_amd import bbfmm
     w, gt, sig, ref = workload
-    prec = {"own-autotuned": w.precision, "bf16x3-autotuned": synth.PREC_BF16X3,
+    other16 = synth.PREC_FP16_SCALED if w.precision == synth.PREC_BF16X3 else synth.PREC_BF16X3
+    prec = {"own-autotuned": w.precision, "other16-autotuned": other16,
             "fp32": synth.PREC_FP32}[which]
-    if which == "bf16x3-autotuned" and prec == w.precision:
-        pytest.skip("the workload's own precision is split-BF16x3 (covered by own-autotuned)")
     go = bbfmm.precompute_operators(gt, w.eps, prec)
     opts = bbfmm.autotune(gt, go, sig, reps=2)[0] if which.endswith("autotuned") else {}
     phi = run_plan(gt, go, sig, **opts).cpu().numpy().astype(np.float64)
