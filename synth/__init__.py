@@ -107,6 +107,26 @@ def cfg_uniform_1m(seed: int = 2, sample_seed: int = 1002,
                     fixed_depth=6, sample_rows=rows)
 
 
+# The paper's strong-scaling table (Section 4): uniform points in the unit
+# cube, 1/r, Chebyshev order 4, tree levels 5 / 6 / 7 for N = 6.4e5 / 5.12e6
+# / 4.096e7 (about 156 points per leaf).
+PAPER_SCALING = ((640_000, 5), (5_120_000, 6), (40_960_000, 7))
+
+
+def cfg_paper_scaling(i: int, n_sample: int = 256) -> Workload:
+    """Row i of the paper's strong-scaling table: N uniform points, 1/r,
+    n = 4, fixed depth, one RHS in U[0,1] (non-negative weights: the table
+    does not print them, and these reproduce its errors); n_sample rows
+    sampled without replacement for the comparison with the direct sum."""
+    n, depth = PAPER_SCALING[i]
+    rng = np.random.default_rng(60 + i)
+    pts = uniform_points(rng, n)
+    sig = rng.uniform(0.0, 1.0, size=(n, 1)).astype(np.float32)
+    rows = np.sort(np.random.default_rng(1060 + i).choice(n, n_sample, replace=False))
+    return Workload(f"uniform-{n}-invr-n4-d{depth}", pts, sig, KERNEL_INV_R, 1.0, 4,
+                    fixed_depth=depth, sample_rows=rows)
+
+
 def cfg_clustered_2m(seed: int = 3, r: int = 16,
                      precision: int = PREC_BF16X3) -> Workload:
     """N=2^21 in 64 Gaussian clusters (std 0.02), exp(-r/0.1), n=6, depth by
