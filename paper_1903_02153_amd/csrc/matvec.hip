@@ -31,7 +31,6 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kLdsFloats = 4096;      // per LDS buffer of the up / down kernels
 
 // --------------------------------------------------------- geometry ----
 __device__ inline uint32_t compact3(uint64_t x) {
@@ -1970,7 +1969,6 @@ k_p2p(const float *xs, const float *ys, const float *zs, const int32_t *sb_leaf,
                 center_pair(geo.lo[d], compact3(key >> d), geo.h, chi, clo);
                 lagrange(cc, local_coord(p[d], chi, clo, geo.inv_h), l[d]);
             }
-#pragma unroll
             for (int c = 0; c < RC; ++c) {
                 if (c >= nr) break;
                 const float *f = FL + (int64_t(a) * r + rhs0 + c) * mp;

@@ -765,7 +765,8 @@ void adapt_lists(bbfmm_tree &t, hipStream_t s) {
                 T, t.fleaf.keys.p, t.fl_level.p, NL, o);
             BB_LAUNCH_CHECK();
         });
-    for (int step = 0; nf > 0; ++step) {
+    for (int step = 0;; ++step) {       // `pass` updates nf, the frontier's size
+        if (nf <= 0) break;
         BB_INTERNAL(step <= L, "adaptive list frontier did not drain");
         DBuf<int32_t> q0 = std::move(fq), l0 = std::move(fl), c0 = std::move(fc);
         const int64_t n0 = nf;
