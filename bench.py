@@ -342,10 +342,10 @@ def batched_variants(steps: int, warmup: int, tune: bool):
 def adaptive_section(steps: int = 10):
     """The level-adaptive tree (Section 2.1 on adaptive subdivision) on the
     clustered 2M-point workload (64 tight clusters, exp(-r/0.1), n = 6,
-    r = 16, split-BF16 M2L, leaf size 64, at most 7 levels) beside the
-    uniform tree of the same depth rule: cells, near-field pairs, time per
-    product (HIP-graph replay) and the error against the stored direct sum on
-    1024 sampled rows (tests/golden/make_bench_refs.py)."""
+    r = 16, split-BF16 M2L, leaf size 64, at most 7 levels, then 8) beside
+    the uniform tree of the same depth rule: cells, near-field pairs, time
+    per product (HIP-graph replay) and the error against the stored direct
+    sum on 1024 sampled rows (tests/golden/make_bench_refs.py)."""
     import numpy as np
     import torch
 
@@ -359,10 +359,14 @@ def adaptive_section(steps: int = 10):
     pts = torch.from_numpy(w.points).cuda()
     sig = torch.from_numpy(w.sigma).cuda()
     out = {"workload": w.name, "precision": "bf16x3"}
-    for tag, adaptive in (("uniform", False), ("adaptive", True)):
+    # the workload's 7-level cap, then both trees with one more level (the
+    # adaptive tree refines only the dense clusters)
+    for tag, adaptive, md in (("uniform", False, w.max_depth), ("adaptive", True, w.max_depth),
+                              ("uniform_d8", False, w.max_depth + 1),
+                              ("adaptive_d8", True, w.max_depth + 1)):
         t0 = time.perf_counter()
         tree = bbfmm.build_tree(pts, w.kernel_id, w.kernel_param, cheb_order=w.order,
-                                leaf_size=w.leaf_size, max_depth=w.max_depth,
+                                leaf_size=w.leaf_size, max_depth=md,
                                 fixed_depth=w.fixed_depth, adaptive=adaptive)
         torch.cuda.synchronize()
         t_tree = time.perf_counter() - t0

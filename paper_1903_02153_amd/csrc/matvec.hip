@@ -2470,23 +2470,26 @@ __device__ inline void node_coords(const ChebConst &cc, const float *lo, uint64_
 // P2L over the X lists of one level: F[cell][c][i] += sum over the points
 // y_j of the cell's X leaves of K(x*_i, y_j) sigma_j[c], x*_i the cell's
 // Chebyshev nodes (the local expansion holds the far field at the nodes).
-// One wave per (cell with an X list, column); lanes own nodes, sources are
-// staged 64 at a time.
-template <int N, int KID>
+// One wave per (cell with an X list, RC columns); lanes own nodes, sources
+// are staged 64 at a time, and each kernel value serves the RC columns.
+template <int N, int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_p2l(const int32_t *xcells, const int32_t *xoff, const int32_t *xleaf, const int32_t *lpb,
       const int32_t *lpe, const uint64_t *keys, const float *xs, const float *ys, const float *zs,
       const float *sig_s, int ld, Geo geo, ChebConst cc, float cs, int r, int mp, float *F) {
     constexpr int m = N * N * N, Q = (m + 63) / 64;
     __shared__ float4 sp[64];
+    __shared__ float sv[64][RC];
     const int lane = threadIdx.x;
-    const int cell = xcells[blockIdx.x], c = blockIdx.y;
+    const int cell = xcells[blockIdx.x], c0 = blockIdx.y * RC;
+    const int nr = min(RC, r - c0);
     const uint64_t key = keys[cell];
-    float nx[Q][3], acc[Q];
+    float nx[Q][3], acc[Q][RC];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         node_coords<N>(cc, geo.lo, key, geo.h, cs, min(lane + 64 * q, m - 1), nx[q]);
-        acc[q] = 0.f;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[q][c] = 0.f;
     }
     for (int e = xoff[cell]; e < xoff[cell + 1]; ++e) {
         const int a = xleaf[e], b = lpb[a], en = lpe[a];
@@ -2495,21 +2498,32 @@ k_p2l(const int32_t *xcells, const int32_t *xoff, const int32_t *xleaf, const in
             __syncthreads();                       // previous chunk consumed
             if (lane < np) {
                 const int j = p0 + lane;
-                sp[lane] = make_float4(xs[j] * cs, ys[j] * cs, zs[j] * cs, sig_s[int64_t(j) * ld + c]);
+                sp[lane] = make_float4(xs[j] * cs, ys[j] * cs, zs[j] * cs, 0.f);
+#pragma unroll
+                for (int c = 0; c < RC; ++c) sv[lane][c] = c < nr ? sig_s[int64_t(j) * ld + c0 + c] : 0.f;
             }
             __syncthreads();
             for (int j = 0; j < np; ++j) {
                 const float4 y = sp[j];
+                float sg[RC];
 #pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    acc[q] += kernel_eval<KID>(nx[q][0] - y.x, nx[q][1] - y.y, nx[q][2] - y.z) * y.w;
+                for (int c = 0; c < RC; ++c) sg[c] = sv[j][c];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const float kv = kernel_eval<KID>(nx[q][0] - y.x, nx[q][1] - y.y, nx[q][2] - y.z);
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) acc[q][c] += kv * sg[c];
+                }
             }
         }
     }
-    float *f = F + (int64_t(cell) * r + c) * mp;
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-        if (lane + 64 * q < m) f[lane + 64 * q] += acc[q];
+    for (int c = 0; c < RC; ++c) {
+        float *f = F + (int64_t(cell) * r + c0 + (c < nr ? c : 0)) * mp;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (c < nr && lane + 64 * q < m) f[lane + 64 * q] += acc[q][c];
+    }
 }
 
 // Per-level arrays of a plan over a level-adaptive tree, by value.
@@ -2523,33 +2537,34 @@ struct LevelExp {
 // The far field at the points of every leaf of a level-adaptive tree, added
 // to phi after the near field: L2P from the leaf's local expansion (leaves on
 // levels >= 2) and M2P over its W list, phi(x) += sum_i K(x, y*_i) M_A[i]
-// with y*_i the Chebyshev nodes of cell A.  One wave per (leaf, column);
-// lanes own targets; a W cell's nodes and coefficients are staged in LDS.
-template <int N, int KID>
+// with y*_i the Chebyshev nodes of cell A.  One wave per (leaf, RC
+// columns); lanes own targets; a W cell's node coordinates and its RC
+// columns of coefficients are staged in LDS, and each kernel value serves
+// the RC columns.  The leaf's local expansion is read at wave-uniform
+// addresses.
+template <int N, int KID, int RC>
 __global__ void __launch_bounds__(64)
 k_leaf_far(const int32_t *lpb, const int32_t *lpe, const uint64_t *lkey, const int32_t *llev,
            const int32_t *lcell, const int32_t *woff, const int32_t *wlev, const int32_t *wcell,
            LevelExp X, const float *xs, const float *ys, const float *zs, const int32_t *perm,
            Geo geo, ChebConst cc, float cs, int r, int mp, float *phi) {
     constexpr int m = N * N * N, Q = (m + 63) / 64;
-    __shared__ float4 nd[64 * Q];        // a W cell: node coordinates (kernel units), M
-    __shared__ float fs[64 * Q];         // the leaf's local expansion
+    __shared__ float4 nd[64 * Q];        // a W cell's node coordinates (kernel units)
+    __shared__ float ms[64 * Q][RC];     // ... and its coefficients, RC columns
     const int lane = threadIdx.x;
-    const int q = blockIdx.x, c = blockIdx.y;
+    const int q = blockIdx.x, c0 = blockIdx.y * RC;
+    const int nr = min(RC, r - c0);
     const int lv = llev[q], b = lpb[q], e = lpe[q];
     const uint64_t key = lkey[q];
     const int w0 = woff[q], w1 = woff[q + 1];
-    if (lv >= 2) {
-        const float *f = X.F[lv] + (int64_t(lcell[q]) * r + c) * mp;
-        for (int i = lane; i < m; i += 64) fs[i] = f[i];
-    }
     for (int p0 = b; p0 < e; p0 += 64) {
         const int i = p0 + lane;
         const bool valid = i < e;
         const int ii = valid ? i : b;
         const float x = xs[ii], y = ys[ii], z = zs[ii];
-        float acc = 0.f;
-        __syncthreads();                         // fs written, nd of the last chunk consumed
+        float acc[RC];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] = 0.f;
         if (lv >= 2) {
             float l[3][N];
             const float p3[3] = {x, y, z};
@@ -2559,26 +2574,37 @@ k_leaf_far(const int32_t *lpb, const int32_t *lpe, const uint64_t *lkey, const i
                 center_pair(geo.lo[d], compact3(key >> d), X.h[lv], chi, clo);
                 lagrange_t<N>(cc, local_coord(p3[d], chi, clo, X.inv_h[lv]), l[d]);
             }
-            acc = l2p_sum<N>(fs, l);
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < nr) acc[c] = l2p_sum<N>(X.F[lv] + (int64_t(lcell[q]) * r + c0 + c) * mp, l);
         }
         const float xc = x * cs, yc = y * cs, zc = z * cs;
         for (int w = w0; w < w1; ++w) {
             const int la = wlev[w], a = wcell[w];
             const uint64_t ka = X.keys[la][a];
-            const float *M = X.M[la] + (int64_t(a) * r + c) * mp;
+            const float *M = X.M[la] + (int64_t(a) * r + c0) * mp;
             __syncthreads();                     // previous W cell consumed
             for (int k = lane; k < m; k += 64) {
                 float t[3];
                 node_coords<N>(cc, geo.lo, ka, X.h[la], cs, k, t);
-                nd[k] = make_float4(t[0], t[1], t[2], M[k]);
+                nd[k] = make_float4(t[0], t[1], t[2], 0.f);
+#pragma unroll
+                for (int c = 0; c < RC; ++c) ms[k][c] = c < nr ? M[int64_t(c) * mp + k] : 0.f;
             }
             __syncthreads();
             for (int k = 0; k < m; ++k) {
                 const float4 v = nd[k];
-                acc += kernel_eval<KID>(xc - v.x, yc - v.y, zc - v.z) * v.w;
+                const float kv = kernel_eval<KID>(xc - v.x, yc - v.y, zc - v.z);
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[c] += kv * ms[k][c];
             }
         }
-        if (valid) phi[int64_t(perm[i]) * r + c] += acc;
+        if (valid) {
+            float *out = phi + int64_t(perm[i]) * r + c0;
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < nr) out[c] += acc[c];
+        }
     }
 }
 
@@ -3129,14 +3155,18 @@ void launch_leaf_far(const Plan &p, const Geo &geo, float *phi, hipStream_t s) {
     }
     const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
     const int mp = p.ops->mp, r = int(p.r);
-    dim3 g(unsigned(fl.C), unsigned(r));
-#define BB_LF(NN) case NN: k_leaf_far<NN, KID><<<g, 64, 0, s>>>(fl.pb.p, fl.pe.p, fl.keys.p,       \
+    // columns per wave: one, or blocks of 16 (each kernel value serves them all)
+    const int rc = r == 1 ? 1 : 16;
+    dim3 g(unsigned(fl.C), unsigned(ceil_div(r, rc)));
+#define BB_LF1(NN, RCC) k_leaf_far<NN, KID, RCC><<<g, 64, 0, s>>>(fl.pb.p, fl.pe.p, fl.keys.p,     \
         t.fl_level.p, t.fl_cell.p, t.w_off.p, t.w_level.p, t.w_cell.p, X, t.xs.p, t.ys.p, t.zs.p, \
-        t.perm.p, geo, p.ops->cheb, cs, r, mp, phi); break;
+        t.perm.p, geo, p.ops->cheb, cs, r, mp, phi)
+#define BB_LF(NN) case NN: if (rc == 1) BB_LF1(NN, 1); else BB_LF1(NN, 16); break;
     switch (p.ops->n) {
     BB_LF(2) BB_LF(3) BB_LF(4) BB_LF(5) BB_LF(6) BB_LF(7) BB_LF(8)
     }
 #undef BB_LF
+#undef BB_LF1
     BB_LAUNCH_CHECK();
 }
 
@@ -3621,16 +3651,20 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             gl.inv_h = 1.0f / gl.h;
             const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
             const LevelData &fl = t.leaves();
-            dim3 g(unsigned(lv.nx_cells), unsigned(r));
+            const int rc = r == 1 ? 1 : 16;        // columns per wave
+            dim3 g(unsigned(lv.nx_cells), unsigned(ceil_div(r, rc)));
+#define BB_P2L_N(NN, KK)                                                                              \
+            if (rc == 1) k_p2l<NN, KK, 1><<<g, 64, 0, s>>>(BB_P2L_ARGS);                              \
+            else k_p2l<NN, KK, 16><<<g, 64, 0, s>>>(BB_P2L_ARGS);
 #define BB_P2L(KK)                                                                                    \
             switch (n) {                                                                              \
-            case 2: k_p2l<2, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            case 3: k_p2l<3, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            case 4: k_p2l<4, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            case 5: k_p2l<5, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            case 6: k_p2l<6, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            case 7: k_p2l<7, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                                \
-            default: k_p2l<8, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS); break;                               \
+            case 2: BB_P2L_N(2, KK) break;                                                            \
+            case 3: BB_P2L_N(3, KK) break;                                                            \
+            case 4: BB_P2L_N(4, KK) break;                                                            \
+            case 5: BB_P2L_N(5, KK) break;                                                            \
+            case 6: BB_P2L_N(6, KK) break;                                                            \
+            case 7: BB_P2L_N(7, KK) break;                                                            \
+            default: BB_P2L_N(8, KK) break;                                                           \
             }
 #define BB_P2L_ARGS lv.x_cells.p, lv.x_off.p, lv.x_leaf.p, fl.pb.p, fl.pe.p, lv.keys.p, t.xs.p, \
                     t.ys.p, t.zs.p, p.sig_s.p, p.ld_s, gl, o.cheb, cs, r, mp, p.F[lvl].p
@@ -3643,6 +3677,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             }
 #undef BB_P2L_ARGS
 #undef BB_P2L
+#undef BB_P2L_N
             BB_LAUNCH_CHECK();
         }
     }
