@@ -2608,6 +2608,112 @@ k_leaf_far(const int32_t *lpb, const int32_t *lpe, const uint64_t *lkey, const i
     }
 }
 
+// The same far field as a product on FP32 MFMA, for blocks of 16 right-hand
+// sides: phi[targets][c] += A B with, for M2P over a W cell, A[t][node] =
+// K(x_t, y*_node) (lane i + 16 k evaluates target i, node 4 s + k itself into
+// its A operand, as the near field does) and B[node][c] the cell's
+// coefficients; for L2P, A[t][node] the Lagrange product of the leaf's own
+// cell at x_t and B its local expansion.  One wave per (leaf, 16 columns),
+// targets in chunks of 64 (four 16-row blocks); a cell's node coordinates
+// and 16 columns of coefficients are staged in LDS (nodes padded to a
+// multiple of 4 with zero coefficients).
+template <int N, int KID>
+__global__ void __launch_bounds__(64)
+k_leaf_far_mfma(const int32_t *lpb, const int32_t *lpe, const uint64_t *lkey, const int32_t *llev,
+                const int32_t *lcell, const int32_t *woff, const int32_t *wlev, const int32_t *wcell,
+                LevelExp X, const float *xs, const float *ys, const float *zs, const int32_t *perm,
+                Geo geo, ChebConst cc, float cs, int r, int mp, float *phi) {
+    constexpr int m = N * N * N, MK = (m + 3) / 4 * 4;
+    __shared__ float4 nd[MK];             // node coordinates (kernel units) of the staged cell
+    __shared__ float cf[MK][16];          // its coefficients, 16 columns
+    __shared__ float Ls[64][3 * N];       // Lagrange values of the chunk's targets
+    const int lane = threadIdx.x, row = lane & 15, kq = lane >> 4;
+    const int q = blockIdx.x, c0 = blockIdx.y * 16;
+    const int nr = min(16, r - c0);
+    const int lv = llev[q], b = lpb[q], e = lpe[q];
+    const uint64_t key = lkey[q];
+    const int w0 = woff[q], w1 = woff[q + 1];
+    // stage cell coefficients C[cell][c0 + c][node] (zero past m and past r)
+    auto stage_coef = [&](const float *C) {
+        for (int g = lane; g < MK * 16; g += 64) {
+            const int k = g >> 4, c = g & 15;
+            cf[k][c] = (k < m && c < nr) ? C[int64_t(c) * mp + k] : 0.f;
+        }
+    };
+    for (int p0 = b; p0 < e; p0 += 64) {
+        float tx[4], ty[4], tz[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int ti = p0 + 16 * rb + row;
+            const int tc = ti < e ? ti : b;          // rows past the leaf repeat a target; not written
+            tx[rb] = xs[tc] * cs;
+            ty[rb] = ys[tc] * cs;
+            tz[rb] = zs[tc] * cs;
+        }
+        v4f acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (lv >= 2) {                               // L2P from the leaf's own local expansion
+            __syncthreads();                         // LDS of the previous chunk consumed
+            {
+                const int ti = p0 + lane < e ? p0 + lane : b;
+                const float p3[3] = {xs[ti], ys[ti], zs[ti]};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    float chi, clo, l[N];
+                    center_pair(geo.lo[d], compact3(key >> d), X.h[lv], chi, clo);
+                    lagrange_t<N>(cc, local_coord(p3[d], chi, clo, X.inv_h[lv]), l);
+#pragma unroll
+                    for (int k = 0; k < N; ++k) Ls[lane][d * N + k] = l[k];
+                }
+            }
+            stage_coef(X.F[lv] + (int64_t(lcell[q]) * r + c0) * mp);
+            __syncthreads();
+            for (int s0 = 0; s0 < MK; s0 += 4) {
+                const int node = s0 + kq, nn = node < m ? node : 0;
+                const int i1 = nn % N, i2 = (nn / N) % N, i3 = nn / (N * N);
+                const float bv = cf[node][row];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const float *L3 = Ls[16 * rb + row];
+                    const float av = L3[i1] * L3[N + i2] * L3[2 * N + i3];
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rb], 0, 0, 0);
+                }
+            }
+        }
+        for (int w = w0; w < w1; ++w) {             // M2P over the W list
+            const int la = wlev[w], a = wcell[w];
+            const uint64_t ka = X.keys[la][a];
+            __syncthreads();                         // previous cell consumed
+            for (int k = lane; k < MK; k += 64) {
+                float t[3];
+                node_coords<N>(cc, geo.lo, ka, X.h[la], cs, k < m ? k : 0, t);
+                nd[k] = make_float4(t[0], t[1], t[2], 0.f);
+            }
+            stage_coef(X.M[la] + (int64_t(a) * r + c0) * mp);
+            __syncthreads();
+            for (int s0 = 0; s0 < MK; s0 += 4) {
+                const int node = s0 + kq;
+                const float4 v = nd[node];
+                const float bv = cf[node][row];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const float kv = kernel_eval<KID>(tx[rb] - v.x, ty[rb] - v.y, tz[rb] - v.z);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, bv, acc[rb], 0, 0, 0);
+                }
+            }
+        }
+        // D[i][j] sits in lane j + 16 (i / 4), register i % 4
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ti = p0 + 16 * rb + 4 * kq + v;
+                if (ti < e && row < nr) phi[int64_t(perm[ti]) * r + c0 + row] += acc[rb][v];
+            }
+    }
+}
+
 // pleaf[i] = leaf holding point i (tree order)
 __global__ void __launch_bounds__(kThreads)
 k_point_leaf(const int32_t *pb, const int32_t *pe, int nleaf, int32_t *pleaf) {
@@ -3155,6 +3261,18 @@ void launch_leaf_far(const Plan &p, const Geo &geo, float *phi, hipStream_t s) {
     }
     const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
     const int mp = p.ops->mp, r = int(p.r);
+    if (p.p2p_mfma) {                       // as a product on MFMA, 16 columns per wave
+        dim3 g(unsigned(fl.C), unsigned(ceil_div(r, 16)));
+#define BB_LFM(NN) case NN: k_leaf_far_mfma<NN, KID><<<g, 64, 0, s>>>(fl.pb.p, fl.pe.p, fl.keys.p, \
+        t.fl_level.p, t.fl_cell.p, t.w_off.p, t.w_level.p, t.w_cell.p, X, t.xs.p, t.ys.p, t.zs.p, \
+        t.perm.p, geo, p.ops->cheb, cs, r, mp, phi); break;
+        switch (p.ops->n) {
+        BB_LFM(2) BB_LFM(3) BB_LFM(4) BB_LFM(5) BB_LFM(6) BB_LFM(7) BB_LFM(8)
+        }
+#undef BB_LFM
+        BB_LAUNCH_CHECK();
+        return;
+    }
     // columns per wave: one, or blocks of 16 (each kernel value serves them all)
     const int rc = r == 1 ? 1 : 16;
     dim3 g(unsigned(fl.C), unsigned(ceil_div(r, rc)));
