@@ -2526,6 +2526,71 @@ k_p2l(const int32_t *xcells, const int32_t *xoff, const int32_t *xleaf, const in
     }
 }
 
+// P2L as a product on FP32 MFMA for blocks of 16 right-hand sides:
+// F[cell][c][node] += sum_j K(x*_node, y_j) sigma_j[c], lane i + 16 k
+// evaluating node i of a 16-row block against point 4 s + k into its A
+// operand, sigma as B.  One wave per (cell with an X list, 16 columns),
+// nodes in chunks of 64 (four 16-row blocks); the X leaves' points are
+// staged 64 at a time (padded to a multiple of 4 with zero sigma).
+template <int N, int KID>
+__global__ void __launch_bounds__(64)
+k_p2l_mfma(const int32_t *xcells, const int32_t *xoff, const int32_t *xleaf, const int32_t *lpb,
+           const int32_t *lpe, const uint64_t *keys, const float *xs, const float *ys, const float *zs,
+           const float *sig_s, int ld, Geo geo, ChebConst cc, float cs, int r, int mp, float *F) {
+    constexpr int m = N * N * N;
+    __shared__ float4 sp[64];
+    __shared__ float ss[64][16];
+    const int lane = threadIdx.x, row = lane & 15, kq = lane >> 4;
+    const int cell = xcells[blockIdx.x], c0 = blockIdx.y * 16;
+    const int nr = min(16, r - c0);
+    const uint64_t key = keys[cell];
+    for (int n0 = 0; n0 < m; n0 += 64) {
+        float nx[4][3];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+            node_coords<N>(cc, geo.lo, key, geo.h, cs, min(n0 + 16 * rb + row, m - 1), nx[rb]);
+        v4f acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int e = xoff[cell]; e < xoff[cell + 1]; ++e) {
+            const int a = xleaf[e], b = lpb[a], en = lpe[a];
+            for (int p0 = b; p0 < en; p0 += 64) {
+                const int np = min(64, en - p0), npad = (np + 3) & ~3;
+                __syncthreads();                   // previous points consumed
+                {
+                    const int j = p0 + (lane < np ? lane : 0);
+                    sp[lane] = make_float4(xs[j] * cs, ys[j] * cs, zs[j] * cs, 0.f);
+                }
+                for (int g = lane; g < 64 * 16; g += 64) {
+                    const int jj = g >> 4, c = g & 15;
+                    ss[jj][c] = (jj < np && c < nr) ? sig_s[int64_t(p0 + jj) * ld + c0 + c] : 0.f;
+                }
+                __syncthreads();
+                for (int s0 = 0; s0 < npad; s0 += 4) {
+                    const float4 y = sp[s0 + kq];
+                    const float bv = ss[s0 + kq][row];
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const float kv = kernel_eval<KID>(nx[rb][0] - y.x, nx[rb][1] - y.y, nx[rb][2] - y.z);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, bv, acc[rb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // D[i][j] sits in lane j + 16 (i / 4), register i % 4: node i, column j
+        if (row < nr) {
+            float *f = F + (int64_t(cell) * r + c0 + row) * mp;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int node = n0 + 16 * rb + 4 * kq + v;
+                    if (node < m) f[node] += acc[rb][v];
+                }
+        }
+    }
+}
+
 // Per-level arrays of a plan over a level-adaptive tree, by value.
 struct LevelExp {
     const float *F[kMaxLevels];      // local expansions (levels >= 2)
@@ -3769,10 +3834,12 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
             gl.inv_h = 1.0f / gl.h;
             const float cs = coord_scale(t.params.kernel_id, t.params.kernel_param);
             const LevelData &fl = t.leaves();
-            const int rc = r == 1 ? 1 : 16;        // columns per wave
+            // columns per wave: one, or blocks of 16 (on MFMA with the MFMA near field)
+            const int rc = r == 1 ? 1 : 16;
             dim3 g(unsigned(lv.nx_cells), unsigned(ceil_div(r, rc)));
 #define BB_P2L_N(NN, KK)                                                                              \
             if (rc == 1) k_p2l<NN, KK, 1><<<g, 64, 0, s>>>(BB_P2L_ARGS);                              \
+            else if (p.p2p_mfma) k_p2l_mfma<NN, KK><<<g, 64, 0, s>>>(BB_P2L_ARGS);                    \
             else k_p2l<NN, KK, 16><<<g, 64, 0, s>>>(BB_P2L_ARGS);
 #define BB_P2L(KK)                                                                                    \
             switch (n) {                                                                              \
