@@ -157,3 +157,56 @@ def test_cancel_pending_and_destroy_with_waiter():
         x.join(timeout=60)
     assert not any(x.is_alive() for x in th)
     assert len(seen) == 6 and all(v in ("done", 7) for v in seen), seen
+
+
+def test_concurrent_clients():
+    """Four client threads submit and wait at the same time (each wait may
+    run while another thread's submit grows the request table); every
+    result equals a lone plan execution of its request bit for bit."""
+    import threading
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    models = _models()
+    srv = bbfmm.Server(hbm_budget_bytes=4 << 30, max_inflight=3, r_max=16)
+    ids = [srv.add(t, o) for t, o, *_ in models]
+    rng = np.random.default_rng(9)
+    jobs = []
+    for q in range(48):
+        m = int(rng.integers(0, len(models)))
+        r = int(rng.choice([1, 2, 4]))
+        sig = torch.from_numpy(rng.standard_normal((models[m][2], r)).astype(np.float32)).cuda()
+        jobs.append((m, sig, torch.empty_like(sig)))
+    torch.cuda.synchronize()
+    stats, errors = {}, []
+
+    def client(k):
+        try:
+            for q in range(k, len(jobs), 4):
+                m, sig, phi = jobs[q]
+                rid = srv.submit(ids[m], sig, phi)
+                stats[q] = srv.wait(rid)
+        except Exception as e:          # reported below, on the main thread
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=120)
+    assert not any(x.is_alive() for x in th) and not errors, errors
+    torch.cuda.synchronize()
+    lone = {}
+    for q, (m, sig, phi) in enumerate(jobs):
+        t, o = models[m][:2]
+        path = 1 if stats[q]["batch_r"] == 1 else 2
+        key = (m, sig.shape[1], path)
+        if key not in lone:
+            lone[key] = bbfmm.Plan(t, o, sig.shape[1], m2l_split=2, p2p_mfma=path)
+        alone = torch.empty_like(sig)
+        lone[key].execute(sig, alone)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, alone), (q, m, sig.shape[1], stats[q])
+    for p in lone.values():
+        p.close()
+    assert srv.stats()["requests_done"] == len(jobs)
+    srv.close()
