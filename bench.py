@@ -692,6 +692,18 @@ def main() -> int:
                     "note": "same plan options with the one-stream schedule, 20 launches; "
                             "p2p_* is the near-field stage alone (near field + L2P kernels) "
                             "against the 78.6 TFLOP/s FP32 vector rate without packed FP32"}
+    # the same plan replayed as one HIP graph per product (after the timed
+    # region; reported beside the metric, which is the eager timed region)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.execute(sig, phi)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(K):
+        plan.execute(sig, phi)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg0) * 1e3 / K
+    plan.set_graph(False)
     up_b, down_b = pass_bytes(info, ranks, w.order, w.r, int(opts.get("m2l_split", 1)) if opts else 1)
     passes = {"up_gbs": round(up_b / ((stage_avg["p2m"] + stage_avg["m2m"]) * 1e-3) / 1e9, 1),
               "down_gbs": round(down_b / (stage_avg["down"] * 1e-3) / 1e9, 1),
@@ -723,6 +735,10 @@ def main() -> int:
                    "plan_options": opts or "heuristic"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
+        "graph_replay": {"ms_per_step": round(graph_ms, 4),
+                         "points_rhs_per_s": w.n * w.r / (graph_ms / 1e3),
+                         "note": "the same plan replayed as a HIP graph, K products after the "
+                                 "timed region (the metric is the eager, stage-timed region)"},
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "passes": passes,
         "roofline": roofline,
