@@ -273,6 +273,19 @@ void fft_inverse(int n, const float2 *Fhat, int64_t rows, float scale, bool accu
 void fft_m2l(int n, const float2 *Mhat, const float2 *Ghat, const int32_t *itab,
              const uint64_t *keys, const int32_t *slot_t, int64_t cells, int r, float2 *Fhat,
              hipStream_t s);
+// Spatial blocks of one level for the FFT M2L of a level-uniform tree: the
+// level's cells in blocks of 4 x 4 x 4 (the cells whose keys agree above
+// the lowest 6 bits); tgt[blk][key & 63] is the cell at that position or
+// -1, halo[blk][(z * 8 + y) * 8 + x] the cell at block offset (x - 2, y - 2,
+// z - 2) cells or -1.  Every interaction-list source of a block's targets
+// lies in that 8 x 8 x 8 halo.
+struct FftBlocks {
+    DBuf<int32_t> tgt, halo;
+    int32_t nblk = 0;
+};
+void fft_build_blocks(const uint64_t *keys, int32_t C, int lvl, FftBlocks &b, hipStream_t s);
+void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b,
+                    const int32_t *tables, int r, float2 *Fhat, hipStream_t s);
 void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s);
 
 struct Plan;

@@ -27,6 +27,8 @@
 // DFT definition) and stored as FP32 complex.
 #include "common.h"
 
+#include <vector>
+
 namespace bbfmm {
 namespace {
 
@@ -200,6 +202,87 @@ k_m2l_fft(const float2 *Mhat, const float2 *Ghat, const int32_t *itab, const uin
     }
 }
 
+// Spatially blocked form of the same sums (level-uniform trees).  One
+// workgroup per (block of 4 x 4 x 4 target cells, slice of kFq frequencies,
+// column): the slice of the 8 x 8 x 8 source halo's spectra and of the 316
+// operator spectra is staged in LDS once, so each staged source value serves
+// every target of the block that has it in its list (up to 27 of 64) instead
+// of being gathered again per target.  Thread (q, o, k): frequency q of the
+// slice, octant o, quarter k of the 189 slots; it accumulates the block's
+// eight targets of octant o (one per parent), which share the transfer
+// vector of every slot, so one operator value serves eight products.  The
+// four quarters' partial sums are added in quarter order.  A slot whose
+// source cell does not exist reads a zero halo entry.
+constexpr int kFq = 8;              // frequencies per workgroup
+constexpr int kHalo = 512;          // 8 x 8 x 8 source cells
+constexpr int kRow = kFq + 1;       // LDS row of one halo cell's slice (padded)
+
+__global__ void __launch_bounds__(kThreads)
+k_m2l_fft_blk(const float2 *Mhat, const float2 *Ghat, const int32_t *btgt, const int32_t *bhalo,
+              const int32_t *tables, int r, int Q, float2 *Fhat) {
+    __shared__ float2 hs[kHalo * kRow];
+    __shared__ float2 gs[kNumT * kFq];
+    __shared__ int32_t sb[8 * kSlots];        // (t, halo base cell) per (octant, slot)
+    const int blk = blockIdx.x, q0 = blockIdx.y * kFq, c = blockIdx.z;
+    const int tid = threadIdx.x;
+    const int32_t *halo = bhalo + int64_t(blk) * kHalo;
+    for (int e = tid; e < kHalo * kFq; e += kThreads) {
+        const int h = e / kFq, q = e % kFq;
+        const int b = halo[h];
+        hs[h * kRow + q] = (b >= 0 && q0 + q < Q) ? Mhat[(int64_t(b) * r + c) * Q + q0 + q]
+                                                  : make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < kNumT * kFq; e += kThreads) {
+        const int t = e / kFq, q = e % kFq;
+        gs[t * kFq + q] = q0 + q < Q ? Ghat[int64_t(t) * Q + q0 + q] : make_float2(0.f, 0.f);
+    }
+    // the source of slot j of the target at (2 px + ox, ...) is that cell
+    // plus t: halo cell base(o, t) + 2 px + 16 py + 128 pz
+    for (int e = tid; e < 8 * kSlots; e += kThreads) {
+        const int o = e / kSlots;
+        const int t = tables[3 * kNumT + e];                 // slot_t[o][j]
+        const int hx = (o & 1) + tables[3 * t] + 2;
+        const int hy = ((o >> 1) & 1) + tables[3 * t + 1] + 2;
+        const int hz = (o >> 2) + tables[3 * t + 2] + 2;
+        sb[e] = t | (((hz * 8 + hy) * 8 + hx) << 16);
+    }
+    __syncthreads();
+    const int q = tid % kFq, o = (tid / kFq) % 8, k = tid / (8 * kFq);
+    float2 acc[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[p] = make_float2(0.f, 0.f);
+    const int j0 = k * kSlots / 4, j1 = (k + 1) * kSlots / 4;
+    for (int j = j0; j < j1; ++j) {
+        const int v = sb[o * kSlots + j];
+        const float2 g = gs[(v & 0xffff) * kFq + q];
+        const float2 *hb = hs + (v >> 16) * kRow + q;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const float2 m = hb[(2 * (p & 1) + 16 * ((p >> 1) & 1) + 128 * (p >> 2)) * kRow];
+            acc[p].x = __fmaf_rn(g.x, m.x, __fmaf_rn(-g.y, m.y, acc[p].x));
+            acc[p].y = __fmaf_rn(g.x, m.y, __fmaf_rn(g.y, m.x, acc[p].y));
+        }
+    }
+    __syncthreads();                          // the halo slice is no longer read
+    float2 *part = hs;                        // [k][target p * 8 + o][q]
+#pragma unroll
+    for (int p = 0; p < 8; ++p) part[(k * 64 + p * 8 + o) * kFq + q] = acc[p];
+    __syncthreads();
+    const int32_t *tg = btgt + int64_t(blk) * 64;
+    for (int e = tid; e < 64 * kFq; e += kThreads) {
+        const int l = e / kFq, qq = e % kFq;
+        const int a = tg[l];
+        if (a < 0 || q0 + qq >= Q) continue;
+        float2 sum = part[e];
+        for (int kk = 1; kk < 4; ++kk) {
+            const float2 v = part[kk * 64 * kFq + e];
+            sum.x += v.x;
+            sum.y += v.y;
+        }
+        Fhat[(int64_t(a) * r + c) * Q + q0 + qq] = sum;
+    }
+}
+
 // ---------------------------------------------- operator spectra (FP64) ----
 __device__ inline double kernel_f64(int kid, double a, double dx, double dy, double dz) {
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -318,6 +401,74 @@ void fft_m2l(int n, const float2 *Mhat, const float2 *Ghat, const int32_t *itab,
     if (cells == 0) return;
     k_m2l_fft<<<dim3(unsigned(cells), unsigned(r)), kThreads, 0, s>>>(Mhat, Ghat, itab, keys, slot_t, r,
                                                                       fft_freqs(n), Fhat);
+    BB_LAUNCH_CHECK();
+}
+
+
+// Host side: the level's keys are ascending Morton keys, so a block's cells
+// are one run of equal key >> 6.  Halo cells are found in a dense grid of
+// the level (levels up to 8) or by binary search in the keys.
+void fft_build_blocks(const uint64_t *keys, int32_t C, int lvl, FftBlocks &b, hipStream_t s) {
+    std::vector<uint64_t> k(size_t(std::max(C, 0)));
+    if (C > 0) {
+        BB_HIP(hipMemcpyAsync(k.data(), keys, size_t(C) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        BB_HIP(hipStreamSynchronize(s));
+    }
+    auto coord = [](uint64_t key, int d) {
+        uint32_t v = 0;
+        for (int i = 0; i < 21; ++i) v |= uint32_t((key >> (3 * i + d)) & 1u) << i;
+        return int(v);
+    };
+    auto key_of = [](int x, int y, int z) {
+        uint64_t key = 0;
+        for (int i = 0; i < 21; ++i)
+            key |= (uint64_t((x >> i) & 1) << (3 * i)) | (uint64_t((y >> i) & 1) << (3 * i + 1)) |
+                   (uint64_t((z >> i) & 1) << (3 * i + 2));
+        return key;
+    };
+    const int64_t lim = int64_t(1) << lvl;
+    const bool dense = lvl <= 8;
+    std::vector<int32_t> grid;
+    if (dense) {
+        grid.assign(size_t(lim * lim * lim), -1);
+        for (int32_t a = 0; a < C; ++a)
+            grid[size_t((coord(k[a], 2) * lim + coord(k[a], 1)) * lim + coord(k[a], 0))] = a;
+    }
+    auto find = [&](int x, int y, int z) -> int32_t {
+        if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+        if (dense) return grid[size_t((z * lim + y) * lim + x)];
+        const uint64_t key = key_of(x, y, z);
+        const auto it = std::lower_bound(k.begin(), k.end(), key);
+        return (it != k.end() && *it == key) ? int32_t(it - k.begin()) : -1;
+    };
+    std::vector<int32_t> tgt, halo;
+    for (int32_t a = 0; a < C;) {
+        const uint64_t bk = k[a] >> 6;
+        tgt.insert(tgt.end(), 64, -1);
+        int32_t *tb = tgt.data() + tgt.size() - 64;
+        for (; a < C && (k[a] >> 6) == bk; ++a) tb[k[a] & 63] = a;
+        const int bx = 4 * coord(bk, 0), by = 4 * coord(bk, 1), bz = 4 * coord(bk, 2);
+        for (int hz = 0; hz < 8; ++hz)
+            for (int hy = 0; hy < 8; ++hy)
+                for (int hx = 0; hx < 8; ++hx) halo.push_back(find(bx - 2 + hx, by - 2 + hy, bz - 2 + hz));
+    }
+    b.nblk = int32_t(tgt.size() / 64);
+    b.tgt.alloc(tgt.size());
+    b.halo.alloc(halo.size());
+    if (b.nblk > 0) {
+        BB_HIP(hipMemcpyAsync(b.tgt.p, tgt.data(), tgt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BB_HIP(hipMemcpyAsync(b.halo.p, halo.data(), halo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BB_HIP(hipStreamSynchronize(s));
+    }
+}
+
+void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b,
+                    const int32_t *tables, int r, float2 *Fhat, hipStream_t s) {
+    if (b.nblk == 0) return;
+    const int Q = fft_freqs(n);
+    BB_REQUIRE(r >= 1 && r <= 65535, "FFT M2L: r out of range");
+    k_m2l_fft_blk<<<dim3(unsigned(b.nblk), unsigned(ceil_div(Q, kFq)), unsigned(r)), kThreads, 0, s>>>(
+        Mhat, Ghat, b.tgt.p, b.halo.p, tables, r, Q, Fhat);
     BB_LAUNCH_CHECK();
 }
 

@@ -2844,6 +2844,8 @@ struct Plan {
     DBuf<uint16_t> Mh16[kMaxLevels], Ml16[kMaxLevels];   // 16-bit M2L operand formats
     DBuf<float> Msinv[kMaxLevels];                       // fp16 block scales
     DBuf<float2> Mc[kMaxLevels], Fc[kMaxLevels];         // FFT M2L: spectra of M and F
+    FftBlocks fblk[kMaxLevels];                          // FFT M2L by spatial blocks
+    bool fft_blocked = false;
     DBuf<int32_t> tiles;                // all M2L tiles of all levels
     DBuf<uint32_t> masks;               // per tile: slots in which some target has a source
     int ntiles = 0, max_kp = 0;
@@ -2956,6 +2958,8 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
     // (off by default: on the batched workloads the separate kernels are
     // faster; the autotuner measures both)
     p->leaf_fused = !t->adaptive && L >= 3 && o->precision != BBFMM_M2L_FFT && op.leaf_fused == 2;
+    // FFT M2L of a level-uniform tree: by spatial blocks unless asked per cell
+    p->fft_blocked = o->precision == BBFMM_M2L_FFT && !t->adaptive && op.m2l_block != 1;
     std::vector<int32_t> tl;
     for (int lvl = 2; lvl <= L; ++lvl) {
         const int64_t C = t->lv[lvl].C;
@@ -2968,6 +2972,10 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             p->Mc[lvl].alloc(C * r * Q);
             p->Fc[lvl].alloc(C * r * Q);
             ws += p->Mc[lvl].bytes() + p->Fc[lvl].bytes() + p->M[lvl].bytes() + p->F[lvl].bytes();
+            if (p->fft_blocked) {
+                fft_build_blocks(t->lv[lvl].keys.p, int32_t(C), lvl, p->fblk[lvl], setup);
+                ws += p->fblk[lvl].tgt.bytes() + p->fblk[lvl].halo.bytes();
+            }
             continue;            // no compressed operands, no M2L tiles
         } else if (o->precision == BBFMM_M2L_FP32) {
             // one zero cell past the last: the M2L's missing sources read it
@@ -3200,7 +3208,7 @@ void plan_resolved_options(const Plan *p, bbfmm_plan_options *out) {
     out->m2l_occupancy = p->m2l_occupancy;
     out->m2l_layout = p->m2l_layout;
     out->m2l_schedule = p->m2l_early ? 2 : 1;
-    out->m2l_block = p->m2l_block ? 2 : 1;
+    out->m2l_block = (p->m2l_block || p->fft_blocked) ? 2 : 1;
     out->m2l_rtile = 16 * p->m2l_cb;
     out->m2l_xcd = p->m2l_xsplit ? 2 : 1;
     out->leaf_fused = p->leaf_fused ? 2 : 1;
@@ -3706,8 +3714,12 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         }
         if (o.precision == BBFMM_M2L_FFT) {
             for (int lvl = lo; lvl <= hi; ++lvl)
-                fft_m2l(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p,
-                        t.tables.p + 3 * kNumT, t.lv[lvl].C, r, p.Fc[lvl].p, st);
+                if (p.fft_blocked)
+                    fft_m2l_blocks(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, p.fblk[lvl], t.tables.p, r,
+                                   p.Fc[lvl].p, st);
+                else
+                    fft_m2l(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p,
+                            t.tables.p + 3 * kNumT, t.lv[lvl].C, r, p.Fc[lvl].p, st);
             return;
         }
         const int t0 = p.tile_off[lo], t1 = p.tile_off[hi + 1];

@@ -520,9 +520,15 @@ def test_fft_m2l_matches_oracle(kid, prm, n, kind, r, depth):
     ot = oracle_tree(pts, fixed_depth=depth)
     oo = oops.precompute(ot, kid, prm, n, 0.0, nodes="uniform")
     ref = ofmm.matvec(ot, oo, pts, sig, kid, prm)
-    for opts in (dict(p2p_mfma=1), dict(p2p_mfma=2)):
+    # m2l_block: 2 (the default) stages each 4^3 block's source halo once
+    # per frequency slice; 1 runs one workgroup per (target cell, column)
+    outs = {}
+    for opts in (dict(p2p_mfma=1), dict(p2p_mfma=2), dict(p2p_mfma=1, m2l_block=1)):
         got = run_plan(gt, go, sig, **opts).cpu().numpy()
         assert_parity(got, ref, TOL, f"FFT M2L kernel {kid} n {n} r {r} {opts}")
+        outs[tuple(opts.items())] = got
+    a, b = outs[(("p2p_mfma", 1),)], outs[(("p2p_mfma", 1), ("m2l_block", 1))]
+    assert np.abs(a - b).max() <= 5e-6 * np.abs(b).max(), "blocked and per-cell FFT M2L differ"
 
 
 def test_fft_m2l_polynomial_kernel_exact():
