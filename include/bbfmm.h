@@ -384,7 +384,11 @@ typedef struct {
                             /* pairs of one octant; 2 = the children of a parent */
                             /* cell as one block, each source of their halo      */
                             /* staged once for all of them (no slot split);      */
-                            /* 0 = 2 from r = 16 on                              */
+                            /* 0 = 2 from r = 16 on.  FFT M2L (level-uniform     */
+                            /* trees): 1 = one workgroup per (target cell,       */
+                            /* column); 2 or 0 = blocks of 4 x 4 x 4 targets     */
+                            /* sharing one staged 8 x 8 x 8 source halo per      */
+                            /* slice of frequencies                              */
     int32_t m2l_rtile;      /* parent blocks: right-hand sides per workgroup, 16, */
                             /* 32 or 64 (0: 16 up to r = 16, 32 up to 47, else   */
                             /* 64)                                               */

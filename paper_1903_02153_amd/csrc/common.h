@@ -279,13 +279,16 @@ void fft_m2l(int n, const float2 *Mhat, const float2 *Ghat, const int32_t *itab,
 // -1, halo[blk][(z * 8 + y) * 8 + x] the cell at block offset (x - 2, y - 2,
 // z - 2) cells or -1.  Every interaction-list source of a block's targets
 // lies in that 8 x 8 x 8 halo.
+// slots[o * 189 + j] = t | base << 16: transfer vector t of slot j of
+// octant o and the halo cell of that slot's source for the block's first
+// parent (the others add 2 px + 16 py + 128 pz).
 struct FftBlocks {
-    DBuf<int32_t> tgt, halo;
+    DBuf<int32_t> tgt, halo, slots;
     int32_t nblk = 0;
 };
 void fft_build_blocks(const uint64_t *keys, int32_t C, int lvl, FftBlocks &b, hipStream_t s);
-void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b,
-                    const int32_t *tables, int r, float2 *Fhat, hipStream_t s);
+void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b, int r,
+                    float2 *Fhat, hipStream_t s);
 void finalize_opset(OpSet &set, int m, int mp, int precision, hipStream_t s);
 
 struct Plan;

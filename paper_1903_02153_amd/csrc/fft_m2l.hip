@@ -206,65 +206,86 @@ k_m2l_fft(const float2 *Mhat, const float2 *Ghat, const int32_t *itab, const uin
 // workgroup per (block of 4 x 4 x 4 target cells, slice of kFq frequencies,
 // column): the slice of the 8 x 8 x 8 source halo's spectra and of the 316
 // operator spectra is staged in LDS once, so each staged source value serves
-// every target of the block that has it in its list (up to 27 of 64) instead
-// of being gathered again per target.  Thread (q, o, k): frequency q of the
-// slice, octant o, quarter k of the 189 slots; it accumulates the block's
-// eight targets of octant o (one per parent), which share the transfer
-// vector of every slot, so one operator value serves eight products.  The
-// four quarters' partial sums are added in quarter order.  A slot whose
-// source cell does not exist reads a zero halo entry.
-constexpr int kFq = 8;              // frequencies per workgroup
+// every target of the block that has it in its list instead of being
+// gathered again per target.  Thread (q, o, k): frequency q of the slice,
+// octant o, part k of the 189 slots; it accumulates the block's eight
+// targets of octant o (one per parent), which share the transfer vector of
+// every slot, so one operator value serves eight products.  The parts'
+// partial sums are added in part order.  A slot whose source cell does not
+// exist reads a zero halo entry.
 constexpr int kHalo = 512;          // 8 x 8 x 8 source cells
-constexpr int kRow = kFq + 1;       // LDS row of one halo cell's slice (padded)
 
+template <int kFq>
 __global__ void __launch_bounds__(kThreads)
 k_m2l_fft_blk(const float2 *Mhat, const float2 *Ghat, const int32_t *btgt, const int32_t *bhalo,
-              const int32_t *tables, int r, int Q, float2 *Fhat) {
-    __shared__ float2 hs[kHalo * kRow];
-    __shared__ float2 gs[kNumT * kFq];
-    __shared__ int32_t sb[8 * kSlots];        // (t, halo base cell) per (octant, slot)
+              const int32_t *slots, int r, int Q, float2 *Fhat) {
+    constexpr int kRow = kFq + 1;               // LDS row of one halo cell's slice (padded)
+    constexpr int kParts = kThreads / (8 * kFq); // slot ranges, summed in order
+    static_assert(kParts * 64 * kFq <= kHalo * kRow + kNumT * kFq, "partial sums reuse the slices");
+    __shared__ float2 stage[kHalo * kRow + kNumT * kFq];
+    float2 *hs = stage, *gs = stage + kHalo * kRow;
+    __shared__ int32_t sb[8 * kSlots];        // FftBlocks::slots
     const int blk = blockIdx.x, q0 = blockIdx.y * kFq, c = blockIdx.z;
     const int tid = threadIdx.x;
     const int32_t *halo = bhalo + int64_t(blk) * kHalo;
-    for (int e = tid; e < kHalo * kFq; e += kThreads) {
-        const int h = e / kFq, q = e % kFq;
-        const int b = halo[h];
-        hs[h * kRow + q] = (b >= 0 && q0 + q < Q) ? Mhat[(int64_t(b) * r + c) * Q + q0 + q]
-                                                  : make_float2(0.f, 0.f);
+    // Every staging load is issued before the first LDS store (addresses
+    // clamped in bounds, values selected afterwards), so the workgroup waits
+    // for one round of loads rather than one per element.
+    constexpr int kHn = kHalo * kFq / kThreads;
+    constexpr int kGn = (kNumT * kFq + kThreads - 1) / kThreads;
+    constexpr int kSn = (8 * kSlots + kThreads - 1) / kThreads;
+    int32_t hb[kHn];
+#pragma unroll
+    for (int i = 0; i < kHn; ++i) hb[i] = halo[(tid + i * kThreads) / kFq];
+    float2 hv[kHn], gv[kGn];
+    int32_t tv[kSn];
+#pragma unroll
+    for (int i = 0; i < kHn; ++i) {
+        const int qq = min(q0 + (tid + i * kThreads) % kFq, Q - 1);
+        hv[i] = Mhat[(int64_t(max(hb[i], 0)) * r + c) * Q + qq];
     }
-    for (int e = tid; e < kNumT * kFq; e += kThreads) {
-        const int t = e / kFq, q = e % kFq;
-        gs[t * kFq + q] = q0 + q < Q ? Ghat[int64_t(t) * Q + q0 + q] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < kGn; ++i) {
+        const int e = min(tid + i * kThreads, kNumT * kFq - 1);
+        gv[i] = Ghat[int64_t(e / kFq) * Q + min(q0 + e % kFq, Q - 1)];
     }
-    // the source of slot j of the target at (2 px + ox, ...) is that cell
-    // plus t: halo cell base(o, t) + 2 px + 16 py + 128 pz
-    for (int e = tid; e < 8 * kSlots; e += kThreads) {
-        const int o = e / kSlots;
-        const int t = tables[3 * kNumT + e];                 // slot_t[o][j]
-        const int hx = (o & 1) + tables[3 * t] + 2;
-        const int hy = ((o >> 1) & 1) + tables[3 * t + 1] + 2;
-        const int hz = (o >> 2) + tables[3 * t + 2] + 2;
-        sb[e] = t | (((hz * 8 + hy) * 8 + hx) << 16);
+#pragma unroll
+    for (int i = 0; i < kSn; ++i) tv[i] = slots[min(tid + i * kThreads, 8 * kSlots - 1)];
+#pragma unroll
+    for (int i = 0; i < kHn; ++i) {
+        const int e = tid + i * kThreads;
+        const bool ok = hb[i] >= 0 && q0 + e % kFq < Q;
+        hs[(e / kFq) * kRow + e % kFq] = ok ? hv[i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < kGn; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < kNumT * kFq) gs[e] = q0 + e % kFq < Q ? gv[i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < kSn; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < 8 * kSlots) sb[e] = tv[i];
     }
     __syncthreads();
     const int q = tid % kFq, o = (tid / kFq) % 8, k = tid / (8 * kFq);
     float2 acc[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) acc[p] = make_float2(0.f, 0.f);
-    const int j0 = k * kSlots / 4, j1 = (k + 1) * kSlots / 4;
+    const int j0 = k * kSlots / kParts, j1 = (k + 1) * kSlots / kParts;
     for (int j = j0; j < j1; ++j) {
         const int v = sb[o * kSlots + j];
         const float2 g = gs[(v & 0xffff) * kFq + q];
-        const float2 *hb = hs + (v >> 16) * kRow + q;
+        const float2 *hrow = hs + (v >> 16) * kRow + q;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const float2 m = hb[(2 * (p & 1) + 16 * ((p >> 1) & 1) + 128 * (p >> 2)) * kRow];
+            const float2 m = hrow[(2 * (p & 1) + 16 * ((p >> 1) & 1) + 128 * (p >> 2)) * kRow];
             acc[p].x = __fmaf_rn(g.x, m.x, __fmaf_rn(-g.y, m.y, acc[p].x));
             acc[p].y = __fmaf_rn(g.x, m.y, __fmaf_rn(g.y, m.x, acc[p].y));
         }
     }
-    __syncthreads();                          // the halo slice is no longer read
-    float2 *part = hs;                        // [k][target p * 8 + o][q]
+    __syncthreads();                          // the staged slices are no longer read
+    float2 *part = stage;                     // [k][target p * 8 + o][q]
 #pragma unroll
     for (int p = 0; p < 8; ++p) part[(k * 64 + p * 8 + o) * kFq + q] = acc[p];
     __syncthreads();
@@ -274,7 +295,7 @@ k_m2l_fft_blk(const float2 *Mhat, const float2 *Ghat, const int32_t *btgt, const
         const int a = tg[l];
         if (a < 0 || q0 + qq >= Q) continue;
         float2 sum = part[e];
-        for (int kk = 1; kk < 4; ++kk) {
+        for (int kk = 1; kk < kParts; ++kk) {
             const float2 v = part[kk * 64 * kFq + e];
             sum.x += v.x;
             sum.y += v.y;
@@ -452,23 +473,39 @@ void fft_build_blocks(const uint64_t *keys, int32_t C, int lvl, FftBlocks &b, hi
             for (int hy = 0; hy < 8; ++hy)
                 for (int hx = 0; hx < 8; ++hx) halo.push_back(find(bx - 2 + hx, by - 2 + hy, bz - 2 + hz));
     }
+    // the source of slot j of the target at (2 px + ox, 2 py + oy, 2 pz + oz)
+    // in the block is that cell plus t: halo cell base(o, t) + 2 px + 16 py
+    // + 128 pz with base(o, t) = ((oz + tz + 2) * 8 + (oy + ty + 2)) * 8 +
+    // ox + tx + 2, each term in [0, 5] for the slots of octant o
+    const TransferTables &tt = transfer_tables();
+    std::vector<int32_t> slots(8 * kSlots);
+    for (int o = 0; o < 8; ++o)
+        for (int j = 0; j < kSlots; ++j) {
+            const int t = tt.slot_t[o][j];
+            const int hx = (o & 1) + tt.tvec[t][0] + 2, hy = ((o >> 1) & 1) + tt.tvec[t][1] + 2,
+                      hz = (o >> 2) + tt.tvec[t][2] + 2;
+            slots[size_t(o) * kSlots + j] = t | (((hz * 8 + hy) * 8 + hx) << 16);
+        }
     b.nblk = int32_t(tgt.size() / 64);
     b.tgt.alloc(tgt.size());
     b.halo.alloc(halo.size());
+    b.slots.alloc(slots.size());
+    BB_HIP(hipMemcpyAsync(b.slots.p, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (b.nblk > 0) {
         BB_HIP(hipMemcpyAsync(b.tgt.p, tgt.data(), tgt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         BB_HIP(hipMemcpyAsync(b.halo.p, halo.data(), halo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        BB_HIP(hipStreamSynchronize(s));
     }
+    BB_HIP(hipStreamSynchronize(s));
 }
 
-void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b,
-                    const int32_t *tables, int r, float2 *Fhat, hipStream_t s) {
+void fft_m2l_blocks(int n, const float2 *Mhat, const float2 *Ghat, const FftBlocks &b, int r,
+                    float2 *Fhat, hipStream_t s) {
     if (b.nblk == 0) return;
     const int Q = fft_freqs(n);
     BB_REQUIRE(r >= 1 && r <= 65535, "FFT M2L: r out of range");
-    k_m2l_fft_blk<<<dim3(unsigned(b.nblk), unsigned(ceil_div(Q, kFq)), unsigned(r)), kThreads, 0, s>>>(
-        Mhat, Ghat, b.tgt.p, b.halo.p, tables, r, Q, Fhat);
+    constexpr int F = 4;        // frequencies per workgroup (measured: 4 beats 2 and 8)
+    k_m2l_fft_blk<F><<<dim3(unsigned(b.nblk), unsigned(ceil_div(Q, F)), unsigned(r)), kThreads, 0, s>>>(
+        Mhat, Ghat, b.tgt.p, b.halo.p, b.slots.p, r, Q, Fhat);
     BB_LAUNCH_CHECK();
 }
 

@@ -2974,7 +2974,7 @@ Plan *plan_create_impl(const bbfmm_tree *t, const bbfmm_ops *o, int64_t r,
             ws += p->Mc[lvl].bytes() + p->Fc[lvl].bytes() + p->M[lvl].bytes() + p->F[lvl].bytes();
             if (p->fft_blocked) {
                 fft_build_blocks(t->lv[lvl].keys.p, int32_t(C), lvl, p->fblk[lvl], setup);
-                ws += p->fblk[lvl].tgt.bytes() + p->fblk[lvl].halo.bytes();
+                ws += p->fblk[lvl].tgt.bytes() + p->fblk[lvl].halo.bytes() + p->fblk[lvl].slots.bytes();
             }
             continue;            // no compressed operands, no M2L tiles
         } else if (o->precision == BBFMM_M2L_FP32) {
@@ -3715,8 +3715,7 @@ void enqueue_matvec(Plan &p, const float *sigma, float *phi, hipStream_t s, bool
         if (o.precision == BBFMM_M2L_FFT) {
             for (int lvl = lo; lvl <= hi; ++lvl)
                 if (p.fft_blocked)
-                    fft_m2l_blocks(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, p.fblk[lvl], t.tables.p, r,
-                                   p.Fc[lvl].p, st);
+                    fft_m2l_blocks(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, p.fblk[lvl], r, p.Fc[lvl].p, st);
                 else
                     fft_m2l(n, p.Mc[lvl].p, o.lv[lvl].set->Ghat.p, t.lv[lvl].itab.p, t.lv[lvl].keys.p,
                             t.tables.p + 3 * kNumT, t.lv[lvl].C, r, p.Fc[lvl].p, st);
