@@ -469,6 +469,29 @@ def test_separate_target_and_source_sets(r, opts):
     assert_parity(got, ref, TOL, f"separate sets bbfmm_matvec r {r}")
 
 
+@pytest.mark.parametrize("r", [1, 3])
+def test_separate_sets_fft_m2l(r):
+    """eq. (1) with distinct targets and sources on equally spaced nodes with
+    the FFT M2L: cells holding only targets or only sources sit in the
+    blocked form's source halos; both forms against the oracle on the same
+    nodes."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    tgt, _ = synth.random_cloud(7000, 230 + r, kind="clustered")
+    src, sig = synth.random_cloud(10000, 235 + r, r=r, kind="slab")
+    union = np.concatenate([tgt, src])
+    gt = bbfmm.build_tree(torch.from_numpy(tgt).cuda(), bbfmm.K_INV_R, 1.0, cheb_order=4,
+                          fixed_depth=5, sources=torch.from_numpy(src).cuda())
+    go = bbfmm.precompute_operators(gt, 1e-5, bbfmm.M2L_FFT)
+    ot = oracle_tree(union, fixed_depth=5)
+    oo = oops.precompute(ot, 0, 1.0, 4, 0.0, nodes="uniform")
+    ref = ofmm.matvec(ot, oo, union, sig, 0, 1.0, n_targets=7000)
+    for blk in (2, 1):
+        phi = run_plan(gt, go, sig, m2l_block=blk)
+        assert tuple(phi.shape) == (7000, r)
+        assert_parity(phi.cpu().numpy(), ref, TOL, f"separate sets FFT M2L r {r} m2l_block {blk}")
+
+
 def test_separate_sets_equal_copies_match_the_shared_set():
     """Targets and sources as two copies of one cloud (1/r, K = 0 at
     coincident points) give the shared-set product within the FP32 bar."""
