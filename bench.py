@@ -202,6 +202,15 @@ def fft_m2l_section(w, sig, steps: int = 20):
                     "up_ms": round((st["p2m"] + st["m2m"]) / ne, 4),
                     "down_ms": round(st["down"] / ne, 4),
                     "rel_err_vs_direct": rel_l2(got, exact)}
+        if tag == "fft_uniform":
+            # algorithmic work of the pointwise products: a complex
+            # multiply-add (8 flop) per frequency per interaction pair
+            info = tree.info()
+            q = (w.order + 1) * (2 * w.order) ** 2
+            flop = sum(info.pairs[lvl] for lvl in range(2, info.depth)) * q * 8 * w.r
+            tf = flop / (st["m2l"] / ne * 1e-3) / 1e12
+            out[tag]["m2l_tflops"] = round(tf, 2)
+            out[tag]["m2l_frac_of_non_packed_fp32"] = round(tf / PEAK_FP32_SCALAR_TFLOPS, 4)
         plan.close()
         ops.close()
     return out
