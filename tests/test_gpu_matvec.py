@@ -486,6 +486,10 @@ def test_separate_sets_fft_m2l(r):
     ot = oracle_tree(union, fixed_depth=5)
     oo = oops.precompute(ot, 0, 1.0, 4, 0.0, nodes="uniform")
     ref = ofmm.matvec(ot, oo, union, sig, 0, 1.0, n_targets=7000)
+    for blk in (0, 1):                    # the plan reports the form it runs
+        plan = bbfmm.Plan(gt, go, r, m2l_block=blk)
+        assert plan.resolved_options()["m2l_block"] == (1 if blk == 1 else 2)
+        plan.close()
     for blk in (2, 1):
         phi = run_plan(gt, go, sig, m2l_block=blk)
         assert tuple(phi.shape) == (7000, r)
