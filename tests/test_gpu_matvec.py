@@ -160,8 +160,20 @@ def test_full_size_uniform_1m_sampled_rows():
     import torch
     ts = torch.from_numpy(w.sigma).cuda()
     opts, _ = bbfmm.autotune(gt, go, ts, reps=3)
-    got = run_plan(gt, go, ts, **opts).cpu().numpy()[w.sample_rows]
+    eager = run_plan(gt, go, ts, **opts)
+    got = eager.cpu().numpy()[w.sample_rows]
     assert_parity(got, ref, TOL, f"uniform-1M autotuned plan {opts}")
+    # the same plan replayed as one HIP graph per product (the benchmark's
+    # graph_replay figure) gives the eager result bit for bit, every replay
+    plan = bbfmm.Plan(gt, go, 1, **opts)
+    plan.set_graph(True)
+    phi = torch.empty_like(eager)
+    for rep in range(3):
+        phi.fill_(float("nan"))
+        plan.execute(ts, phi)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, eager), f"graph replay {rep}"
+    plan.close()
 
 
 def test_paper_scaling_first_row():
