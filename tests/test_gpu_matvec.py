@@ -570,6 +570,28 @@ def test_fft_m2l_matches_oracle(kid, prm, n, kind, r, depth):
     assert np.abs(a - b).max() <= 5e-6 * np.abs(b).max(), "blocked and per-cell FFT M2L differ"
 
 
+def test_fft_m2l_graph_replay():
+    """FFT plans (both M2L forms) replayed as HIP graphs equal their eager
+    products bit for bit on every replay."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, sig = synth.random_cloud(12000, 245, r=2, kind="clustered")
+    gt = gpu_tree(pts, 0, 1.0, 5, fixed_depth=5)
+    go = bbfmm.precompute_operators(gt, 1e-5, bbfmm.M2L_FFT)
+    ts = torch.from_numpy(sig).cuda()
+    for blk in (2, 1):
+        eager = run_plan(gt, go, ts, m2l_block=blk)
+        plan = bbfmm.Plan(gt, go, 2, m2l_block=blk)
+        plan.set_graph(True)
+        phi = torch.empty_like(eager)
+        for rep in range(3):
+            phi.fill_(float("nan"))
+            plan.execute(ts, phi)
+            torch.cuda.synchronize()
+            assert torch.equal(phi, eager), (blk, rep)
+        plan.close()
+
+
 def test_fft_m2l_polynomial_kernel_exact():
     """On equally spaced nodes the interpolant of a kernel of degree < n per
     coordinate is exact too, so the FFT path equals the direct sum (FP32)."""
