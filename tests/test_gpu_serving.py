@@ -210,3 +210,43 @@ def test_concurrent_clients():
         p.close()
     assert srv.stats()["requests_done"] == len(jobs)
     srv.close()
+
+
+def test_fft_model_served():
+    """A resident model whose operators are the FFT M2L's spectra (equally
+    spaced nodes): served requests of several widths equal a lone plan
+    execution bit for bit (each column's M2L runs in its own workgroups)
+    and meet the FP32 bar against the oracle on the same nodes."""
+    import torch
+    from paper_1903_02153_amd import bbfmm
+    pts, _ = synth.random_cloud(10000, 90, kind="uniform")
+    t = gpu_tree(pts, 0, 1.0, 4, fixed_depth=4)
+    o = bbfmm.precompute_operators(t, 1e-5, bbfmm.M2L_FFT)
+    srv = bbfmm.Server(hbm_budget_bytes=4 << 30, max_inflight=2, r_max=16)
+    mid = srv.add(t, o)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for q in range(12):
+        r = int(rng.choice([1, 2, 4]))
+        sig = torch.from_numpy(rng.standard_normal((10000, r)).astype(np.float32)).cuda()
+        phi = torch.empty_like(sig)
+        reqs.append((sig, phi, srv.submit(mid, sig, phi)))
+    stats = [srv.wait(rid) for _, _, rid in reqs]
+    torch.cuda.synchronize()
+    for (sig, phi, _), st in zip(reqs, stats):
+        path = 1 if st["batch_r"] == 1 else 2
+        plan = bbfmm.Plan(t, o, sig.shape[1], m2l_split=2, p2p_mfma=path)
+        alone = torch.empty_like(sig)
+        plan.execute(sig, alone)
+        torch.cuda.synchronize()
+        plan.close()
+        assert torch.equal(phi, alone), (sig.shape[1], st["batch_r"])
+    ot = oracle_tree(pts, fixed_depth=4)
+    oo = oops.precompute(ot, 0, 1.0, 4, 0.0, nodes="uniform")
+    sig_all = np.concatenate([s.cpu().numpy() for s, _, _ in reqs], axis=1)
+    got = np.concatenate([p.cpu().numpy() for _, p, _ in reqs], axis=1)
+    ref = ofmm.matvec(ot, oo, pts, sig_all, 0, 1.0)
+    err = ofmm.rel_l2_cols(got.astype(np.float64), ref).max()
+    print(f"FFT model: {sig_all.shape[1]} served columns, max rel err vs oracle {err:.2e}")
+    assert err < 1e-5
+    srv.close()
